@@ -1,0 +1,22 @@
+"""FP64 CPU oracle for Schwarz-factorised stochastic determinant-ratio estimation.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
+reference against which the HIP library is checked.  Only the test-suite, the
+smoke check and the benchmark's CPU-baseline leg may import, call, link or run
+anything under ``oracle/``.  The product path never routes through it and
+shares no code with it (no kernels, headers, helpers, tables or constants).
+
+Contents
+  lattice.py    geometry: site indexing, neighbours, time boundary sign,
+                Schwarz blocks, black/white colouring, the projector P
+  dirac.py      chiral gamma matrices, the clover field and the assembled
+                sparse Wilson-clover operator D(m) in the mass normalisation
+  schwarz.py    D_bb, D_ww, D_bw, D_wb, the Schur complement and its
+                P-restricted form and inverse (Sec. 1, Eq. 1)
+  estimator.py  the two-flavour noise estimator of Eq. (3) and W_gl of Eq. (8)
+                with mass interpolation, log-domain combination, variances
+  cref.py       ctypes wrapper of c/ddref.c, a matrix-free FP64 C version of
+                the operator, block solves and estimator for lattices too large
+                for the assembled matrix
+Readings of points the paper leaves open are listed in each module header.
+"""

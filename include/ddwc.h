@@ -1,0 +1,157 @@
+/*
+ * ddwc — Schwarz-factorised stochastic determinant ratios for Wilson-clover
+ * fermions on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The method: the Dirac operator in black/white Schwarz block form
+ * (Finkenrath, Knechtli, Leder, "Application of Domain Decomposition to the
+ * Evaluation of Fermion Determinant Ratios", Lattice 2012; Sec. 1, Eq. 1)
+ *
+ *     D = [[D_bb, D_bw], [D_wb, D_ww]],  det D = det Dhat * det D_ww * det D_bb,
+ *     Dhat = 1 - D_bb^-1 D_bw D_ww^-1 D_wb,   on range(P): Dhat^-1 = 1 - P Dc_bw D_wb
+ *
+ * and the two-flavour reweighting factor W_gl of Eq. (8), estimated with
+ * complex Gaussian noise as prod_i (1/N_hit) sum_j exp(-eta_ij^+ (Mh_i^+ Mh_i - 1) eta_ij),
+ * Mh_i = Dhat(m_i)^-1 Dhat(m_{i-1}), m_i linear in m between m1 and m2 (Sec. 2, 2.1).
+ *
+ * Operator (mass normalisation; Eq. 6 needs D(m1) = D(m2) + (m1 - m2)):
+ *     D(m) = (4 + m) + c_sw (i/4) sum sigma_{mu nu} Fhat_{mu nu} - 1/2 H,   m = 1/(2 kappa) - 4,
+ * H the Wilson hopping term with (1 -+ gamma_mu) projectors, chiral gamma basis,
+ * clover-leaf Fhat = (Q - Q^+)/8, hops across the time boundary times time_bc.
+ *
+ * Conventions at this boundary (all FP64 complex, interleaved re/im):
+ *   site index  x = ((x0*L1 + x1)*L2 + x2)*L3 + x3, x0 = time (extent lat[0])
+ *   spinor      [nrhs][V][4 spin][3 colour]   (16 bytes per complex entry)
+ *   links       [4 mu][V][3][3], U_mu(x) = link from x to x + mu, row-major
+ *   colour of a Schwarz block: (sum_mu x_mu / blk_mu) mod 2, black = 0;
+ *   P = black sites with a nearest neighbour in another block (all 12 components).
+ *   Schur-space vectors are full-lattice spinors that are zero off range(P).
+ *
+ * Ownership: every data pointer is a caller-owned DEVICE buffer (e.g. a torch
+ * tensor's data_ptr) unless its name ends in _host.  The library copies the links
+ * at create time, never frees caller memory, and owns its workspace (allocated on
+ * first use, freed by ddwc_destroy).  `stream` is a hipStream_t (NULL = default).
+ *
+ * Errors: every function returns a ddwc_status.  Argument and geometry errors
+ * (DDWC_EINVAL) are detected on the host before any launch and nothing is written.
+ * ddwc_last_error() gives a thread-local message for the last non-zero status.
+ * Calls that fill a ddwc_stats synchronise their stream; ddwc_dslash_apply is
+ * asynchronous.  Calls on one context must not overlap (they share workspace).
+ */
+#ifndef DDWC_H
+#define DDWC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddwc_ctx ddwc_ctx;
+
+typedef enum {
+    DDWC_OK = 0,
+    DDWC_EINVAL = -1,     /* bad argument or geometry; nothing launched */
+    DDWC_ENOCONV = -2,    /* a solve hit maxit; best iterate written, stats filled */
+    DDWC_EHIP = -3,       /* HIP runtime error */
+    DDWC_ENONFINITE = -4, /* NaN or Inf met in a residual or norm */
+    DDWC_EUNDEF = -5      /* estimate undefined: non-finite step mean or variance */
+} ddwc_status;
+
+typedef enum { DDWC_FP64 = 0, DDWC_MIXED32 = 1 } ddwc_precision;
+typedef enum { DDWC_BLACK = 0, DDWC_WHITE = 1 } ddwc_colour;
+typedef enum { DDWC_OP_FULL = 0, DDWC_OP_SCHUR = 1 } ddwc_operator;
+
+typedef struct {
+    int outer_iters;     /* FP64 defect-correction steps (restarts for DDWC_FP64) */
+    int inner_iters;     /* Krylov iterations summed over restarts (max over RHS / blocks) */
+    double rel_residual; /* final ||b - A x|| / ||b|| in FP64, max over RHS (and blocks) */
+    double seconds;      /* host wall time of the call */
+} ddwc_stats;
+
+/*
+ * Create a context for one gauge field.
+ *   lat[4]    = {T, L1, L2, L3};  blk[4] = Schwarz block extents (Sec. 1).
+ *   Geometry: blk[mu] divides lat[mu], and lat[mu]/blk[mu] is even and >= 2.
+ *   time_bc   = -1 (antiperiodic) or +1 (periodic) in time; space is periodic.
+ *   c_sw      = clover coefficient (0 gives plain Wilson).
+ *   links_dev = canonical links (device, read during the call).
+ * Builds the clover term on the device (once per configuration).
+ */
+int ddwc_create(ddwc_ctx **ctx, const int lat[4], const int blk[4], int time_bc, double c_sw,
+                const void *links_dev, void *stream);
+int ddwc_destroy(ddwc_ctx *ctx);
+
+/*
+ * out = D(m) in for nrhs right-hand sides (the Wilson-clover operator of Sec. 1/2,
+ * m = 1/(2 kappa) - 4).  prec = DDWC_FP64 computes in FP64; DDWC_MIXED32 rounds the
+ * fields to FP32 and computes in FP32 (result returned in FP64).  Asynchronous.
+ */
+int ddwc_dslash_apply(ddwc_ctx *ctx, double kappa, const void *in, void *out, int nrhs, int prec, void *stream);
+
+/*
+ * sol = D_cc(m)^-1 rhs for all Schwarz blocks of one colour (D_bb or D_ww: the
+ * Dirichlet block operators on the diagonal, Sec. 1).  Only sites of that colour
+ * are read; the other colour of sol is set to zero.  One persistent launch: one
+ * workgroup per (block, rhs) iterates to ||r_k|| <= tol ||b_k|| for its own block.
+ * prec = DDWC_MIXED32 runs FP32 BiCGStab inside FP64 defect correction.
+ */
+int ddwc_block_solve(ddwc_ctx *ctx, int colour, double kappa, const void *rhs, void *sol, int nrhs, double tol,
+                     int maxit, int prec, ddwc_stats *stats, void *stream);
+
+/*
+ * Schur complement on range(P) (Sec. 1).  inverse = 0: out = Dhat_P(m) in
+ * = P in - P D_bb^-1 D_bw D_ww^-1 D_wb P in (two block sweeps).  inverse = 1:
+ * out = Dhat_P(m)^-1 in = P in - P [D(m)^-1 (0_b, D_wb P in)]_b (one global solve).
+ * in is projected with P first; out is zero off range(P).
+ */
+int ddwc_schur_apply(ddwc_ctx *ctx, double kappa, int inverse, const void *in, void *out, int nrhs, double tol,
+                     int prec, ddwc_stats *stats, void *stream);
+
+/*
+ * x = D(m)^-1 b, BiCGStab on all nrhs at once (multi-RHS Dslash), until
+ * ||b - D x|| <= tol ||b|| in FP64 for every RHS.  prec = DDWC_MIXED32: FP32 inner
+ * solves with FP64 defect correction (the FP64 residual is recomputed after each).
+ */
+int ddwc_solve(ddwc_ctx *ctx, double kappa, const void *b, void *x, int nrhs, double tol, int maxit, int prec,
+               ddwc_stats *stats, void *stream);
+
+/*
+ * Two-flavour determinant-ratio estimate (Eq. 3 for op = FULL, Eq. 8 for SCHUR).
+ *   eta         = noise, device, [n_interp][n_hit][V][4][3] (complex Gaussian, E|eta_k|^2 = 1;
+ *                 for SCHUR it is projected with P first).
+ *   x_host      = [n_interp][n_hit] exponents x_ij = eta^+ (M^+ M - 1) eta, computed in the
+ *                 cancellation-free form x = 2 Re<eta, y> + ||y||^2 with y = M eta - eta.
+ *   log_w_gl    = sum_i [logsumexp_j(-x_ij) - ln n_hit]   (FP64, log domain).
+ *   step_var_host = [n_interp] relative sample variance var_j(e^-x)/mean_j(e^-x)^2.
+ * Masses m_i = (i/N) m2 + ((N-i)/N) m1 linear in m (Sec. 2.1); all n_hit noise vectors of
+ * a step go through the solvers as one multi-RHS batch.  n_f must be 2.
+ */
+int ddwc_det_ratio_estimate(ddwc_ctx *ctx, double kappa1, double kappa2, int n_interp, int op, int n_f,
+                            const void *eta, int n_hit, double tol, int prec, double *x_host, double *log_w_gl,
+                            double *step_var_host, ddwc_stats *stats, void *stream);
+
+/*
+ * Kernel timing for measurement.  When enabled, launches of the library's kernels
+ * are bracketed with HIP events on their stream; ddwc_profile_read synchronises and
+ * returns, for kernel class `kclass` (DDWC_K_*), the number of launches and their
+ * summed duration in milliseconds since the last reset.
+ */
+typedef enum {
+    DDWC_K_DSLASH64 = 0,  /* full-lattice Dslash, FP64 */
+    DDWC_K_DSLASH32 = 1,  /* full-lattice Dslash, FP32 */
+    DDWC_K_BLOCK = 2,     /* persistent block solver */
+    DDWC_K_BLAS = 3,      /* vector updates and reductions */
+    DDWC_K_OTHER = 4,     /* hops, conversions, projections */
+    DDWC_K_COUNT = 5
+} ddwc_kernel_class;
+int ddwc_profile_enable(ddwc_ctx *ctx, int on);
+int ddwc_profile_read(ddwc_ctx *ctx, int kclass, long long *launches, double *total_ms, double *bytes);
+
+/* Algorithmic HBM bytes of one full-lattice Dslash launch at this geometry (per RHS count). */
+double ddwc_dslash_bytes(const ddwc_ctx *ctx, int nrhs, int prec);
+
+const char *ddwc_last_error(void);
+const char *ddwc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDWC_H */

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libddwc.so (include/ddwc.h).
+
+Argument marshalling only: every step of the computation runs in the library's HIP
+kernels.  Tensors are torch tensors on the GPU (PyTorch provides device memory and
+the stream); they are passed as raw device pointers.  If the library has not been
+built this module raises on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libddwc.so")
+
+OK, EINVAL, ENOCONV, EHIP, ENONFINITE, EUNDEF = 0, -1, -2, -3, -4, -5
+FP64, MIXED32 = 0, 1
+BLACK, WHITE = 0, 1
+OP_FULL, OP_SCHUR = 0, 1
+K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER = range(5)
+_STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
+
+# Every function the header declares, with its ctypes signature.
+_P, _I, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+_PD, _PI, _PLL = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_PS = ctypes.POINTER(Stats)
+SIGNATURES = {
+    "ddwc_create": (_I, [ctypes.POINTER(_P), _P, _P, _I, _D, _P, _P]),
+    "ddwc_destroy": (_I, [_P]),
+    "ddwc_dslash_apply": (_I, [_P, _D, _P, _P, _I, _I, _P]),
+    "ddwc_block_solve": (_I, [_P, _I, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),
+    "ddwc_schur_apply": (_I, [_P, _D, _I, _P, _P, _I, _D, _I, _PS, _P]),
+    "ddwc_solve": (_I, [_P, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),
+    "ddwc_det_ratio_estimate": (_I, [_P, _D, _D, _I, _I, _I, _P, _I, _D, _I, _PD, _PD, _PD, _PS, _P]),
+    "ddwc_profile_enable": (_I, [_P, _I]),
+    "ddwc_profile_read": (_I, [_P, _I, _PLL, _PD, _PD]),
+    "ddwc_dslash_bytes": (_D, [_P, _I, _I]),
+    "ddwc_last_error": (ctypes.c_char_p, []),
+    "ddwc_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libddwc.so; raise loudly if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1211_1214_amd.build.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DDWCError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().ddwc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_STATUS.get(code, code)}: {msg}")
+
+
+def _check(code, where, allow=()):
+    if code != OK and code not in allow:
+        raise DDWCError(code, where)
+    return code
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, V=None, what="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on the GPU")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{what} must be complex128")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _spinors(t, V, what):
+    """Shape check: [V,4,3] or [n,V,4,3] -> number of RHS."""
+    sh = tuple(t.shape)
+    if sh[-3:] != (V, 4, 3):
+        raise ValueError(f"{what} must end in ({V}, 4, 3), got {sh}")
+    return int(np.prod(sh[:-3])) if len(sh) > 3 else 1
+
+
+def mass(kappa: float) -> float:
+    return 1.0 / (2.0 * kappa) - 4.0
+
+
+class Context:
+    """One gauge field on one GPU: links (complex128 [4, V, 3, 3] on the device)."""
+
+    def __init__(self, links, lat, blk, time_bc: int = -1, csw: float = 1.0):
+        import torch
+        self.lat = tuple(int(v) for v in lat)
+        self.blk = tuple(int(v) for v in blk)
+        self.V = int(np.prod(self.lat))
+        if tuple(links.shape) != (4, self.V, 3, 3):
+            raise ValueError(f"links must have shape (4, {self.V}, 3, 3)")
+        self.device = links.device
+        L = lib()
+        h = ctypes.c_void_p()
+        la = (ctypes.c_int * 4)(*self.lat)
+        ba = (ctypes.c_int * 4)(*self.blk)
+        with torch.cuda.device(self.device):
+            _check(L.ddwc_create(ctypes.byref(h), la, ba, int(time_bc), float(csw), _ptr(links, what="links"),
+                                 _stream()), "ddwc_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddwc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty_like(self, t):
+        import torch
+        return torch.empty_like(t)
+
+    def dslash_apply(self, kappa, inp, out=None, prec=FP64):
+        n = _spinors(inp, self.V, "input")
+        out = self._empty_like(inp) if out is None else out
+        _check(lib().ddwc_dslash_apply(self._h, float(kappa), _ptr(inp), _ptr(out), n, int(prec), _stream()),
+               "ddwc_dslash_apply")
+        return out
+
+    def block_solve(self, colour, kappa, rhs, tol=1e-12, maxit=10000, prec=FP64, out=None):
+        n = _spinors(rhs, self.V, "rhs")
+        out = self._empty_like(rhs) if out is None else out
+        st = Stats()
+        _check(lib().ddwc_block_solve(self._h, int(colour), float(kappa), _ptr(rhs), _ptr(out), n, float(tol),
+                                      int(maxit), int(prec), ctypes.byref(st), _stream()), "ddwc_block_solve")
+        return out, st.as_dict()
+
+    def schur_apply(self, kappa, inp, inverse=False, tol=1e-12, prec=FP64, out=None):
+        n = _spinors(inp, self.V, "input")
+        out = self._empty_like(inp) if out is None else out
+        st = Stats()
+        _check(lib().ddwc_schur_apply(self._h, float(kappa), int(bool(inverse)), _ptr(inp), _ptr(out), n,
+                                      float(tol), int(prec), ctypes.byref(st), _stream()), "ddwc_schur_apply")
+        return out, st.as_dict()
+
+    def solve(self, kappa, b, tol=1e-12, maxit=10000, prec=FP64, out=None):
+        n = _spinors(b, self.V, "b")
+        out = self._empty_like(b) if out is None else out
+        st = Stats()
+        _check(lib().ddwc_solve(self._h, float(kappa), _ptr(b), _ptr(out), n, float(tol), int(maxit), int(prec),
+                                ctypes.byref(st), _stream()), "ddwc_solve")
+        return out, st.as_dict()
+
+    def det_ratio_estimate(self, kappa1, kappa2, eta, op=OP_SCHUR, tol=1e-12, prec=FP64, n_f=2):
+        """eta: complex128 [n_interp, n_hit, V, 4, 3] on the device."""
+        sh = tuple(eta.shape)
+        if len(sh) != 5 or sh[2:] != (self.V, 4, 3):
+            raise ValueError(f"eta must have shape (n_interp, n_hit, {self.V}, 4, 3)")
+        n_interp, n_hit = sh[:2]
+        x = np.zeros((n_interp, n_hit))
+        var = np.zeros(n_interp)
+        lw = ctypes.c_double()
+        st = Stats()
+        _check(lib().ddwc_det_ratio_estimate(
+            self._h, float(kappa1), float(kappa2), int(n_interp), int(op), int(n_f), _ptr(eta), int(n_hit),
+            float(tol), int(prec), x.ctypes.data_as(_PD), ctypes.byref(lw), var.ctypes.data_as(_PD),
+            ctypes.byref(st), _stream()), "ddwc_det_ratio_estimate")
+        return {"x": x, "log_w_gl": lw.value, "step_var": var, "stats": st.as_dict()}
+
+    def profile_enable(self, on=True):
+        _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")
+
+    def profile_read(self, kclass):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(lib().ddwc_profile_read(self._h, int(kclass), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+               "ddwc_profile_read")
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+    def dslash_bytes(self, nrhs, prec):
+        return lib().ddwc_dslash_bytes(self._h, int(nrhs), int(prec))

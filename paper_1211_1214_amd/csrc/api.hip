@@ -1,0 +1,700 @@
+// C ABI of the ddwc library: context, workspace, the global Krylov solver with FP64
+// defect correction, the Schur-complement pipeline and the determinant-ratio estimator.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ddwc.h"
+#include "ddwc_internal.h"
+
+using namespace ddwc;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HC(call)                                                                          \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(DDWC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define CK(expr)                 \
+    do {                         \
+        int st_ = (expr);        \
+        if (st_ != DDWC_OK) return st_; \
+    } while (0)
+
+// ------------------------------------------------------------------ profiler
+namespace ddwc {
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+void Profiler::begin(hipStream_t s, int kclass, double b, Pair& p) {
+    if (pending.size() >= 4096) harvest();
+    p.a = get();
+    p.b = get();
+    p.kclass = kclass;
+    p.bytes = b;
+    (void)hipEventRecord(p.a, s);
+}
+void Profiler::end(hipStream_t s, Pair& p) {
+    (void)hipEventRecord(p.b, s);
+    pending.push_back(p);
+}
+void Profiler::harvest() {
+    for (auto& p : pending) {
+        (void)hipEventSynchronize(p.b);
+        float ms_ = 0;
+        if (hipEventElapsedTime(&ms_, p.a, p.b) == hipSuccess) {
+            ms[p.kclass] += ms_;
+            launches[p.kclass] += 1;
+            bytes[p.kclass] += p.bytes;
+        }
+        pool.push_back(p.a);
+        pool.push_back(p.b);
+    }
+    pending.clear();
+}
+void Profiler::reset() {
+    harvest();
+    for (int k = 0; k < 8; ++k) {
+        launches[k] = 0;
+        ms[k] = 0;
+        bytes[k] = 0;
+    }
+}
+Profiler::~Profiler() {
+    harvest();
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+}  // namespace ddwc
+
+// ------------------------------------------------------------------ context
+struct ddwc_ctx {
+    Geom g;
+    int lat[4], blk[4];
+    int device = 0;
+    double csw = 0;
+    cx<double>* U64 = nullptr;
+    cx<float>* U32 = nullptr;
+    double2* K64 = nullptr;
+    float4* K32 = nullptr;
+    Profiler prof;
+    struct Buf {
+        void* p = nullptr;
+        size_t n = 0;
+    };
+    std::map<std::string, Buf> ws;
+    double* host = nullptr;  // pinned scratch for small device-to-host copies
+    size_t host_n = 0;
+};
+
+static int ws_get(ddwc_ctx* C, const std::string& key, size_t bytes, void** out) {
+    auto& b = C->ws[key];
+    if (b.n < bytes) {
+        if (b.p) HC(hipFree(b.p));
+        b.p = nullptr;
+        b.n = 0;
+        HC(hipMalloc(&b.p, bytes));
+        b.n = bytes;
+    }
+    *out = b.p;
+    return DDWC_OK;
+}
+
+template <class T>
+static int ws_t(ddwc_ctx* C, const std::string& key, size_t count, T** out) {
+    void* p;
+    CK(ws_get(C, key, count * sizeof(T), &p));
+    *out = (T*)p;
+    return DDWC_OK;
+}
+
+static int host_buf(ddwc_ctx* C, size_t n, double** out) {
+    if (C->host_n < n) {
+        if (C->host) HC(hipHostFree(C->host));
+        C->host = nullptr;
+        HC(hipHostMalloc((void**)&C->host, n * sizeof(double)));
+        C->host_n = n;
+    }
+    *out = C->host;
+    return DDWC_OK;
+}
+
+static double mass_of(double kappa) { return 1.0 / (2.0 * kappa) - 4.0; }
+
+static int check_ctx(const ddwc_ctx* C) {
+    if (!C) return fail(DDWC_EINVAL, "null context");
+    return DDWC_OK;
+}
+
+static int check_common(const ddwc_ctx* C, double kappa, int nrhs, int prec) {
+    CK(check_ctx(C));
+    if (!(kappa > 0) || !isfinite(kappa)) return fail(DDWC_EINVAL, "kappa must be positive and finite");
+    if (nrhs < 1 || nrhs > 65535) return fail(DDWC_EINVAL, "nrhs must be in [1, 65535]");
+    if (prec != DDWC_FP64 && prec != DDWC_MIXED32) return fail(DDWC_EINVAL, "unknown precision");
+    size_t words = (size_t)nrhs * 12 * C->g.V;
+    if (words > (size_t)1 << 40) return fail(DDWC_EINVAL, "problem too large");
+    return DDWC_OK;
+}
+
+static size_t vec_words(const ddwc_ctx* C, int nrhs, bool fp64) {
+    return (size_t)nrhs * (fp64 ? 12 : 6) * C->g.V;  // 16-byte words
+}
+
+double ddwc_dslash_bytes(const ddwc_ctx* C, int nrhs, int prec) {
+    if (!C) return 0;
+    const double r = prec == DDWC_FP64 ? 8.0 : 4.0;
+    // per site: spinor in + out (24 reals each per RHS), 4 links (36 reals), clover (72 reals)
+    return (double)C->g.V * ((double)nrhs * 48.0 * r + 108.0 * r);
+}
+
+extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], int time_bc, double c_sw,
+                           const void* links_dev, void* stream) {
+    if (!out || !lat || !blk || !links_dev) return fail(DDWC_EINVAL, "null argument");
+    *out = nullptr;
+    if (time_bc != -1 && time_bc != 1) return fail(DDWC_EINVAL, "time_bc must be -1 or +1");
+    if (!isfinite(c_sw)) return fail(DDWC_EINVAL, "c_sw must be finite");
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (lat[mu] < 1 || blk[mu] < 1 || lat[mu] % blk[mu] != 0)
+            return fail(DDWC_EINVAL, "block extent must divide the lattice extent in every direction");
+        int nb = lat[mu] / blk[mu];
+        if (nb < 2 || nb % 2 != 0)
+            return fail(DDWC_EINVAL, "the number of blocks in every direction must be even and >= 2");
+        V *= lat[mu];
+    }
+    if (V * 12 * 16 > ((long long)1 << 40) || V > (1 << 30)) return fail(DDWC_EINVAL, "lattice too large");
+    ddwc_ctx* C = new ddwc_ctx();
+    Geom& g = C->g;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = C->lat[mu] = lat[mu];
+        g.b[mu] = C->blk[mu] = blk[mu];
+        g.nb[mu] = lat[mu] / blk[mu];
+    }
+    g.lstr[3] = 1;
+    g.lstr[2] = g.b[3];
+    g.lstr[1] = g.b[3] * g.b[2];
+    g.lstr[0] = g.b[3] * g.b[2] * g.b[1];
+    g.V = (int)V;
+    g.Vb = g.b[0] * g.b[1] * g.b[2] * g.b[3];
+    g.NB = g.V / g.Vb;
+    g.NBc = g.NB / 2;
+    g.nb3h = g.nb[3] / 2;
+    g.tbc = time_bc;
+    C->csw = c_sw;
+    hipError_t e0 = hipGetDevice(&C->device);
+    size_t n = (size_t)4 * 9 * g.V;
+    if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
+        hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
+        hipMalloc(&C->K64, (size_t)36 * g.V * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&C->K32, (size_t)18 * g.V * sizeof(float4)) != hipSuccess) {
+        ddwc_destroy(C);
+        return fail(DDWC_EHIP, "device allocation of links/clover failed");
+    }
+    Exec ex{(hipStream_t)stream, &C->prof};
+    launch_links_import(ex, g, links_dev, C->U64, C->U32);
+    launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        ddwc_destroy(C);
+        return fail(DDWC_EHIP, std::string("setup kernels failed: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    *out = C;
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_destroy(ddwc_ctx* C) {
+    if (!C) return DDWC_OK;
+    (void)hipDeviceSynchronize();
+    C->prof.harvest();
+    if (C->U64) (void)hipFree(C->U64);
+    if (C->U32) (void)hipFree(C->U32);
+    if (C->K64) (void)hipFree(C->K64);
+    if (C->K32) (void)hipFree(C->K32);
+    for (auto& kv : C->ws)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    if (C->host) (void)hipHostFree(C->host);
+    delete C;
+    return DDWC_OK;
+}
+
+// ------------------------------------------------------------------ global solver
+// FP64 defect correction around BiCGStab in precision R on all RHS at once.
+// b64, x64: internal FP64 multi-vectors.  Scalars stay on the device; the host polls
+// the per-RHS state every `poll` iterations.
+struct SolveInfo {
+    int outer = 0, inner = 0;
+    double relres = 0;
+};
+
+template <class R>
+static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
+                        int maxit, SolveInfo* info) {
+    typedef typename Traits<R>::word W;
+    const Geom& g = C->g;
+    const bool fp64 = sizeof(R) == 8;
+    const size_t nw = vec_words(C, nrhs, fp64);
+    const int nt = tiles_of(g.V);
+    const cx<R>* U = fp64 ? (const cx<R>*)C->U64 : (const cx<R>*)C->U32;
+    const W* K = fp64 ? (const W*)C->K64 : (const W*)C->K32;
+    const int kcl = fp64 ? DDWC_K_DSLASH64 : DDWC_K_DSLASH32;
+    const double dbytes = ddwc_dslash_bytes(C, nrhs, fp64 ? DDWC_FP64 : DDWC_MIXED32);
+    const double rb = (double)nrhs * g.V * 24.0 * sizeof(R);  // one vector of nrhs spinors
+    const double mass4 = 4.0 + mass;
+    W *r, *rh, *p, *v, *s, *t, *xR;
+    double2* r64;
+    double *part, *sums, *scale, *thr;
+    BiState* st;
+    const std::string pre = fp64 ? "g64_" : "g32_";
+    CK(ws_t(C, pre + "r", nw, &r));
+    CK(ws_t(C, pre + "rh", nw, &rh));
+    CK(ws_t(C, pre + "p", nw, &p));
+    CK(ws_t(C, pre + "v", nw, &v));
+    CK(ws_t(C, pre + "s", nw, &s));
+    CK(ws_t(C, pre + "t", nw, &t));
+    CK(ws_t(C, pre + "x", nw, &xR));
+    CK(ws_t(C, "g_r64", vec_words(C, nrhs, true), &r64));
+    CK(ws_t(C, "g_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(C, "g_sums", (size_t)nrhs * NPART, &sums));
+    CK(ws_t(C, "g_scale", (size_t)nrhs, &scale));
+    CK(ws_t(C, "g_thr", (size_t)nrhs, &thr));
+    CK(ws_t(C, "g_state", (size_t)nrhs, &st));
+    double* hb;
+    const size_t nst = (sizeof(BiState) + 7) / 8;
+    CK(host_buf(C, (size_t)nrhs * (NPART + 2 + nst) + 16, &hb));
+    double* h_sums = hb;
+    double* h_scale = hb + (size_t)nrhs * NPART;
+    double* h_thr = h_scale + nrhs;
+    BiState* h_st = (BiState*)(h_thr + nrhs);
+    hipStream_t sm = ex.stream;
+
+    // ||b||^2
+    launch_dots(ex, g, b64, b64, part, nrhs);
+    launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+    HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
+    HC(hipStreamSynchronize(sm));
+    std::vector<double> bb(nrhs), rr(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+        bb[k] = h_sums[k * NPART + 2];
+        rr[k] = bb[k];
+        if (!isfinite(bb[k])) return fail(DDWC_ENONFINITE, "non-finite right-hand side");
+    }
+    HC(hipMemsetAsync(x64, 0, sizeof(double2) * vec_words(C, nrhs, true), sm));
+    HC(hipMemcpyAsync(r64, b64, sizeof(double2) * vec_words(C, nrhs, true), hipMemcpyDeviceToDevice, sm));
+    const double floor_eps = fp64 ? 0.0 : 2e-6;
+    const int poll = 2;
+    int total = 0, nout = 0;
+    bool converged = false;
+    while (true) {
+        bool all = true;
+        for (int k = 0; k < nrhs; ++k)
+            if (bb[k] > 0 && rr[k] > tol * tol * bb[k]) all = false;
+        if (all) {
+            converged = true;
+            break;
+        }
+        if (total >= maxit || nout >= 100) break;
+        ++nout;
+        for (int k = 0; k < nrhs; ++k) {
+            bool done = !(bb[k] > 0 && rr[k] > tol * tol * bb[k]);
+            h_scale[k] = done ? 0.0 : 1.0 / sqrt(rr[k]);
+            double eps = done ? 0.0 : 0.5 * tol * sqrt(bb[k] / rr[k]);
+            if (eps < floor_eps) eps = floor_eps;
+            h_thr[k] = done ? 2.0 : eps * eps;
+        }
+        HC(hipMemcpyAsync(scale, h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
+        HC(hipMemcpyAsync(thr, h_thr, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
+        launch_bicg_init<R>(ex, g, r64, scale, r, rh, p, xR, part, nrhs);
+        launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_INIT, thr);
+        int it = 0;
+        while (total < maxit) {
+            for (int k = 0; k < poll && total < maxit; ++k, ++it, ++total) {
+                launch_dslash_dot<R>(ex, g, U, K, mass4, p, v, rh, part, nrhs, kcl, dbytes + rb);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_ALPHA, nullptr);
+                launch_bicg_s<R>(ex, g, st, r, v, s, nrhs);
+                launch_dslash_dot2<R>(ex, g, U, K, mass4, s, t, part, nrhs, kcl, dbytes);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_OMEGA, nullptr);
+                launch_bicg_xr<R>(ex, g, st, xR, p, s, t, rh, r, part, nrhs);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_BETA, nullptr);
+                launch_bicg_p<R>(ex, g, st, r, v, p, nrhs);
+            }
+            HC(hipGetLastError());
+            HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
+            HC(hipStreamSynchronize(sm));
+            bool any = false;
+            for (int k = 0; k < nrhs; ++k) any = any || h_st[k].active;
+            if (!any) break;
+        }
+        launch_accumulate<R>(ex, g, xR, scale, x64, nrhs);
+        launch_residual<double>(ex, g, C->U64, C->K64, mass4, x64, b64, r64, part, nrhs, DDWC_K_DSLASH64,
+                                ddwc_dslash_bytes(C, nrhs, DDWC_FP64) + 2 * (double)nrhs * g.V * 192.0);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
+        HC(hipStreamSynchronize(sm));
+        for (int k = 0; k < nrhs; ++k) {
+            rr[k] = h_sums[k * NPART];
+            if (!isfinite(rr[k])) return fail(DDWC_ENONFINITE, "non-finite residual in the global solve");
+        }
+    }
+    double worst = 0;
+    for (int k = 0; k < nrhs; ++k)
+        if (bb[k] > 0) worst = fmax(worst, sqrt(rr[k] / bb[k]));
+    if (info) {
+        info->outer += nout;
+        info->inner += total;
+        info->relres = fmax(info->relres, worst);
+    }
+    if (!converged) return fail(DDWC_ENOCONV, "global solve did not reach its tolerance within maxit");
+    return DDWC_OK;
+}
+
+static int solve_internal(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs,
+                          double tol, int maxit, int prec, SolveInfo* info) {
+    if (prec == DDWC_FP64) return global_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
+    return global_solve<float>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
+}
+
+// ------------------------------------------------------------------ block solves
+struct BlockInfo {
+    int outer = 0, inner = 0;
+    double relres = 0;
+    long long block_iters = 0;  // summed over blocks and RHS
+};
+
+static int block_internal(ddwc_ctx* C, Exec& ex, int colour, double mass, const double2* b64, double2* x64,
+                          int nrhs, double tol, int maxit, int prec, BlockInfo* info) {
+    const Geom& g = C->g;
+    const bool fp64 = prec == DDWC_FP64;
+    const size_t nw = vec_words(C, nrhs, fp64);
+    const size_t esz = 16;
+    BlockSolveArgs a;
+    a.b = b64;
+    a.x = x64;
+    CK(ws_t(C, "b_r64", vec_words(C, nrhs, true), &a.r64));
+    const char* names[6] = {"b_r", "b_rh", "b_p", "b_v", "b_t", "b_e"};
+    for (int k = 0; k < 6; ++k) CK(ws_get(C, std::string(names[k]) + (fp64 ? "64" : "32"), nw * esz, &a.w[k]));
+    a.colour = colour;
+    a.nrhs = nrhs;
+    a.mass4 = 4.0 + mass;
+    a.tol = tol;
+    a.maxit = maxit;
+    const size_t nb = (size_t)nrhs * g.NBc;
+    CK(ws_t(C, "b_iters", nb, &a.iters));
+    CK(ws_t(C, "b_outer", nb, &a.outer));
+    CK(ws_t(C, "b_relres", nb, &a.relres));
+    // the other colour of x is zero
+    const size_t half = (size_t)g.V / 2;
+    for (int k = 0; k < nrhs; ++k)
+        for (int c = 0; c < 12; ++c)
+            HC(hipMemsetAsync(x64 + ((size_t)k * 12 + c) * g.V + (colour == 0 ? half : 0), 0, half * sizeof(double2),
+                              ex.stream));
+    if (fp64)
+        launch_block_solve64(ex, g, C->U64, C->K64, a);
+    else
+        launch_block_solve32(ex, g, C->U64, C->K64, C->U32, C->K32, a);
+    HC(hipGetLastError());
+    std::vector<int> it(nb), ou(nb);
+    std::vector<double> rr(nb);
+    HC(hipMemcpyAsync(it.data(), a.iters, nb * sizeof(int), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipMemcpyAsync(ou.data(), a.outer, nb * sizeof(int), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipMemcpyAsync(rr.data(), a.relres, nb * sizeof(double), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipStreamSynchronize(ex.stream));
+    int imax = 0, omax = 0;
+    double worst = 0;
+    long long sum = 0;
+    bool finite = true;
+    for (size_t k = 0; k < nb; ++k) {
+        imax = it[k] > imax ? it[k] : imax;
+        omax = ou[k] > omax ? ou[k] : omax;
+        if (!isfinite(rr[k])) finite = false;
+        worst = fmax(worst, rr[k]);
+        sum += it[k];
+    }
+    if (info) {
+        info->outer += omax;
+        info->inner += imax;
+        info->relres = fmax(info->relres, worst);
+        info->block_iters += sum;
+    }
+    if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
+    if (worst > tol) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");
+    return DDWC_OK;
+}
+
+// ------------------------------------------------------------------ public entry points
+static void fill_stats(ddwc_stats* s, int outer, int inner, double rel, std::chrono::steady_clock::time_point t0) {
+    if (!s) return;
+    s->outer_iters = outer;
+    s->inner_iters = inner;
+    s->rel_residual = rel;
+    s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void* out, int nrhs, int prec,
+                                 void* stream) {
+    CK(check_common(C, kappa, nrhs, prec));
+    if (!in || !out) return fail(DDWC_EINVAL, "null vector");
+    Exec ex{(hipStream_t)stream, &C->prof};
+    const Geom& g = C->g;
+    const double mass4 = 4.0 + mass_of(kappa);
+    if (prec == DDWC_FP64) {
+        double2 *a, *b;
+        CK(ws_t(C, "d_in64", vec_words(C, nrhs, true), &a));
+        CK(ws_t(C, "d_out64", vec_words(C, nrhs, true), &b));
+        launch_import<double>(ex, g, in, a, nrhs, MASK_ALL);
+        launch_dslash<double>(ex, g, C->U64, C->K64, mass4, a, b, nrhs, DDWC_K_DSLASH64,
+                              ddwc_dslash_bytes(C, nrhs, DDWC_FP64));
+        launch_export<double>(ex, g, b, out, nrhs, MASK_ALL);
+    } else {
+        float4 *a, *b;
+        CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));
+        CK(ws_t(C, "d_out32", vec_words(C, nrhs, false), &b));
+        launch_import<float>(ex, g, in, a, nrhs, MASK_ALL);
+        launch_dslash<float>(ex, g, C->U32, C->K32, mass4, a, b, nrhs, DDWC_K_DSLASH32,
+                             ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
+        launch_export<float>(ex, g, b, out, nrhs, MASK_ALL);
+    }
+    HC(hipGetLastError());
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_block_solve(ddwc_ctx* C, int colour, double kappa, const void* rhs, void* sol, int nrhs,
+                                double tol, int maxit, int prec, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa, nrhs, prec));
+    if (!rhs || !sol) return fail(DDWC_EINVAL, "null vector");
+    if (colour != DDWC_BLACK && colour != DDWC_WHITE) return fail(DDWC_EINVAL, "colour must be 0 or 1");
+    if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
+    Exec ex{(hipStream_t)stream, &C->prof};
+    double2 *b, *x;
+    CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &b));
+    CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &x));
+    launch_import<double>(ex, C->g, rhs, b, nrhs, colour == 0 ? MASK_BLACK : MASK_WHITE);
+    BlockInfo bi;
+    int st = block_internal(C, ex, colour, mass_of(kappa), b, x, nrhs, tol, maxit, prec, &bi);
+    if (st == DDWC_OK || st == DDWC_ENOCONV) {
+        launch_export<double>(ex, C->g, x, sol, nrhs, colour == 0 ? MASK_BLACK : MASK_WHITE);
+        HC(hipStreamSynchronize(ex.stream));
+    }
+    fill_stats(stats, bi.outer, bi.inner, bi.relres, t0);
+    return st;
+}
+
+extern "C" int ddwc_solve(ddwc_ctx* C, double kappa, const void* b, void* x, int nrhs, double tol, int maxit,
+                          int prec, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa, nrhs, prec));
+    if (!b || !x) return fail(DDWC_EINVAL, "null vector");
+    if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
+    Exec ex{(hipStream_t)stream, &C->prof};
+    double2 *bi, *xi;
+    CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &bi));
+    CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &xi));
+    launch_import<double>(ex, C->g, b, bi, nrhs, MASK_ALL);
+    SolveInfo si;
+    int st = solve_internal(C, ex, mass_of(kappa), bi, xi, nrhs, tol, maxit, prec, &si);
+    if (st == DDWC_OK || st == DDWC_ENOCONV) {
+        launch_export<double>(ex, C->g, xi, x, nrhs, MASK_ALL);
+        HC(hipStreamSynchronize(ex.stream));
+    }
+    fill_stats(stats, si.outer, si.inner, si.relres, t0);
+    return st;
+}
+
+// Dhat_P(m) e for e already projected (internal FP64): out = e - P D_bb^-1 D_bw D_ww^-1 D_wb e.
+static int schur_hat(ddwc_ctx* C, Exec& ex, double mass, const double2* e, double2* out, int nrhs, double tol,
+                     int prec, BlockInfo* bi) {
+    const size_t nw = vec_words(C, nrhs, true);
+    double2 *a, *w;
+    CK(ws_t(C, "s_a", nw, &a));
+    CK(ws_t(C, "s_w", nw, &w));
+    launch_hop<double>(ex, C->g, C->U64, e, a, nrhs, 1);
+    CK(block_internal(C, ex, 1, mass, a, w, nrhs, tol, 5000, prec, bi));
+    launch_hop<double>(ex, C->g, C->U64, w, a, nrhs, 0);
+    CK(block_internal(C, ex, 0, mass, a, w, nrhs, tol, 5000, prec, bi));
+    launch_axpby(ex, C->g, 1.0, e, -1.0, w, out, nrhs, MASK_P);
+    return DDWC_OK;
+}
+
+// Dhat_P(m)^-1 f for f already projected: out = f - P [D^-1 (0_b, D_wb f)]_b.
+static int schur_hat_inverse(ddwc_ctx* C, Exec& ex, double mass, const double2* f, double2* out, int nrhs,
+                             double tol, int prec, SolveInfo* si) {
+    const size_t nw = vec_words(C, nrhs, true);
+    double2 *a, *chi;
+    CK(ws_t(C, "s_src", nw, &a));
+    CK(ws_t(C, "s_chi", nw, &chi));
+    launch_hop<double>(ex, C->g, C->U64, f, a, nrhs, 1);
+    CK(solve_internal(C, ex, mass, a, chi, nrhs, tol, 5000, prec, si));
+    launch_axpby(ex, C->g, 1.0, f, -1.0, chi, out, nrhs, MASK_P);
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_schur_apply(ddwc_ctx* C, double kappa, int inverse, const void* in, void* out, int nrhs,
+                                double tol, int prec, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa, nrhs, prec));
+    if (!in || !out) return fail(DDWC_EINVAL, "null vector");
+    if (inverse != 0 && inverse != 1) return fail(DDWC_EINVAL, "inverse must be 0 or 1");
+    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
+    Exec ex{(hipStream_t)stream, &C->prof};
+    double2 *e, *o;
+    CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &e));
+    CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &o));
+    launch_import<double>(ex, C->g, in, e, nrhs, MASK_P);
+    int st;
+    int outer = 0, inner = 0;
+    double rel = 0;
+    if (inverse == 0) {
+        BlockInfo bi;
+        st = schur_hat(C, ex, mass_of(kappa), e, o, nrhs, tol, prec, &bi);
+        outer = bi.outer, inner = bi.inner, rel = bi.relres;
+    } else {
+        SolveInfo si;
+        st = schur_hat_inverse(C, ex, mass_of(kappa), e, o, nrhs, tol, prec, &si);
+        outer = si.outer, inner = si.inner, rel = si.relres;
+    }
+    if (st == DDWC_OK) {
+        launch_export<double>(ex, C->g, o, out, nrhs, MASK_ALL);
+        HC(hipStreamSynchronize(ex.stream));
+    }
+    fill_stats(stats, outer, inner, rel, t0);
+    return st;
+}
+
+extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2, int n_interp, int op, int n_f,
+                                       const void* eta, int n_hit, double tol, int prec, double* x_host,
+                                       double* log_w_gl, double* step_var_host, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa1, n_hit, prec));
+    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
+    if (n_f != 2) return fail(DDWC_EINVAL, "only the two-flavour estimator (n_f = 2) is provided");
+    if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
+    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
+    Exec ex{(hipStream_t)stream, &C->prof};
+    const Geom& g = C->g;
+    const int nrhs = n_hit;
+    const size_t nw = vec_words(C, nrhs, true);
+    const int nt = tiles_of(g.V);
+    const double m1 = mass_of(kappa1), m2 = mass_of(kappa2);
+    double2 *E, *A, *W1, *W12, *A1, *G, *Z;
+    double *part, *sums, *hb;
+    CK(ws_t(C, "e_E", nw, &E));
+    CK(ws_t(C, "e_A", nw, &A));
+    CK(ws_t(C, "e_W1", nw, &W1));
+    CK(ws_t(C, "e_W12", nw, &W12));
+    CK(ws_t(C, "e_A1", nw, &A1));
+    CK(ws_t(C, "e_G", nw, &G));
+    CK(ws_t(C, "e_Z", nw, &Z));
+    CK(ws_t(C, "e_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(C, "e_sums", (size_t)nrhs * NPART, &sums));
+    SolveInfo si;
+    BlockInfo bi;
+    std::vector<double> hs((size_t)nrhs * NPART);
+    for (int i = 0; i < n_interp; ++i) {
+        // m_i = (i/N) m2 + ((N - i)/N) m1
+        const double mp = ((double)i / n_interp) * m2 + ((double)(n_interp - i) / n_interp) * m1;
+        const double mn = ((double)(i + 1) / n_interp) * m2 + ((double)(n_interp - i - 1) / n_interp) * m1;
+        const double dm = mp - mn;
+        const char* eta_i = (const char*)eta + (size_t)i * nrhs * g.V * 12 * 16;
+        double ca, cb;  // x = ca * Re<e, y> + cb * ||y||^2
+        if (op == DDWC_OP_FULL) {
+            // M eta - eta = dm D(mn)^-1 eta
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_ALL);
+            CK(solve_internal(C, ex, mn, E, Z, nrhs, tol, 5000, prec, &si));
+            ca = 2 * dm;
+            cb = dm * dm;
+        } else {
+            // Mh eta - eta = Dhat(mn)^-1 g, g = dm P [D_bb(mp)^-1 D_bb(mn)^-1 D_bw D_ww(mp)^-1
+            //                + D_bb(mn)^-1 D_bw D_ww(mp)^-1 D_ww(mn)^-1] D_wb eta
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_P);
+            launch_hop<double>(ex, g, C->U64, E, A, nrhs, 1);
+            CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, 5000, prec, &bi));
+            CK(block_internal(C, ex, 1, mn, W1, W12, nrhs, tol, 5000, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, W1, A, nrhs, 0);
+            CK(block_internal(C, ex, 0, mp, A, A1, nrhs, tol, 5000, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, W12, A, nrhs, 0);
+            launch_axpby(ex, g, 1.0, A1, 1.0, A, A, nrhs, MASK_BLACK);
+            CK(block_internal(C, ex, 0, mn, A, G, nrhs, tol, 5000, prec, &bi));
+            launch_axpby(ex, g, dm, G, 0.0, nullptr, G, nrhs, MASK_P);
+            CK(schur_hat_inverse(C, ex, mn, G, Z, nrhs, tol, prec, &si));
+            ca = 2.0;
+            cb = 1.0;
+        }
+        launch_dots(ex, g, E, Z, part, nrhs);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        HC(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, ex.stream));
+        HC(hipStreamSynchronize(ex.stream));
+        for (int j = 0; j < nrhs; ++j) {
+            double x = ca * hs[j * NPART] + cb * hs[j * NPART + 2];
+            if (!isfinite(x)) return fail(DDWC_ENONFINITE, "non-finite exponent");
+            x_host[(size_t)i * nrhs + j] = x;
+        }
+    }
+    // log W_gl = sum_i [max_j a_ij + ln sum_j exp(a_ij - max) - ln n_hit], a = -x; step variances
+    double lw = 0;
+    bool undefined = false;
+    for (int i = 0; i < n_interp; ++i) {
+        const double* xi = x_host + (size_t)i * nrhs;
+        double amax = -xi[0];
+        for (int j = 1; j < nrhs; ++j) amax = fmax(amax, -xi[j]);
+        double sw = 0, sw2 = 0;
+        for (int j = 0; j < nrhs; ++j) {
+            double w = exp(-xi[j] - amax);
+            sw += w;
+        }
+        const double mean = sw / nrhs;
+        for (int j = 0; j < nrhs; ++j) {
+            double d = exp(-xi[j] - amax) - mean;
+            sw2 += d * d;
+        }
+        lw += amax + log(sw) - log((double)nrhs);
+        double var = nrhs > 1 ? (sw2 / (nrhs - 1)) / (mean * mean) : 0.0;
+        if (!isfinite(var)) undefined = true;
+        if (step_var_host) step_var_host[i] = var;
+    }
+    *log_w_gl = lw;
+    fill_stats(stats, si.outer, si.inner, si.relres, t0);
+    if (!isfinite(lw) || undefined) return fail(DDWC_EUNDEF, "estimate undefined (non-finite step mean or variance)");
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_profile_enable(ddwc_ctx* C, int on) {
+    CK(check_ctx(C));
+    C->prof.harvest();
+    C->prof.on = on != 0;
+    if (on) C->prof.reset();
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_profile_read(ddwc_ctx* C, int kclass, long long* launches, double* total_ms, double* bytes) {
+    CK(check_ctx(C));
+    if (kclass < 0 || kclass >= DDWC_K_COUNT) return fail(DDWC_EINVAL, "unknown kernel class");
+    C->prof.harvest();
+    if (launches) *launches = C->prof.launches[kclass];
+    if (total_ms) *total_ms = C->prof.ms[kclass];
+    if (bytes) *bytes = C->prof.bytes[kclass];
+    return DDWC_OK;
+}
+
+extern "C" const char* ddwc_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* ddwc_version(void) { return "ddwc 0.1 (gfx950)"; }

@@ -1,0 +1,436 @@
+// Device-side building blocks of the ddwc library (gfx950).
+//
+// Internal site order is block-major: site s = ((c * NBc + rank) * Vb) + local,
+// with c the Schwarz colour (black = 0), rank the block's number among the blocks of
+// that colour and local the lexicographic site inside the block.  Black sites are
+// the first half of every field, and each block's sites are contiguous, so a
+// workgroup that owns one block reads it with unit stride.
+//
+// Fields are SoA, site fastest, in 16-byte words:
+//   spinor  [nrhs][NCW][V] words   FP64: one complex per double2 (NCW = 12)
+//                                  FP32: two complex per float4  (NCW = 6)
+//   links   [4][9][V] complex      (row-major 3x3, U_mu(x) from x to x + mu)
+//   clover  [NKW][V] words of the 72 reals of two Hermitian 6x6 blocks
+//           (chiral spin blocks {0,1} and {2,3}); FP64 NKW = 36, FP32 NKW = 18.
+//           Reals 0..5: diagonal of block 0, 6..11: diagonal of block 1,
+//           12..41: upper off-diagonal of block 0 as (re, im) in row order
+//           (0,1),(0,2),...,(0,5),(1,2),...,(4,5), 42..71: same for block 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddwc {
+
+template <class R>
+struct cx {
+    R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> mk(R a, R b) {
+    cx<R> z;
+    z.re = a;
+    z.im = b;
+    return z;
+}
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a) { return mk(-a.re, -a.im); }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return mk(s * a.re, s * a.im); }
+template <class R>
+__device__ __forceinline__ cx<R> conj_mul(cx<R> a, cx<R> b) {  // conj(a) * b
+    return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class R>
+__device__ __forceinline__ cx<R> times_i(cx<R> a) { return mk(-a.im, a.re); }
+template <class R>
+__device__ __forceinline__ cx<R> times_mi(cx<R> a) { return mk(a.im, -a.re); }
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];      // T, L1, L2, L3
+    int b[4];      // block extents
+    int nb[4];     // blocks per direction
+    int lstr[4];   // stride of a unit step inside a block (local index)
+    int V, Vb, NB, NBc, nb3h;
+    int tbc;       // time boundary factor (-1 antiperiodic, +1 periodic)
+};
+
+struct Site {
+    int l[4];  // coordinates inside the block
+    int n[4];  // block coordinates
+    int c;     // colour
+};
+
+__device__ __forceinline__ Site decode(const Geom& g, int s) {
+    Site S;
+    int loc = s % g.Vb;
+    int B = s / g.Vb;
+    S.l[3] = loc % g.b[3];
+    loc /= g.b[3];
+    S.l[2] = loc % g.b[2];
+    loc /= g.b[2];
+    S.l[1] = loc % g.b[1];
+    S.l[0] = loc / g.b[1];
+    S.c = B / g.NBc;
+    int r = B % g.NBc;
+    int h = r % g.nb3h;
+    r /= g.nb3h;
+    S.n[2] = r % g.nb[2];
+    r /= g.nb[2];
+    S.n[1] = r % g.nb[1];
+    S.n[0] = r / g.nb[1];
+    S.n[3] = 2 * h + ((S.c + S.n[0] + S.n[1] + S.n[2]) & 1);
+    return S;
+}
+
+__device__ __forceinline__ int block_base(const Geom& g, const int n[4]) {
+    int c = (n[0] + n[1] + n[2] + n[3]) & 1;
+    int r = ((n[0] * g.nb[1] + n[1]) * g.nb[2] + n[2]) * g.nb3h + (n[3] >> 1);
+    return (c * g.NBc + r) * g.Vb;
+}
+
+__device__ __forceinline__ int local_index(const Geom& g, const int l[4]) {
+    return ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
+}
+
+// Neighbour of site s (decoded as S) one step forward (+1) or backward (-1) in mu.
+// Sets inside = whether it lies in the same Schwarz block, and bc = the
+// time-boundary factor of the hop.
+template <int DIR>
+__device__ __forceinline__ int neighbour(const Geom& g, int s, const Site& S, int mu, bool& inside, int& bc) {
+    bc = 1;
+    if (DIR > 0) {
+        if (S.l[mu] < g.b[mu] - 1) {
+            inside = true;
+            return s + g.lstr[mu];
+        }
+        inside = false;
+        int n[4] = {S.n[0], S.n[1], S.n[2], S.n[3]};
+        int l[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+        l[mu] = 0;
+        n[mu] = n[mu] + 1;
+        if (n[mu] == g.nb[mu]) {
+            n[mu] = 0;
+            if (mu == 0) bc = g.tbc;
+        }
+        return block_base(g, n) + local_index(g, l);
+    } else {
+        if (S.l[mu] > 0) {
+            inside = true;
+            return s - g.lstr[mu];
+        }
+        inside = false;
+        int n[4] = {S.n[0], S.n[1], S.n[2], S.n[3]};
+        int l[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+        l[mu] = g.b[mu] - 1;
+        n[mu] = n[mu] - 1;
+        if (n[mu] < 0) {
+            n[mu] = g.nb[mu] - 1;
+            if (mu == 0) bc = g.tbc;
+        }
+        return block_base(g, n) + local_index(g, l);
+    }
+}
+
+// The black face sites: range of the projector P.
+__device__ __forceinline__ bool in_P(const Geom& g, const Site& S) {
+    if (S.c != 0) return false;
+    for (int mu = 0; mu < 4; ++mu)
+        if (S.l[mu] == 0 || S.l[mu] == g.b[mu] - 1) return true;
+    return false;
+}
+
+// Lexicographic (canonical) site index of a decoded internal site.
+__device__ __forceinline__ int canonical_index(const Geom& g, const Site& S) {
+    int x[4];
+    for (int mu = 0; mu < 4; ++mu) x[mu] = S.n[mu] * g.b[mu] + S.l[mu];
+    return ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+
+// ------------------------------------------------------------------ storage traits
+template <class R>
+struct Traits;
+
+template <>
+struct Traits<double> {
+    typedef double2 word;
+    static constexpr int NCW = 12;  // spinor words per site
+    static constexpr int NKW = 36;  // clover words per site
+};
+template <>
+struct Traits<float> {
+    typedef float4 word;
+    static constexpr int NCW = 6;
+    static constexpr int NKW = 18;
+};
+
+__device__ __forceinline__ void load_spinor(const double2* __restrict__ f, int V, int s, cx<double> p[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double2 w = f[(size_t)c * V + s];
+        p[c] = mk(w.x, w.y);
+    }
+}
+__device__ __forceinline__ void load_spinor(const float4* __restrict__ f, int V, int s, cx<float> p[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float4 w = f[(size_t)k * V + s];
+        p[2 * k] = mk(w.x, w.y);
+        p[2 * k + 1] = mk(w.z, w.w);
+    }
+}
+__device__ __forceinline__ void store_spinor(double2* __restrict__ f, int V, int s, const cx<double> p[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) f[(size_t)c * V + s] = make_double2(p[c].re, p[c].im);
+}
+__device__ __forceinline__ void store_spinor(float4* __restrict__ f, int V, int s, const cx<float> p[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        f[(size_t)k * V + s] = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
+}
+
+template <class R>
+__device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int V, int mu, int s, cx<R> u[9]) {
+    const cx<R>* base = U + (size_t)mu * 9 * V + s;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = base[(size_t)k * V];
+}
+
+// The 36 reals of chiral block `blk` of the clover term at site s:
+// d[0..5] = diagonal, o[0..29] = upper off-diagonal (re, im) in row order.
+__device__ __forceinline__ void load_clover_block(const double2* __restrict__ K, int V, int s, int blk, double d[6],
+                                                  double o[30]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double2 w = K[(size_t)(3 * blk + k) * V + s];
+        d[2 * k] = w.x;
+        d[2 * k + 1] = w.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+        double2 w = K[(size_t)(6 + 15 * blk + k) * V + s];
+        o[2 * k] = w.x;
+        o[2 * k + 1] = w.y;
+    }
+}
+// FP32: reals 0..11 are words 0..2; block 0 off-diagonal reals 12..41 start in word 3,
+// block 1 reals 42..71 start at word 10 offset 2.  Load the 9 words that cover a block.
+__device__ __forceinline__ void load_clover_block(const float4* __restrict__ K, int V, int s, int blk, float d[6],
+                                                  float o[30]) {
+    float w[40];
+    const int w0 = blk == 0 ? 3 : 10;  // first word holding off-diagonal reals of this block
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float4 q = K[(size_t)(w0 + k) * V + s];
+        w[4 * k] = q.x;
+        w[4 * k + 1] = q.y;
+        w[4 * k + 2] = q.z;
+        w[4 * k + 3] = q.w;
+    }
+    const int sh = blk == 0 ? 0 : 2;  // reals 42.. start at offset 2 of word 10
+#pragma unroll
+    for (int k = 0; k < 30; ++k) o[k] = w[sh + k];
+    // diagonal reals 6*blk .. 6*blk+5 live in words 0..2
+    float4 q0 = K[(size_t)(blk == 0 ? 0 : 1) * V + s];
+    float4 q1 = K[(size_t)(blk == 0 ? 1 : 2) * V + s];
+    if (blk == 0) {
+        d[0] = q0.x; d[1] = q0.y; d[2] = q0.z; d[3] = q0.w; d[4] = q1.x; d[5] = q1.y;
+    } else {
+        d[0] = q0.z; d[1] = q0.w; d[2] = q1.x; d[3] = q1.y; d[4] = q1.z; d[5] = q1.w;
+    }
+}
+
+// y = (4 + m) psi + C psi with the two packed Hermitian 6x6 blocks, one block at a time.
+template <class R>
+__device__ __forceinline__ void apply_diag(const typename Traits<R>::word* __restrict__ K, int V, int s, R mass4,
+                                           const cx<R> p[12], cx<R> y[12]) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        R d[6], o[30];
+        load_clover_block(K, V, s, blk, d, o);
+        const cx<R>* v = p + 6 * blk;
+        cx<R>* w = y + 6 * blk;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) w[i] = (mass4 + d[i]) * v[i];
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) {
+                cx<R> aij = mk(o[2 * k], o[2 * k + 1]);
+                w[i] = w[i] + aij * v[j];
+                w[j] = w[j] + conj_mul(aij, v[i]);
+                ++k;
+            }
+        }
+    }
+}
+
+// acc += (1 - g_mu) U psi_nb (DIR = +1) or (1 + g_mu) U^+ psi_nb (DIR = -1), chiral basis,
+// through the spin-projected half spinor h (2 spins x 3 colours).
+template <class R, int DIR>
+__device__ __forceinline__ void hop_accumulate(int mu, const cx<R> u[9], const cx<R> q[12], R fac, cx<R> acc[12]) {
+    cx<R> h[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<R> p0 = q[a], p1 = q[3 + a], p2 = q[6 + a], p3 = q[9 + a];
+        if (mu == 0) {
+            if (DIR > 0) { h[0][a] = p0 + p2; h[1][a] = p1 + p3; }
+            else         { h[0][a] = p0 - p2; h[1][a] = p1 - p3; }
+        } else if (mu == 1) {
+            if (DIR > 0) { h[0][a] = p0 + times_i(p3); h[1][a] = p1 + times_i(p2); }
+            else         { h[0][a] = p0 - times_i(p3); h[1][a] = p1 - times_i(p2); }
+        } else if (mu == 2) {
+            if (DIR > 0) { h[0][a] = p0 + p3; h[1][a] = p1 - p2; }
+            else         { h[0][a] = p0 - p3; h[1][a] = p1 + p2; }
+        } else {
+            if (DIR > 0) { h[0][a] = p0 + times_i(p2); h[1][a] = p1 - times_i(p3); }
+            else         { h[0][a] = p0 - times_i(p2); h[1][a] = p1 + times_i(p3); }
+        }
+    }
+    cx<R> k[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> t;
+            if (DIR > 0) {
+                t = u[3 * a] * h[s][0] + u[3 * a + 1] * h[s][1] + u[3 * a + 2] * h[s][2];
+            } else {
+                t = conj_mul(u[a], h[s][0]) + conj_mul(u[3 + a], h[s][1]) + conj_mul(u[6 + a], h[s][2]);
+            }
+            k[s][a] = fac * t;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + k[0][a];
+        acc[3 + a] = acc[3 + a] + k[1][a];
+        cx<R> l0, l1;
+        if (mu == 0) {
+            if (DIR > 0) { l0 = k[0][a]; l1 = k[1][a]; }
+            else         { l0 = -k[0][a]; l1 = -k[1][a]; }
+        } else if (mu == 1) {
+            if (DIR > 0) { l0 = times_mi(k[1][a]); l1 = times_mi(k[0][a]); }
+            else         { l0 = times_i(k[1][a]); l1 = times_i(k[0][a]); }
+        } else if (mu == 2) {
+            if (DIR > 0) { l0 = -k[1][a]; l1 = k[0][a]; }
+            else         { l0 = k[1][a]; l1 = -k[0][a]; }
+        } else {
+            if (DIR > 0) { l0 = times_mi(k[0][a]); l1 = times_i(k[1][a]); }
+            else         { l0 = times_i(k[0][a]); l1 = times_mi(k[1][a]); }
+        }
+        acc[6 + a] = acc[6 + a] + l0;
+        acc[9 + a] = acc[9 + a] + l1;
+    }
+}
+
+// Which hops a site operator includes.
+enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
+
+// y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops.  `in` points at one RHS.
+// The diagonal part is applied first; the hops then accumulate into y with the factor
+// -1/2 (times the time-boundary sign) folded into the half-spinor products.
+template <class R, bool DIAG, int HOPS>
+__device__ __forceinline__ void site_operator(const Geom& g, int s, const typename Traits<R>::word* __restrict__ in,
+                                              const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
+                                              R mass4, cx<R> y[12]) {
+    const int V = g.V;
+    if (DIAG) {
+        cx<R> c[12];
+        load_spinor(in, V, s, c);
+        apply_diag<R>(K, V, s, mass4, c, y);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) y[c] = mk(R(0), R(0));
+    }
+    if (HOPS != HOPS_NONE) {
+        Site S = decode(g, s);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            {
+                bool inside;
+                int bc;
+                int t = neighbour<+1>(g, s, S, mu, inside, bc);
+                bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+                if (take) {
+                    cx<R> q[12], u[9];
+                    load_spinor(in, V, t, q);
+                    load_link(U, V, mu, s, u);
+                    hop_accumulate<R, +1>(mu, u, q, R(-0.5) * R(bc), y);
+                }
+            }
+            {
+                bool inside;
+                int bc;
+                int t = neighbour<-1>(g, s, S, mu, inside, bc);
+                bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+                if (take) {
+                    cx<R> q[12], u[9];
+                    load_spinor(in, V, t, q);
+                    load_link(U, V, mu, t, u);
+                    hop_accumulate<R, -1>(mu, u, q, R(-0.5) * R(bc), y);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+// Sum over the workgroup; every thread receives the total.  `lds` holds one
+// double per wave; the order of the sums is fixed, so results are reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0)
+        for (int k = 0; k < NV; ++k) lds[k * 16 + wave] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = 0;
+        for (int w = 0; w < nw; ++w) t += lds[k * 16 + w];
+        v[k] = t;
+    }
+}
+
+// ------------------------------------------------------------------ per-site dot products (FP64 accumulate)
+template <class R>
+__device__ __forceinline__ void acc_dot(const cx<R> a[12], const cx<R> b[12], double& re, double& im) {
+    // (a, b) = sum conj(a) b
+    R sr = 0, si = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        sr += a[c].re * b[c].re + a[c].im * b[c].im;
+        si += a[c].re * b[c].im - a[c].im * b[c].re;
+    }
+    re += (double)sr;
+    im += (double)si;
+}
+
+template <class R>
+__device__ __forceinline__ double acc_nrm(const cx<R> a[12]) {
+    R s = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) s += a[c].re * a[c].re + a[c].im * a[c].im;
+    return (double)s;
+}
+
+}  // namespace ddwc

@@ -1,0 +1,156 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "ddwc_device.h"
+
+namespace ddwc {
+
+// Per-RHS BiCGStab scalars, kept on the device so that iterations need no host round trip.
+struct BiState {
+    double rho[2], alpha[2], omega[2], beta[2];
+    double rr;    // ||r||^2 after the last iteration
+    double thr2;  // stop when rr <= thr2
+    int active;   // 0 once converged (or broken down): updates become no-ops
+    int broken;   // breakdown (zero denominator) detected
+};
+
+enum Stage { ST_SUM = 0, ST_INIT = 1, ST_ALPHA = 2, ST_OMEGA = 3, ST_BETA = 4 };
+
+// Spinor masks for import / combination kernels.
+enum Mask { MASK_ALL = 0, MASK_P = 1, MASK_BLACK = 2, MASK_WHITE = 3 };
+
+// Kernel timing with HIP events (measurement only).
+struct Profiler {
+    bool on = false;
+    struct Pair {
+        hipEvent_t a, b;
+        int kclass;
+        double bytes;
+    };
+    std::vector<Pair> pending;
+    std::vector<hipEvent_t> pool;
+    long long launches[8] = {0};
+    double ms[8] = {0};
+    double bytes[8] = {0};
+    hipEvent_t get();
+    void begin(hipStream_t s, int kclass, double bytes, Pair& p);
+    void end(hipStream_t s, Pair& p);
+    void harvest();  // synchronises on the pending events
+    void reset();
+    ~Profiler();
+};
+
+struct Exec {
+    hipStream_t stream;
+    Profiler* prof;
+};
+
+// RAII-free scoped timing helper used by the launchers.
+struct Timed {
+    Exec& e;
+    Profiler::Pair p;
+    bool active;
+    Timed(Exec& ex, int kclass, double bytes) : e(ex), active(ex.prof && ex.prof->on) {
+        if (active) e.prof->begin(e.stream, kclass, bytes, p);
+    }
+    ~Timed() {
+        if (active) e.prof->end(e.stream, p);
+    }
+};
+
+// ------------------------------------------------------------------ launchers (kernels.hip)
+constexpr int WG = 256;  // sites per workgroup of the site-parallel kernels
+constexpr int NPART = 4; // doubles per partial-sum slot
+
+inline int tiles_of(int n) { return (n + WG - 1) / WG; }
+
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32);
+void launch_clover_build(Exec& e, const Geom& g, const cx<double>* U64, double csw, double2* K64, float4* K32);
+
+template <class R>
+void launch_import(Exec& e, const Geom& g, const void* canon, typename Traits<R>::word* out, int nrhs, int mask);
+template <class R>
+void launch_export(Exec& e, const Geom& g, const typename Traits<R>::word* in, void* canon, int nrhs, int mask);
+
+// out = D(m) in over all sites (no reductions).
+template <class R>
+void launch_dslash(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                   const typename Traits<R>::word* in, typename Traits<R>::word* out, int nrhs, int kclass,
+                   double bytes);
+// out = D(m) in, partial[rhs][tile] = (w, out) (complex).
+template <class R>
+void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                       const typename Traits<R>::word* in, typename Traits<R>::word* out,
+                       const typename Traits<R>::word* w, double* part, int nrhs, int kclass, double bytes);
+// out = D(m) in, partials (out, in) complex and (out, out).
+template <class R>
+void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                        const typename Traits<R>::word* in, typename Traits<R>::word* out, double* part, int nrhs,
+                        int kclass, double bytes);
+// r = b - D(m) x, partial ||r||^2.
+template <class R>
+void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                     const typename Traits<R>::word* x, const typename Traits<R>::word* b,
+                     typename Traits<R>::word* r, double* part, int nrhs, int kclass, double bytes);
+// out = hops crossing block faces into sites of colour `to_colour` (D_wb for white, D_bw for
+// black); out is zero on the other colour.
+template <class R>
+void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
+                typename Traits<R>::word* out, int nrhs, int to_colour);
+
+// BiCGStab vector kernels (nrhs multi-vectors, per-RHS scalars in st).
+template <class R>
+void launch_bicg_init(Exec& e, const Geom& g, const double2* r64, const double* scale,
+                      typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
+                      typename Traits<R>::word* x, double* part, int nrhs);
+template <class R>
+void launch_bicg_s(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+                   const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs);
+template <class R>
+void launch_bicg_xr(Exec& e, const Geom& g, const BiState* st, typename Traits<R>::word* x,
+                    const typename Traits<R>::word* p, const typename Traits<R>::word* s,
+                    const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
+                    typename Traits<R>::word* r, double* part, int nrhs);
+template <class R>
+void launch_bicg_p(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+                   const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs);
+// x64 += (1/scale) * x_R (per RHS); only RHS with active_mask set are touched.
+template <class R>
+void launch_accumulate(Exec& e, const Geom& g, const typename Traits<R>::word* x, const double* scale,
+                       double2* x64, int nrhs);
+
+// Sums partials per RHS in a fixed order and applies the BiCGStab stage update.
+void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
+                     const double* thr_rel2);
+
+// FP64 helpers on internal vectors.
+// z = a*x + b*y on sites selected by mask (others of z set to zero); x or y may be null (= 0).
+void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, const double2* y, double2* z,
+                  int nrhs, int mask);
+// partials: (x, y) complex and (y, y) per RHS; x may equal y.
+void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs);
+
+// ------------------------------------------------------------------ block solver (block_solver.hip)
+struct BlockSolveArgs {
+    const double2* b;     // FP64 right-hand sides, internal layout
+    double2* x;           // FP64 solutions
+    double2* r64;         // FP64 residual scratch
+    void* w[6];           // inner-precision scratch vectors: r, rh, p, v, t, e
+    int colour;
+    int nrhs;
+    double mass4;
+    double tol;
+    int maxit;
+    int* iters;           // [nrhs][NBc] inner iterations per block
+    int* outer;           // [nrhs][NBc] defect-correction steps per block
+    double* relres;       // [nrhs][NBc] final FP64 relative residual per block
+};
+void launch_block_solve64(Exec& e, const Geom& g, const cx<double>* U, const double2* K, const BlockSolveArgs& a);
+void launch_block_solve32(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const cx<float>* U32,
+                          const float4* K32, const BlockSolveArgs& a);
+int block_solver_threads(const Geom& g);
+
+}  // namespace ddwc

@@ -1,0 +1,653 @@
+// Site-parallel kernels: layout conversion, clover build, Wilson-clover operator
+// variants with fused reductions, BiCGStab vector updates, FP64 reductions.
+//
+// Mapping: one thread per (site, RHS); a workgroup holds WG consecutive internal
+// sites of one RHS.  Workgroups are numbered tile-major / RHS-minor and remapped so
+// that each of the 8 XCDs sweeps one contiguous range: the RHS of a tile share its
+// links and clover in that XCD's L2, and face neighbours of consecutive Schwarz
+// blocks stay in the same L2.
+#include "ddwc_internal.h"
+
+namespace ddwc {
+
+#define HIPCHECK_LAUNCH() (void)hipGetLastError()
+
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+    if ((n & 7) != 0) return i;
+    return (i & 7) * (n >> 3) + (i >> 3);
+}
+
+struct TileRhs {
+    int tile, rhs;
+};
+
+__device__ __forceinline__ TileRhs tile_rhs(int ntiles, int nrhs) {
+    int L = xcd_remap(blockIdx.x, ntiles * nrhs);
+    TileRhs t;
+    t.tile = L / nrhs;
+    t.rhs = L - t.tile * nrhs;
+    return t;
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double v[NV], double* part, int ntiles, TileRhs tr) {
+    __shared__ double lds[NV * 16];
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+        double* p = part + ((size_t)tr.rhs * ntiles + tr.tile) * NPART;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) p[k] = v[k];
+    }
+}
+
+// ------------------------------------------------------------------ conversions
+__global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<double>* __restrict__ U64,
+                               cx<float>* __restrict__ U32) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int mu = blockIdx.y;
+    if (s >= g.V) return;
+    Site S = decode(g, s);
+    int x = canonical_index(g, S);
+    const double2* src = can + ((size_t)mu * g.V + x) * 9;
+    for (int k = 0; k < 9; ++k) {
+        double2 w = src[k];
+        size_t o = ((size_t)mu * 9 + k) * g.V + s;
+        U64[o] = mk(w.x, w.y);
+        U32[o] = mk((float)w.x, (float)w.y);
+    }
+}
+
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32) {
+    Timed t(e, 4, 0);
+    dim3 grid(tiles_of(g.V), 4);
+    k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32);
+}
+
+// Neighbour of an arbitrary internal site (decodes it first).
+template <int DIR>
+__device__ int step(const Geom& g, int s, int mu) {
+    Site S = decode(g, s);
+    bool in;
+    int bc;
+    return neighbour<DIR>(g, s, S, mu, in, bc);
+}
+
+struct M3 {
+    cx<double> a[9];
+};
+
+__device__ M3 ld(const cx<double>* U, const Geom& g, int mu, int s) {
+    M3 m;
+    for (int k = 0; k < 9; ++k) m.a[k] = U[((size_t)mu * 9 + k) * g.V + s];
+    return m;
+}
+__device__ M3 mul(const M3& x, const M3& y) {
+    M3 z;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cx<double> t = mk(0.0, 0.0);
+            for (int k = 0; k < 3; ++k) t = t + x.a[3 * i + k] * y.a[3 * k + j];
+            z.a[3 * i + j] = t;
+        }
+    return z;
+}
+__device__ M3 dag(const M3& x) {
+    M3 z;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) z.a[3 * i + j] = mk(x.a[3 * j + i].re, -x.a[3 * j + i].im);
+    return z;
+}
+
+// Fhat_{mu nu}(s) = (Q - Q^+)/8 from the four plaquette leaves at s (no boundary signs).
+__device__ M3 field_strength(const Geom& g, const cx<double>* U, int s, int mu, int nu) {
+    int xpm = step<+1>(g, s, mu), xpn = step<+1>(g, s, nu);
+    int xmm = step<-1>(g, s, mu), xmn = step<-1>(g, s, nu);
+    int xmm_pn = step<+1>(g, xmm, nu), xmm_mn = step<-1>(g, xmm, nu), xpm_mn = step<-1>(g, xpm, nu);
+    M3 q1 = mul(mul(ld(U, g, mu, s), ld(U, g, nu, xpm)), mul(dag(ld(U, g, mu, xpn)), dag(ld(U, g, nu, s))));
+    M3 q2 = mul(mul(ld(U, g, nu, s), dag(ld(U, g, mu, xmm_pn))), mul(dag(ld(U, g, nu, xmm)), ld(U, g, mu, xmm)));
+    M3 q3 = mul(mul(dag(ld(U, g, mu, xmm)), dag(ld(U, g, nu, xmm_mn))), mul(ld(U, g, mu, xmm_mn), ld(U, g, nu, xmn)));
+    M3 q4 = mul(mul(dag(ld(U, g, nu, xmn)), ld(U, g, mu, xmn)), mul(ld(U, g, nu, xpm_mn), dag(ld(U, g, mu, s))));
+    M3 F;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cx<double> q = q1.a[3 * i + j] + q2.a[3 * i + j] + q3.a[3 * i + j] + q4.a[3 * i + j];
+            cx<double> qt = q1.a[3 * j + i] + q2.a[3 * j + i] + q3.a[3 * j + i] + q4.a[3 * j + i];
+            F.a[3 * i + j] = mk((q.re - qt.re) / 8.0, (q.im + qt.im) / 8.0);
+        }
+    return F;
+}
+
+// Clover term in the chiral basis: sigma_{0k} = diag(s_k, -s_k), sigma_{jk} = -eps_{jkl} diag(s_l, s_l),
+// so C = (i c_sw / 2) sum_l diag(s_l x E_l, s_l x E'_l) with
+// E = (F01 - F23, F02 + F13, F03 - F12), E' = -(F01 + F23, F02 - F13, F03 + F12).
+__global__ void k_clover_build(Geom g, const cx<double>* __restrict__ U, double csw, double2* __restrict__ K64,
+                               float4* __restrict__ K32) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    M3 F01 = field_strength(g, U, s, 0, 1), F02 = field_strength(g, U, s, 0, 2), F03 = field_strength(g, U, s, 0, 3);
+    M3 F12 = field_strength(g, U, s, 1, 2), F13 = field_strength(g, U, s, 1, 3), F23 = field_strength(g, U, s, 2, 3);
+    double a[72];
+    for (int blk = 0; blk < 2; ++blk) {
+        double sg = blk == 0 ? 1.0 : -1.0;
+        M3 E1, E2, E3;
+        for (int k = 0; k < 9; ++k) {
+            if (blk == 0) {
+                E1.a[k] = F01.a[k] - F23.a[k];
+                E2.a[k] = F02.a[k] + F13.a[k];
+                E3.a[k] = F03.a[k] - F12.a[k];
+            } else {
+                E1.a[k] = -(F01.a[k] + F23.a[k]);
+                E2.a[k] = -(F02.a[k] - F13.a[k]);
+                E3.a[k] = -(F03.a[k] + F12.a[k]);
+            }
+        }
+        (void)sg;
+        cx<double> M[6][6];
+        const cx<double> ic2 = mk(0.0, 0.5 * csw);
+        for (int a1 = 0; a1 < 3; ++a1)
+            for (int b1 = 0; b1 < 3; ++b1) {
+                int k = 3 * a1 + b1;
+                M[a1][b1] = ic2 * E3.a[k];
+                M[3 + a1][3 + b1] = -(ic2 * E3.a[k]);
+                M[a1][3 + b1] = ic2 * (E1.a[k] - times_i(E2.a[k]));
+                M[3 + a1][b1] = ic2 * (E1.a[k] + times_i(E2.a[k]));
+            }
+        for (int i = 0; i < 6; ++i) a[6 * blk + i] = M[i][i].re;
+        int k = 0;
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j) {
+                a[12 + 30 * blk + 2 * k] = M[i][j].re;
+                a[12 + 30 * blk + 2 * k + 1] = M[i][j].im;
+                ++k;
+            }
+    }
+    for (int k = 0; k < 36; ++k) K64[(size_t)k * g.V + s] = make_double2(a[2 * k], a[2 * k + 1]);
+    for (int k = 0; k < 18; ++k)
+        K32[(size_t)k * g.V + s] = make_float4((float)a[4 * k], (float)a[4 * k + 1], (float)a[4 * k + 2], (float)a[4 * k + 3]);
+}
+
+void launch_clover_build(Exec& e, const Geom& g, const cx<double>* U64, double csw, double2* K64, float4* K32) {
+    Timed t(e, 4, 0);
+    k_clover_build<<<(g.V + 127) / 128, 128, 0, e.stream>>>(g, U64, csw, K64, K32);
+}
+
+__device__ __forceinline__ bool mask_keep(const Geom& g, const Site& S, int mask) {
+    switch (mask) {
+        case MASK_P: return in_P(g, S);
+        case MASK_BLACK: return S.c == 0;
+        case MASK_WHITE: return S.c == 1;
+        default: return true;
+    }
+}
+
+template <class R>
+__global__ void k_import(Geom g, const double2* __restrict__ can, typename Traits<R>::word* __restrict__ out,
+                         int nrhs, int mask) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int rhs = blockIdx.y;
+    if (s >= g.V) return;
+    Site S = decode(g, s);
+    bool keep = mask_keep(g, S, mask);
+    const double2* src = can + ((size_t)rhs * g.V + canonical_index(g, S)) * 12;
+    cx<R> p[12];
+    for (int c = 0; c < 12; ++c) {
+        double2 w = src[c];
+        p[c] = keep ? mk((R)w.x, (R)w.y) : mk(R(0), R(0));
+    }
+    store_spinor(out + (size_t)rhs * Traits<R>::NCW * g.V, g.V, s, p);
+}
+
+template <class R>
+__global__ void k_export(Geom g, const typename Traits<R>::word* __restrict__ in, double2* __restrict__ can, int nrhs,
+                         int mask) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int rhs = blockIdx.y;
+    if (s >= g.V) return;
+    Site S = decode(g, s);
+    bool keep = mask_keep(g, S, mask);
+    cx<R> p[12];
+    load_spinor(in + (size_t)rhs * Traits<R>::NCW * g.V, g.V, s, p);
+    double2* dst = can + ((size_t)rhs * g.V + canonical_index(g, S)) * 12;
+    for (int c = 0; c < 12; ++c) dst[c] = keep ? make_double2((double)p[c].re, (double)p[c].im) : make_double2(0, 0);
+}
+
+template <class R>
+void launch_import(Exec& e, const Geom& g, const void* canon, typename Traits<R>::word* out, int nrhs, int mask) {
+    Timed t(e, 4, 0);
+    k_import<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, (const double2*)canon, out, nrhs, mask);
+}
+template <class R>
+void launch_export(Exec& e, const Geom& g, const typename Traits<R>::word* in, void* canon, int nrhs, int mask) {
+    Timed t(e, 4, 0);
+    k_export<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, in, (double2*)canon, nrhs, mask);
+}
+
+// ------------------------------------------------------------------ operator kernels
+enum Epi { EPI_NONE = 0, EPI_DOT = 1, EPI_DOT2 = 2, EPI_RESID = 3 };
+
+template <class R, int EPI>
+__global__ __launch_bounds__(WG) void k_dslash(Geom g, const cx<R>* __restrict__ U,
+                                               const typename Traits<R>::word* __restrict__ K, R mass4,
+                                               const typename Traits<R>::word* __restrict__ in,
+                                               typename Traits<R>::word* __restrict__ out,
+                                               const typename Traits<R>::word* __restrict__ aux, double* part,
+                                               int nrhs, int ntiles) {
+    typedef typename Traits<R>::word W;
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    double v[3] = {0, 0, 0};
+    if (s < g.V) {
+        cx<R> y[12];
+        site_operator<R, true, HOPS_ALL>(g, s, in + off, U, K, mass4, y);
+        if (EPI == EPI_RESID) {
+            cx<R> b[12];
+            load_spinor((const W*)aux + off, g.V, s, b);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) y[k] = b[k] - y[k];
+            v[0] = acc_nrm(y);
+        }
+        store_spinor(out + off, g.V, s, y);
+        if (EPI == EPI_DOT) {
+            cx<R> w[12];
+            load_spinor(aux + off, g.V, s, w);
+            acc_dot(w, y, v[0], v[1]);
+        }
+        if (EPI == EPI_DOT2) {
+            cx<R> c[12];
+            load_spinor(in + off, g.V, s, c);
+            acc_dot(y, c, v[0], v[1]);  // (t, s)
+            v[2] = acc_nrm(y);          // (t, t)
+        }
+    }
+    if (EPI == EPI_DOT) write_partials<2>(v, part, ntiles, tr);
+    if (EPI == EPI_DOT2) write_partials<3>(v, part, ntiles, tr);
+    if (EPI == EPI_RESID) write_partials<1>(v, part, ntiles, tr);
+}
+
+template <class R>
+void launch_dslash(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                   const typename Traits<R>::word* in, typename Traits<R>::word* out, int nrhs, int kclass,
+                   double bytes) {
+    Timed t(e, kclass, bytes);
+    int nt = tiles_of(g.V);
+    k_dslash<R, EPI_NONE><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, nullptr, nrhs, nt);
+}
+template <class R>
+void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                       const typename Traits<R>::word* in, typename Traits<R>::word* out,
+                       const typename Traits<R>::word* w, double* part, int nrhs, int kclass, double bytes) {
+    Timed t(e, kclass, bytes);
+    int nt = tiles_of(g.V);
+    k_dslash<R, EPI_DOT><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, w, part, nrhs, nt);
+}
+template <class R>
+void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                        const typename Traits<R>::word* in, typename Traits<R>::word* out, double* part, int nrhs,
+                        int kclass, double bytes) {
+    Timed t(e, kclass, bytes);
+    int nt = tiles_of(g.V);
+    k_dslash<R, EPI_DOT2><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, part, nrhs, nt);
+}
+template <class R>
+void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                     const typename Traits<R>::word* x, const typename Traits<R>::word* b,
+                     typename Traits<R>::word* r, double* part, int nrhs, int kclass, double bytes) {
+    Timed t(e, kclass, bytes);
+    int nt = tiles_of(g.V);
+    k_dslash<R, EPI_RESID><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, x, r, b, part, nrhs, nt);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_hop(Geom g, const cx<R>* __restrict__ U,
+                                            const typename Traits<R>::word* __restrict__ in,
+                                            typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int rhs = blockIdx.y;
+    if (s >= g.V) return;
+    const size_t off = (size_t)rhs * Traits<R>::NCW * g.V;
+    cx<R> y[12];
+    if ((s / (g.V / 2)) == to_colour) {
+        site_operator<R, false, HOPS_CROSSING>(g, s, in + off, U, nullptr, R(0), y);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) y[k] = mk(R(0), R(0));
+    }
+    store_spinor(out + off, g.V, s, y);
+}
+
+template <class R>
+void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
+                typename Traits<R>::word* out, int nrhs, int to_colour) {
+    Timed t(e, 4, 0);
+    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour);
+}
+
+// ------------------------------------------------------------------ BiCGStab vector kernels
+template <class R>
+__device__ __forceinline__ cx<R> cxs(const double* a) {
+    return mk((R)a[0], (R)a[1]);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_bicg_init(Geom g, const double2* __restrict__ r64, const double* __restrict__ scale,
+                                                  typename Traits<R>::word* r, typename Traits<R>::word* rh,
+                                                  typename Traits<R>::word* p, typename Traits<R>::word* x,
+                                                  double* part, int nrhs, int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    double v[1] = {0};
+    if (s < g.V) {
+        cx<double> a[12];
+        load_spinor(r64 + (size_t)tr.rhs * 12 * g.V, g.V, s, a);
+        const double sc = scale[tr.rhs];
+        cx<R> q[12], z[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            q[k] = mk((R)(sc * a[k].re), (R)(sc * a[k].im));
+            z[k] = mk(R(0), R(0));
+        }
+        store_spinor(r + off, g.V, s, q);
+        store_spinor(rh + off, g.V, s, q);
+        store_spinor(p + off, g.V, s, q);
+        store_spinor(x + off, g.V, s, z);
+        v[0] = acc_nrm(q);
+    }
+    write_partials<1>(v, part, ntiles, tr);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_bicg_s(Geom g, const BiState* __restrict__ st,
+                                               const typename Traits<R>::word* __restrict__ r,
+                                               const typename Traits<R>::word* __restrict__ v,
+                                               typename Traits<R>::word* __restrict__ s_out, int nrhs, int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    const cx<R> al = cxs<R>(st[tr.rhs].alpha);
+    cx<R> a[12], b[12];
+    load_spinor(r + off, g.V, s, a);
+    load_spinor(v + off, g.V, s, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = a[k] - al * b[k];
+    store_spinor(s_out + off, g.V, s, a);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_bicg_xr(Geom g, const BiState* __restrict__ st,
+                                                typename Traits<R>::word* __restrict__ x,
+                                                const typename Traits<R>::word* __restrict__ p,
+                                                const typename Traits<R>::word* __restrict__ sv,
+                                                const typename Traits<R>::word* __restrict__ t,
+                                                const typename Traits<R>::word* __restrict__ rh,
+                                                typename Traits<R>::word* __restrict__ r, double* part, int nrhs,
+                                                int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    double v[3] = {0, 0, 0};
+    if (s < g.V) {
+        const cx<R> al = cxs<R>(st[tr.rhs].alpha), om = cxs<R>(st[tr.rhs].omega);
+        cx<R> xx[12], pp[12], ss[12], tt[12];
+        load_spinor(x + off, g.V, s, xx);
+        load_spinor(p + off, g.V, s, pp);
+        load_spinor(sv + off, g.V, s, ss);
+        load_spinor(t + off, g.V, s, tt);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            xx[k] = xx[k] + al * pp[k] + om * ss[k];
+            ss[k] = ss[k] - om * tt[k];
+        }
+        store_spinor(x + off, g.V, s, xx);
+        store_spinor(r + off, g.V, s, ss);
+        load_spinor(rh + off, g.V, s, pp);
+        acc_dot(pp, ss, v[0], v[1]);
+        v[2] = acc_nrm(ss);
+    }
+    write_partials<3>(v, part, ntiles, tr);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_bicg_p(Geom g, const BiState* __restrict__ st,
+                                               const typename Traits<R>::word* __restrict__ r,
+                                               const typename Traits<R>::word* __restrict__ v,
+                                               typename Traits<R>::word* __restrict__ p, int nrhs, int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    const cx<R> be = cxs<R>(st[tr.rhs].beta), om = cxs<R>(st[tr.rhs].omega);
+    cx<R> rr[12], pp[12], vv[12];
+    load_spinor(r + off, g.V, s, rr);
+    load_spinor(p + off, g.V, s, pp);
+    load_spinor(v + off, g.V, s, vv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pp[k] = rr[k] + be * (pp[k] - om * vv[k]);
+    store_spinor(p + off, g.V, s, pp);
+}
+
+template <class R>
+__global__ __launch_bounds__(WG) void k_accumulate(Geom g, const typename Traits<R>::word* __restrict__ x,
+                                                   const double* __restrict__ scale, double2* __restrict__ x64,
+                                                   int nrhs, int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    if (s >= g.V) return;
+    const double sc = scale[tr.rhs];
+    if (sc == 0.0) return;
+    const double inv = 1.0 / sc;
+    cx<R> a[12];
+    cx<double> b[12];
+    load_spinor(x + (size_t)tr.rhs * Traits<R>::NCW * g.V, g.V, s, a);
+    double2* dst = x64 + (size_t)tr.rhs * 12 * g.V;
+    load_spinor(dst, g.V, s, b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k] = b[k] + mk(inv * (double)a[k].re, inv * (double)a[k].im);
+    store_spinor(dst, g.V, s, b);
+}
+
+template <class R>
+void launch_bicg_init(Exec& e, const Geom& g, const double2* r64, const double* scale,
+                      typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
+                      typename Traits<R>::word* x, double* part, int nrhs) {
+    Timed t(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_bicg_init<R><<<nt * nrhs, WG, 0, e.stream>>>(g, r64, scale, r, rh, p, x, part, nrhs, nt);
+}
+template <class R>
+void launch_bicg_s(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+                   const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs) {
+    Timed t(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_bicg_s<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, r, v, s, nrhs, nt);
+}
+template <class R>
+void launch_bicg_xr(Exec& e, const Geom& g, const BiState* st, typename Traits<R>::word* x,
+                    const typename Traits<R>::word* p, const typename Traits<R>::word* s,
+                    const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
+                    typename Traits<R>::word* r, double* part, int nrhs) {
+    Timed tm(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_bicg_xr<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, x, p, s, t, rh, r, part, nrhs, nt);
+}
+template <class R>
+void launch_bicg_p(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+                   const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs) {
+    Timed t(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_bicg_p<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, r, v, p, nrhs, nt);
+}
+template <class R>
+void launch_accumulate(Exec& e, const Geom& g, const typename Traits<R>::word* x, const double* scale,
+                       double2* x64, int nrhs) {
+    Timed t(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_accumulate<R><<<nt * nrhs, WG, 0, e.stream>>>(g, x, scale, x64, nrhs, nt);
+}
+
+// ------------------------------------------------------------------ finalize (one workgroup per RHS)
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
+                                                  double* __restrict__ sums, BiState* __restrict__ st, int stage,
+                                                  const double* __restrict__ thr_rel2) {
+    const int rhs = blockIdx.x;
+    double v[NPART] = {0, 0, 0, 0};
+    for (int w = threadIdx.x; w < ntiles; w += blockDim.x) {
+        const double* p = part + ((size_t)rhs * ntiles + w) * NPART;
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) v[k] += p[k];
+    }
+    __shared__ double lds[NPART * 16];
+    block_sum<NPART>(v, lds);
+    if (threadIdx.x != 0) return;
+    if (sums)
+        for (int k = 0; k < NPART; ++k) sums[rhs * NPART + k] = v[k];
+    if (!st) return;
+    BiState S = st[rhs];
+    if (stage == ST_INIT) {
+        S.rho[0] = v[0];
+        S.rho[1] = 0;
+        S.rr = v[0];
+        S.thr2 = thr_rel2[rhs] * v[0];
+        S.active = (v[0] > S.thr2 && thr_rel2[rhs] < 1.0) ? 1 : 0;
+        S.broken = 0;
+        S.alpha[0] = S.alpha[1] = S.omega[0] = S.omega[1] = S.beta[0] = S.beta[1] = 0;
+    } else if (stage == ST_ALPHA) {
+        double d = v[0] * v[0] + v[1] * v[1];
+        if (S.active && d > 0 && isfinite(d)) {
+            // alpha = rho / (rh, v)
+            S.alpha[0] = (S.rho[0] * v[0] + S.rho[1] * v[1]) / d;
+            S.alpha[1] = (S.rho[1] * v[0] - S.rho[0] * v[1]) / d;
+        } else {
+            if (S.active) S.broken = 1;
+            S.active = 0;
+            S.alpha[0] = S.alpha[1] = 0;
+        }
+    } else if (stage == ST_OMEGA) {
+        if (S.active && v[2] > 0 && isfinite(v[2])) {
+            S.omega[0] = v[0] / v[2];
+            S.omega[1] = v[1] / v[2];
+        } else {
+            // t = 0 means s = 0: x += alpha p is exact, stop here
+            S.omega[0] = S.omega[1] = 0;
+            if (S.active && !(v[2] >= 0)) S.broken = 1;
+        }
+    } else if (stage == ST_BETA) {
+        if (S.active) {
+            S.rr = v[2];
+            double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
+            double rh2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+            if (!isfinite(v[2])) {
+                S.broken = 1;
+                S.active = 0;
+            } else if (v[2] <= S.thr2) {
+                S.active = 0;
+            } else if (om2 == 0 || rh2 == 0) {
+                S.broken = 1;
+                S.active = 0;
+            }
+            if (S.active) {
+                // beta = (rho_new / rho) (alpha / omega)
+                double qr = (v[0] * S.rho[0] + v[1] * S.rho[1]) / rh2;
+                double qi = (v[1] * S.rho[0] - v[0] * S.rho[1]) / rh2;
+                double ar = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
+                double ai = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
+                S.beta[0] = qr * ar - qi * ai;
+                S.beta[1] = qr * ai + qi * ar;
+                S.rho[0] = v[0];
+                S.rho[1] = v[1];
+            }
+        }
+        if (!S.active) {
+            S.alpha[0] = S.alpha[1] = S.omega[0] = S.omega[1] = S.beta[0] = S.beta[1] = 0;
+        }
+    }
+    st[rhs] = S;
+}
+
+void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
+                     const double* thr_rel2) {
+    Timed t(e, 3, 0);
+    k_finalize<<<nrhs, 256, 0, e.stream>>>(part, ntiles, nrhs, sums, st, stage, thr_rel2);
+}
+
+// ------------------------------------------------------------------ FP64 helpers
+__global__ __launch_bounds__(WG) void k_axpby(Geom g, double a, const double2* __restrict__ x, double b,
+                                              const double2* __restrict__ y, double2* __restrict__ z, int nrhs,
+                                              int mask) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int rhs = blockIdx.y;
+    if (s >= g.V) return;
+    Site S = decode(g, s);
+    bool keep = mask_keep(g, S, mask);
+    const size_t off = (size_t)rhs * 12 * g.V;
+    cx<double> u[12], w[12];
+    for (int k = 0; k < 12; ++k) u[k] = w[k] = mk(0.0, 0.0);
+    if (keep) {
+        if (x) load_spinor(x + off, g.V, s, u);
+        if (y) load_spinor(y + off, g.V, s, w);
+        for (int k = 0; k < 12; ++k) u[k] = a * u[k] + b * w[k];
+    }
+    store_spinor(z + off, g.V, s, u);
+}
+
+void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, const double2* y, double2* z,
+                  int nrhs, int mask) {
+    Timed t(e, 4, 0);
+    k_axpby<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, a, x, b, y, z, nrhs, mask);
+}
+
+__global__ __launch_bounds__(WG) void k_dots(Geom g, const double2* __restrict__ x, const double2* __restrict__ y,
+                                             double* part, int nrhs, int ntiles) {
+    TileRhs tr = tile_rhs(ntiles, nrhs);
+    const int s = tr.tile * WG + threadIdx.x;
+    double v[3] = {0, 0, 0};
+    if (s < g.V) {
+        const size_t off = (size_t)tr.rhs * 12 * g.V;
+        cx<double> a[12], b[12];
+        load_spinor(x + off, g.V, s, a);
+        load_spinor(y + off, g.V, s, b);
+        acc_dot(a, b, v[0], v[1]);
+        v[2] = acc_nrm(b);
+    }
+    write_partials<3>(v, part, ntiles, tr);
+}
+
+void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs) {
+    Timed t(e, 3, 0);
+    int nt = tiles_of(g.V);
+    k_dots<<<nt * nrhs, WG, 0, e.stream>>>(g, x, y, part, nrhs, nt);
+}
+
+// ------------------------------------------------------------------ instantiations
+#define INST(R)                                                                                                    \
+    template void launch_import<R>(Exec&, const Geom&, const void*, Traits<R>::word*, int, int);                  \
+    template void launch_export<R>(Exec&, const Geom&, const Traits<R>::word*, void*, int, int);                  \
+    template void launch_dslash<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,              \
+                                   const Traits<R>::word*, Traits<R>::word*, int, int, double);                   \
+    template void launch_dslash_dot<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,          \
+                                       const Traits<R>::word*, Traits<R>::word*, const Traits<R>::word*, double*, \
+                                       int, int, double);                                                         \
+    template void launch_dslash_dot2<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,         \
+                                        const Traits<R>::word*, Traits<R>::word*, double*, int, int, double);     \
+    template void launch_residual<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,            \
+                                     const Traits<R>::word*, const Traits<R>::word*, Traits<R>::word*, double*,   \
+                                     int, int, double);                                                           \
+    template void launch_hop<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, Traits<R>::word*, int,  \
+                                int);                                                                             \
+    template void launch_bicg_init<R>(Exec&, const Geom&, const double2*, const double*, Traits<R>::word*,        \
+                                      Traits<R>::word*, Traits<R>::word*, Traits<R>::word*, double*, int);        \
+    template void launch_bicg_s<R>(Exec&, const Geom&, const BiState*, const Traits<R>::word*,                    \
+                                   const Traits<R>::word*, Traits<R>::word*, int);                                \
+    template void launch_bicg_xr<R>(Exec&, const Geom&, const BiState*, Traits<R>::word*, const Traits<R>::word*, \
+                                    const Traits<R>::word*, const Traits<R>::word*, const Traits<R>::word*,       \
+                                    Traits<R>::word*, double*, int);                                              \
+    template void launch_bicg_p<R>(Exec&, const Geom&, const BiState*, const Traits<R>::word*,                    \
+                                   const Traits<R>::word*, Traits<R>::word*, int);                                \
+    template void launch_accumulate<R>(Exec&, const Geom&, const Traits<R>::word*, const double*, double2*, int);
+
+INST(double)
+INST(float)
+
+}  // namespace ddwc

@@ -182,22 +182,12 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     }
     if (V * 12 * 16 > ((long long)1 << 40) || V > (1 << 30)) return fail(DDWC_EINVAL, "lattice too large");
     ddwc_ctx* C = new ddwc_ctx();
-    Geom& g = C->g;
+    C->g = make_geom(lat, blk, time_bc);
+    const Geom& g = C->g;
     for (int mu = 0; mu < 4; ++mu) {
-        g.L[mu] = C->lat[mu] = lat[mu];
-        g.b[mu] = C->blk[mu] = blk[mu];
-        g.nb[mu] = lat[mu] / blk[mu];
+        C->lat[mu] = lat[mu];
+        C->blk[mu] = blk[mu];
     }
-    g.lstr[3] = 1;
-    g.lstr[2] = g.b[3];
-    g.lstr[1] = g.b[3] * g.b[2];
-    g.lstr[0] = g.b[3] * g.b[2] * g.b[1];
-    g.V = (int)V;
-    g.Vb = g.b[0] * g.b[1] * g.b[2] * g.b[3];
-    g.NB = g.V / g.Vb;
-    g.NBc = g.NB / 2;
-    g.nb3h = g.nb[3] / 2;
-    g.tbc = time_bc;
     C->csw = c_sw;
     hipError_t e0 = hipGetDevice(&C->device);
     size_t n = (size_t)4 * 9 * g.V;

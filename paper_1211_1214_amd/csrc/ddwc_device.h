@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#define DDWC_HD __host__ __device__ __forceinline__
+
 namespace ddwc {
 
 template <class R>
@@ -27,32 +29,32 @@ struct cx {
 };
 
 template <class R>
-__device__ __forceinline__ cx<R> mk(R a, R b) {
+DDWC_HD cx<R> mk(R a, R b) {
     cx<R> z;
     z.re = a;
     z.im = b;
     return z;
 }
 template <class R>
-__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+DDWC_HD cx<R> operator+(cx<R> a, cx<R> b) { return mk(a.re + b.re, a.im + b.im); }
 template <class R>
-__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+DDWC_HD cx<R> operator-(cx<R> a, cx<R> b) { return mk(a.re - b.re, a.im - b.im); }
 template <class R>
-__device__ __forceinline__ cx<R> operator-(cx<R> a) { return mk(-a.re, -a.im); }
+DDWC_HD cx<R> operator-(cx<R> a) { return mk(-a.re, -a.im); }
 template <class R>
-__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+DDWC_HD cx<R> operator*(cx<R> a, cx<R> b) {
     return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
 }
 template <class R>
-__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return mk(s * a.re, s * a.im); }
+DDWC_HD cx<R> operator*(R s, cx<R> a) { return mk(s * a.re, s * a.im); }
 template <class R>
-__device__ __forceinline__ cx<R> conj_mul(cx<R> a, cx<R> b) {  // conj(a) * b
+DDWC_HD cx<R> conj_mul(cx<R> a, cx<R> b) {  // conj(a) * b
     return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
 template <class R>
-__device__ __forceinline__ cx<R> times_i(cx<R> a) { return mk(-a.im, a.re); }
+DDWC_HD cx<R> times_i(cx<R> a) { return mk(-a.im, a.re); }
 template <class R>
-__device__ __forceinline__ cx<R> times_mi(cx<R> a) { return mk(a.im, -a.re); }
+DDWC_HD cx<R> times_mi(cx<R> a) { return mk(a.im, -a.re); }
 
 // ------------------------------------------------------------------ geometry
 struct Geom {
@@ -64,13 +66,34 @@ struct Geom {
     int tbc;       // time boundary factor (-1 antiperiodic, +1 periodic)
 };
 
+// Geometry of a T x L1 x L2 x L3 lattice split into blocks blk (extents already validated).
+inline Geom make_geom(const int lat[4], const int blk[4], int time_bc) {
+    Geom g;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = lat[mu];
+        g.b[mu] = blk[mu];
+        g.nb[mu] = lat[mu] / blk[mu];
+    }
+    g.lstr[3] = 1;
+    g.lstr[2] = g.b[3];
+    g.lstr[1] = g.b[3] * g.b[2];
+    g.lstr[0] = g.b[3] * g.b[2] * g.b[1];
+    g.V = lat[0] * lat[1] * lat[2] * lat[3];
+    g.Vb = g.b[0] * g.b[1] * g.b[2] * g.b[3];
+    g.NB = g.V / g.Vb;
+    g.NBc = g.NB / 2;
+    g.nb3h = g.nb[3] / 2;
+    g.tbc = time_bc;
+    return g;
+}
+
 struct Site {
     int l[4];  // coordinates inside the block
     int n[4];  // block coordinates
     int c;     // colour
 };
 
-__device__ __forceinline__ Site decode(const Geom& g, int s) {
+DDWC_HD Site decode(const Geom& g, int s) {
     Site S;
     int loc = s % g.Vb;
     int B = s / g.Vb;
@@ -92,13 +115,13 @@ __device__ __forceinline__ Site decode(const Geom& g, int s) {
     return S;
 }
 
-__device__ __forceinline__ int block_base(const Geom& g, const int n[4]) {
+DDWC_HD int block_base(const Geom& g, const int n[4]) {
     int c = (n[0] + n[1] + n[2] + n[3]) & 1;
     int r = ((n[0] * g.nb[1] + n[1]) * g.nb[2] + n[2]) * g.nb3h + (n[3] >> 1);
     return (c * g.NBc + r) * g.Vb;
 }
 
-__device__ __forceinline__ int local_index(const Geom& g, const int l[4]) {
+DDWC_HD int local_index(const Geom& g, const int l[4]) {
     return ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
 }
 
@@ -106,7 +129,7 @@ __device__ __forceinline__ int local_index(const Geom& g, const int l[4]) {
 // Sets inside = whether it lies in the same Schwarz block, and bc = the
 // time-boundary factor of the hop.
 template <int DIR>
-__device__ __forceinline__ int neighbour(const Geom& g, int s, const Site& S, int mu, bool& inside, int& bc) {
+DDWC_HD int neighbour(const Geom& g, int s, const Site& S, int mu, bool& inside, int& bc) {
     bc = 1;
     if (DIR > 0) {
         if (S.l[mu] < g.b[mu] - 1) {
@@ -142,7 +165,7 @@ __device__ __forceinline__ int neighbour(const Geom& g, int s, const Site& S, in
 }
 
 // The black face sites: range of the projector P.
-__device__ __forceinline__ bool in_P(const Geom& g, const Site& S) {
+DDWC_HD bool in_P(const Geom& g, const Site& S) {
     if (S.c != 0) return false;
     for (int mu = 0; mu < 4; ++mu)
         if (S.l[mu] == 0 || S.l[mu] == g.b[mu] - 1) return true;
@@ -150,7 +173,7 @@ __device__ __forceinline__ bool in_P(const Geom& g, const Site& S) {
 }
 
 // Lexicographic (canonical) site index of a decoded internal site.
-__device__ __forceinline__ int canonical_index(const Geom& g, const Site& S) {
+DDWC_HD int canonical_index(const Geom& g, const Site& S) {
     int x[4];
     for (int mu = 0; mu < 4; ++mu) x[mu] = S.n[mu] * g.b[mu] + S.l[mu];
     return ((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
@@ -173,14 +196,14 @@ struct Traits<float> {
     static constexpr int NKW = 18;
 };
 
-__device__ __forceinline__ void load_spinor(const double2* __restrict__ f, int V, int s, cx<double> p[12]) {
+DDWC_HD void load_spinor(const double2* __restrict__ f, int V, int s, cx<double> p[12]) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         double2 w = f[(size_t)c * V + s];
         p[c] = mk(w.x, w.y);
     }
 }
-__device__ __forceinline__ void load_spinor(const float4* __restrict__ f, int V, int s, cx<float> p[12]) {
+DDWC_HD void load_spinor(const float4* __restrict__ f, int V, int s, cx<float> p[12]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         float4 w = f[(size_t)k * V + s];
@@ -188,18 +211,18 @@ __device__ __forceinline__ void load_spinor(const float4* __restrict__ f, int V,
         p[2 * k + 1] = mk(w.z, w.w);
     }
 }
-__device__ __forceinline__ void store_spinor(double2* __restrict__ f, int V, int s, const cx<double> p[12]) {
+DDWC_HD void store_spinor(double2* __restrict__ f, int V, int s, const cx<double> p[12]) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) f[(size_t)c * V + s] = make_double2(p[c].re, p[c].im);
 }
-__device__ __forceinline__ void store_spinor(float4* __restrict__ f, int V, int s, const cx<float> p[12]) {
+DDWC_HD void store_spinor(float4* __restrict__ f, int V, int s, const cx<float> p[12]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k)
         f[(size_t)k * V + s] = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
 }
 
 template <class R>
-__device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int V, int mu, int s, cx<R> u[9]) {
+DDWC_HD void load_link(const cx<R>* __restrict__ U, int V, int mu, int s, cx<R> u[9]) {
     const cx<R>* base = U + (size_t)mu * 9 * V + s;
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = base[(size_t)k * V];
@@ -207,7 +230,7 @@ __device__ __forceinline__ void load_link(const cx<R>* __restrict__ U, int V, in
 
 // The 36 reals of chiral block `blk` of the clover term at site s:
 // d[0..5] = diagonal, o[0..29] = upper off-diagonal (re, im) in row order.
-__device__ __forceinline__ void load_clover_block(const double2* __restrict__ K, int V, int s, int blk, double d[6],
+DDWC_HD void load_clover_block(const double2* __restrict__ K, int V, int s, int blk, double d[6],
                                                   double o[30]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -224,7 +247,7 @@ __device__ __forceinline__ void load_clover_block(const double2* __restrict__ K,
 }
 // FP32: reals 0..11 are words 0..2; block 0 off-diagonal reals 12..41 start in word 3,
 // block 1 reals 42..71 start at word 10 offset 2.  Load the 9 words that cover a block.
-__device__ __forceinline__ void load_clover_block(const float4* __restrict__ K, int V, int s, int blk, float d[6],
+DDWC_HD void load_clover_block(const float4* __restrict__ K, int V, int s, int blk, float d[6],
                                                   float o[30]) {
     float w[40];
     const int w0 = blk == 0 ? 3 : 10;  // first word holding off-diagonal reals of this block
@@ -249,9 +272,17 @@ __device__ __forceinline__ void load_clover_block(const float4* __restrict__ K, 
     }
 }
 
+// Keeps the instruction scheduler from hoisting the next direction's loads above the
+// current direction's arithmetic (which would hold all eight neighbours in registers).
+DDWC_HD void sched_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // y = (4 + m) psi + C psi with the two packed Hermitian 6x6 blocks, one block at a time.
 template <class R>
-__device__ __forceinline__ void apply_diag(const typename Traits<R>::word* __restrict__ K, int V, int s, R mass4,
+DDWC_HD void apply_diag(const typename Traits<R>::word* __restrict__ K, int V, int s, R mass4,
                                            const cx<R> p[12], cx<R> y[12]) {
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
@@ -272,66 +303,76 @@ __device__ __forceinline__ void apply_diag(const typename Traits<R>::word* __res
                 ++k;
             }
         }
+        sched_fence();
     }
 }
 
-// acc += (1 - g_mu) U psi_nb (DIR = +1) or (1 + g_mu) U^+ psi_nb (DIR = -1), chiral basis,
-// through the spin-projected half spinor h (2 spins x 3 colours).
-template <class R, int DIR>
-__device__ __forceinline__ void hop_accumulate(int mu, const cx<R> u[9], const cx<R> q[12], R fac, cx<R> acc[12]) {
-    cx<R> h[2][3];
+// Spin structure of the hop terms in the chiral basis.  With q the neighbour spinor
+// (spins 0..3), the projected half spinor of (1 - dir g_mu) q is
+//     h0 = q0 + dir a0 q[i0],   h1 = q1 + dir a1 q[5 - i0],
+// and after k = U h (forward) or U^+ h (backward) the four spins of the hop are
+//     (k0, k1, dir b0 k[j0], dir b1 k[1 - j0]).
+// a0, a1, b0, b1 are in {+-1, +-i}; the backward (1 + g_mu) terms only flip their sign.
+struct HopSpin {
+    int i0, j0;
+    float a0r, a0i, a1r, a1i, b0r, b0i, b1r, b1i;
+};
+
+DDWC_HD HopSpin hop_spin(int mu) {
+    HopSpin h;
+    switch (mu) {
+        case 0: h = HopSpin{2, 0, 1, 0, 1, 0, 1, 0, 1, 0}; break;     // h = q_u + q_l,          l = k
+        case 1: h = HopSpin{3, 1, 0, 1, 0, 1, 0, -1, 0, -1}; break;   // h = q_u + i s1 q_l,     l = -i s1 k
+        case 2: h = HopSpin{3, 1, 1, 0, -1, 0, -1, 0, 1, 0}; break;   // h = q_u + i s2 q_l,     l = -i s2 k
+        default: h = HopSpin{2, 0, 0, 1, 0, -1, 0, -1, 0, 1}; break;  // h = q_u + i s3 q_l,     l = -i s3 k
+    }
+    return h;
+}
+
+template <class R>
+DDWC_HD cx<R> cscale(float re, float im, cx<R> z) {
+    return mk((R)re * z.re - (R)im * z.im, (R)re * z.im + (R)im * z.re);
+}
+
+// acc += fac * (1 - dir g_mu) W q, W = U (dir = +1) or U^+ (dir = -1).
+template <class R>
+DDWC_HD void hop_accumulate(int mu, int dir, const cx<R> u[9], const cx<R> q[12], R fac, cx<R> acc[12]) {
+    const HopSpin hs = hop_spin(mu);
+    const R sg = (R)dir;
+    cx<R> h0[3], h1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const cx<R> p0 = q[a], p1 = q[3 + a], p2 = q[6 + a], p3 = q[9 + a];
-        if (mu == 0) {
-            if (DIR > 0) { h[0][a] = p0 + p2; h[1][a] = p1 + p3; }
-            else         { h[0][a] = p0 - p2; h[1][a] = p1 - p3; }
-        } else if (mu == 1) {
-            if (DIR > 0) { h[0][a] = p0 + times_i(p3); h[1][a] = p1 + times_i(p2); }
-            else         { h[0][a] = p0 - times_i(p3); h[1][a] = p1 - times_i(p2); }
-        } else if (mu == 2) {
-            if (DIR > 0) { h[0][a] = p0 + p3; h[1][a] = p1 - p2; }
-            else         { h[0][a] = p0 - p3; h[1][a] = p1 + p2; }
-        } else {
-            if (DIR > 0) { h[0][a] = p0 + times_i(p2); h[1][a] = p1 - times_i(p3); }
-            else         { h[0][a] = p0 - times_i(p2); h[1][a] = p1 + times_i(p3); }
-        }
+        const cx<R> x0 = hs.i0 == 2 ? q[6 + a] : q[9 + a];
+        const cx<R> x1 = hs.i0 == 2 ? q[9 + a] : q[6 + a];
+        h0[a] = q[a] + sg * cscale(hs.a0r, hs.a0i, x0);
+        h1[a] = q[3 + a] + sg * cscale(hs.a1r, hs.a1i, x1);
     }
-    cx<R> k[2][3];
+    cx<R> w[9];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cx<R> t;
-            if (DIR > 0) {
-                t = u[3 * a] * h[s][0] + u[3 * a + 1] * h[s][1] + u[3 * a + 2] * h[s][2];
-            } else {
-                t = conj_mul(u[a], h[s][0]) + conj_mul(u[3 + a], h[s][1]) + conj_mul(u[6 + a], h[s][2]);
-            }
-            k[s][a] = fac * t;
-        }
+        for (int b = 0; b < 3; ++b) w[3 * a + b] = dir > 0 ? u[3 * a + b] : mk(u[3 * b + a].re, -u[3 * b + a].im);
+    cx<R> k0[3], k1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        k0[a] = fac * (w[3 * a] * h0[0] + w[3 * a + 1] * h0[1] + w[3 * a + 2] * h0[2]);
+        k1[a] = fac * (w[3 * a] * h1[0] + w[3 * a + 1] * h1[1] + w[3 * a + 2] * h1[2]);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        acc[a] = acc[a] + k[0][a];
-        acc[3 + a] = acc[3 + a] + k[1][a];
-        cx<R> l0, l1;
-        if (mu == 0) {
-            if (DIR > 0) { l0 = k[0][a]; l1 = k[1][a]; }
-            else         { l0 = -k[0][a]; l1 = -k[1][a]; }
-        } else if (mu == 1) {
-            if (DIR > 0) { l0 = times_mi(k[1][a]); l1 = times_mi(k[0][a]); }
-            else         { l0 = times_i(k[1][a]); l1 = times_i(k[0][a]); }
-        } else if (mu == 2) {
-            if (DIR > 0) { l0 = -k[1][a]; l1 = k[0][a]; }
-            else         { l0 = k[1][a]; l1 = -k[0][a]; }
-        } else {
-            if (DIR > 0) { l0 = times_mi(k[0][a]); l1 = times_i(k[1][a]); }
-            else         { l0 = times_i(k[0][a]); l1 = times_mi(k[1][a]); }
-        }
-        acc[6 + a] = acc[6 + a] + l0;
-        acc[9 + a] = acc[9 + a] + l1;
+        acc[a] = acc[a] + k0[a];
+        acc[3 + a] = acc[3 + a] + k1[a];
+        const cx<R> y0 = hs.j0 == 0 ? k0[a] : k1[a];
+        const cx<R> y1 = hs.j0 == 0 ? k1[a] : k0[a];
+        acc[6 + a] = acc[6 + a] + sg * cscale(hs.b0r, hs.b0i, y0);
+        acc[9 + a] = acc[9 + a] + sg * cscale(hs.b1r, hs.b1i, y1);
     }
+}
+
+// Neighbour one step in direction dir (+1 / -1) along mu: index, same-block flag, and the
+// time-boundary factor of the hop.
+DDWC_HD int neighbour_rt(const Geom& g, int s, const Site& S, int mu, int dir, bool& inside, int& bc) {
+    return dir > 0 ? neighbour<+1>(g, s, S, mu, inside, bc) : neighbour<-1>(g, s, S, mu, inside, bc);
 }
 
 // Which hops a site operator includes.
@@ -341,7 +382,7 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // The diagonal part is applied first; the hops then accumulate into y with the factor
 // -1/2 (times the time-boundary sign) folded into the half-spinor products.
 template <class R, bool DIAG, int HOPS>
-__device__ __forceinline__ void site_operator(const Geom& g, int s, const typename Traits<R>::word* __restrict__ in,
+DDWC_HD void site_operator(const Geom& g, int s, const typename Traits<R>::word* __restrict__ in,
                                               const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
                                               R mass4, cx<R> y[12]) {
     const int V = g.V;
@@ -349,37 +390,26 @@ __device__ __forceinline__ void site_operator(const Geom& g, int s, const typena
         cx<R> c[12];
         load_spinor(in, V, s, c);
         apply_diag<R>(K, V, s, mass4, c, y);
+        sched_fence();
     } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) y[c] = mk(R(0), R(0));
     }
     if (HOPS != HOPS_NONE) {
-        Site S = decode(g, s);
+        const Site S = decode(g, s);
+        // one direction per trip: only one neighbour spinor and link are live at a time
 #pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
-            {
-                bool inside;
-                int bc;
-                int t = neighbour<+1>(g, s, S, mu, inside, bc);
-                bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
-                if (take) {
-                    cx<R> q[12], u[9];
-                    load_spinor(in, V, t, q);
-                    load_link(U, V, mu, s, u);
-                    hop_accumulate<R, +1>(mu, u, q, R(-0.5) * R(bc), y);
-                }
-            }
-            {
-                bool inside;
-                int bc;
-                int t = neighbour<-1>(g, s, S, mu, inside, bc);
-                bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
-                if (take) {
-                    cx<R> q[12], u[9];
-                    load_spinor(in, V, t, q);
-                    load_link(U, V, mu, t, u);
-                    hop_accumulate<R, -1>(mu, u, q, R(-0.5) * R(bc), y);
-                }
+        for (int d = 0; d < 8; ++d) {
+            const int mu = d >> 1, dir = (d & 1) ? -1 : 1;
+            bool inside;
+            int bc;
+            const int t = neighbour_rt(g, s, S, mu, dir, inside, bc);
+            const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+            if (take) {
+                cx<R> q[12], u[9];
+                load_spinor(in, V, t, q);
+                load_link(U, V, mu, dir > 0 ? s : t, u);
+                hop_accumulate<R>(mu, dir, u, q, R(-0.5) * R(bc), y);
             }
         }
     }
@@ -413,7 +443,7 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
 
 // ------------------------------------------------------------------ per-site dot products (FP64 accumulate)
 template <class R>
-__device__ __forceinline__ void acc_dot(const cx<R> a[12], const cx<R> b[12], double& re, double& im) {
+DDWC_HD void acc_dot(const cx<R> a[12], const cx<R> b[12], double& re, double& im) {
     // (a, b) = sum conj(a) b
     R sr = 0, si = 0;
 #pragma unroll
@@ -426,7 +456,7 @@ __device__ __forceinline__ void acc_dot(const cx<R> a[12], const cx<R> b[12], do
 }
 
 template <class R>
-__device__ __forceinline__ double acc_nrm(const cx<R> a[12]) {
+DDWC_HD double acc_nrm(const cx<R> a[12]) {
     R s = 0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) s += a[c].re * a[c].re + a[c].im * a[c].im;

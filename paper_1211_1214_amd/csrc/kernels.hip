@@ -7,10 +7,12 @@
 // links and clover in that XCD's L2, and face neighbours of consecutive Schwarz
 // blocks stay in the same L2.
 #include "ddwc_internal.h"
+#include "clover_build.h"
 
 namespace ddwc {
 
-#define HIPCHECK_LAUNCH() (void)hipGetLastError()
+// Operator kernels are memory bound: ask for at least 4 waves per SIMD (<= 128 VGPRs).
+#define DDWC_OCC
 
 __device__ __forceinline__ int xcd_remap(int i, int n) {
     if ((n & 7) != 0) return i;
@@ -63,104 +65,13 @@ void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* 
     k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32);
 }
 
-// Neighbour of an arbitrary internal site (decodes it first).
-template <int DIR>
-__device__ int step(const Geom& g, int s, int mu) {
-    Site S = decode(g, s);
-    bool in;
-    int bc;
-    return neighbour<DIR>(g, s, S, mu, in, bc);
-}
-
-struct M3 {
-    cx<double> a[9];
-};
-
-__device__ M3 ld(const cx<double>* U, const Geom& g, int mu, int s) {
-    M3 m;
-    for (int k = 0; k < 9; ++k) m.a[k] = U[((size_t)mu * 9 + k) * g.V + s];
-    return m;
-}
-__device__ M3 mul(const M3& x, const M3& y) {
-    M3 z;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            cx<double> t = mk(0.0, 0.0);
-            for (int k = 0; k < 3; ++k) t = t + x.a[3 * i + k] * y.a[3 * k + j];
-            z.a[3 * i + j] = t;
-        }
-    return z;
-}
-__device__ M3 dag(const M3& x) {
-    M3 z;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) z.a[3 * i + j] = mk(x.a[3 * j + i].re, -x.a[3 * j + i].im);
-    return z;
-}
-
-// Fhat_{mu nu}(s) = (Q - Q^+)/8 from the four plaquette leaves at s (no boundary signs).
-__device__ M3 field_strength(const Geom& g, const cx<double>* U, int s, int mu, int nu) {
-    int xpm = step<+1>(g, s, mu), xpn = step<+1>(g, s, nu);
-    int xmm = step<-1>(g, s, mu), xmn = step<-1>(g, s, nu);
-    int xmm_pn = step<+1>(g, xmm, nu), xmm_mn = step<-1>(g, xmm, nu), xpm_mn = step<-1>(g, xpm, nu);
-    M3 q1 = mul(mul(ld(U, g, mu, s), ld(U, g, nu, xpm)), mul(dag(ld(U, g, mu, xpn)), dag(ld(U, g, nu, s))));
-    M3 q2 = mul(mul(ld(U, g, nu, s), dag(ld(U, g, mu, xmm_pn))), mul(dag(ld(U, g, nu, xmm)), ld(U, g, mu, xmm)));
-    M3 q3 = mul(mul(dag(ld(U, g, mu, xmm)), dag(ld(U, g, nu, xmm_mn))), mul(ld(U, g, mu, xmm_mn), ld(U, g, nu, xmn)));
-    M3 q4 = mul(mul(dag(ld(U, g, nu, xmn)), ld(U, g, mu, xmn)), mul(ld(U, g, nu, xpm_mn), dag(ld(U, g, mu, s))));
-    M3 F;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            cx<double> q = q1.a[3 * i + j] + q2.a[3 * i + j] + q3.a[3 * i + j] + q4.a[3 * i + j];
-            cx<double> qt = q1.a[3 * j + i] + q2.a[3 * j + i] + q3.a[3 * j + i] + q4.a[3 * j + i];
-            F.a[3 * i + j] = mk((q.re - qt.re) / 8.0, (q.im + qt.im) / 8.0);
-        }
-    return F;
-}
-
-// Clover term in the chiral basis: sigma_{0k} = diag(s_k, -s_k), sigma_{jk} = -eps_{jkl} diag(s_l, s_l),
-// so C = (i c_sw / 2) sum_l diag(s_l x E_l, s_l x E'_l) with
-// E = (F01 - F23, F02 + F13, F03 - F12), E' = -(F01 + F23, F02 - F13, F03 + F12).
+// Clover term at every site (setup, once per gauge field).
 __global__ void k_clover_build(Geom g, const cx<double>* __restrict__ U, double csw, double2* __restrict__ K64,
                                float4* __restrict__ K32) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    M3 F01 = field_strength(g, U, s, 0, 1), F02 = field_strength(g, U, s, 0, 2), F03 = field_strength(g, U, s, 0, 3);
-    M3 F12 = field_strength(g, U, s, 1, 2), F13 = field_strength(g, U, s, 1, 3), F23 = field_strength(g, U, s, 2, 3);
     double a[72];
-    for (int blk = 0; blk < 2; ++blk) {
-        double sg = blk == 0 ? 1.0 : -1.0;
-        M3 E1, E2, E3;
-        for (int k = 0; k < 9; ++k) {
-            if (blk == 0) {
-                E1.a[k] = F01.a[k] - F23.a[k];
-                E2.a[k] = F02.a[k] + F13.a[k];
-                E3.a[k] = F03.a[k] - F12.a[k];
-            } else {
-                E1.a[k] = -(F01.a[k] + F23.a[k]);
-                E2.a[k] = -(F02.a[k] - F13.a[k]);
-                E3.a[k] = -(F03.a[k] + F12.a[k]);
-            }
-        }
-        (void)sg;
-        cx<double> M[6][6];
-        const cx<double> ic2 = mk(0.0, 0.5 * csw);
-        for (int a1 = 0; a1 < 3; ++a1)
-            for (int b1 = 0; b1 < 3; ++b1) {
-                int k = 3 * a1 + b1;
-                M[a1][b1] = ic2 * E3.a[k];
-                M[3 + a1][3 + b1] = -(ic2 * E3.a[k]);
-                M[a1][3 + b1] = ic2 * (E1.a[k] - times_i(E2.a[k]));
-                M[3 + a1][b1] = ic2 * (E1.a[k] + times_i(E2.a[k]));
-            }
-        for (int i = 0; i < 6; ++i) a[6 * blk + i] = M[i][i].re;
-        int k = 0;
-        for (int i = 0; i < 6; ++i)
-            for (int j = i + 1; j < 6; ++j) {
-                a[12 + 30 * blk + 2 * k] = M[i][j].re;
-                a[12 + 30 * blk + 2 * k + 1] = M[i][j].im;
-                ++k;
-            }
-    }
+    clover_site(g, U, csw, s, a);
     for (int k = 0; k < 36; ++k) K64[(size_t)k * g.V + s] = make_double2(a[2 * k], a[2 * k + 1]);
     for (int k = 0; k < 18; ++k)
         K32[(size_t)k * g.V + s] = make_float4((float)a[4 * k], (float)a[4 * k + 1], (float)a[4 * k + 2], (float)a[4 * k + 3]);
@@ -226,7 +137,7 @@ void launch_export(Exec& e, const Geom& g, const typename Traits<R>::word* in, v
 enum Epi { EPI_NONE = 0, EPI_DOT = 1, EPI_DOT2 = 2, EPI_RESID = 3 };
 
 template <class R, int EPI>
-__global__ __launch_bounds__(WG) void k_dslash(Geom g, const cx<R>* __restrict__ U,
+__global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __restrict__ U,
                                                const typename Traits<R>::word* __restrict__ K, R mass4,
                                                const typename Traits<R>::word* __restrict__ in,
                                                typename Traits<R>::word* __restrict__ out,
@@ -299,7 +210,7 @@ void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Trai
 }
 
 template <class R>
-__global__ __launch_bounds__(WG) void k_hop(Geom g, const cx<R>* __restrict__ U,
+__global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __restrict__ U,
                                             const typename Traits<R>::word* __restrict__ in,
                                             typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;

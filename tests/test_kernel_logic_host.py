@@ -1,0 +1,80 @@
+"""The library's per-site device code (geometry, spin projection, clover build and
+application) executed on the host through tests/host/kernel_logic.cpp, against the
+FP64 oracle.  Needs hipcc but no GPU."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import dirac
+from oracle.schwarz import Schwarz
+from paper_1211_1214_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "host", "kernel_logic.cpp")
+LIB = os.path.join(HERE, "host", "libkernel_logic.so")
+
+
+@pytest.fixture(scope="module")
+def L():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    deps = [SRC] + [os.path.join(HERE, "..", "paper_1211_1214_amd", "csrc", f)
+                    for f in ("ddwc_device.h", "clover_build.h")]
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared", SRC,
+                               "-o", LIB + ".tmp"], stderr=subprocess.DEVNULL)
+        os.replace(LIB + ".tmp", LIB)
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    lib.host_apply.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_int, P, P]
+    return lib
+
+
+def run(L, lat, blk, tbc, csw, U, psi, kappa, mode, colour):
+    out = np.zeros_like(psi)
+    clov = np.zeros((int(np.prod(lat)), 72))
+    L.host_apply((ctypes.c_int * 4)(*lat), (ctypes.c_int * 4)(*blk), tbc, csw, U.ctypes.data, psi.ctypes.data,
+                 kappa, mode, colour, out.ctypes.data, clov.ctypes.data)
+    return out, clov
+
+
+@pytest.mark.parametrize("lat,blk,tbc", [((4, 4, 4, 4), (2, 2, 2, 2), -1), ((4, 6, 6, 6), (2, 3, 3, 3), -1),
+                                         ((8, 4, 2, 6), (2, 2, 1, 3), 1)])
+def test_host_operator_matches_oracle(L, lat, blk, tbc):
+    U = inputs.make_links(lat, 0.3, 3)
+    psi = inputs.make_spinor(lat, 4)
+    S = Schwarz(U, lat, blk, 1.0, tbc)
+    m = dirac.mass(0.121)
+    out, clov = run(L, lat, blk, tbc, 1.0, U, psi, 0.121, 0, 0)
+    want = dirac.apply(S.D(m), psi)
+    assert np.abs(out - want).max() < 1e-13 * np.abs(want).max()
+    for c in (0, 1):
+        out, _ = run(L, lat, blk, tbc, 1.0, U, psi, 0.121, 1, c)
+        assert np.abs(out - S.block_apply(c, m, psi)).max() < 1e-13 * np.abs(want).max()
+        out, _ = run(L, lat, blk, tbc, 1.0, U, psi, 0.121, 2, c)
+        hop = S.hop_wb(m, psi) if c == 1 else S.hop_bw(m, psi)
+        assert np.abs(out - hop).max() < 1e-13 * np.abs(want).max()
+
+
+def test_host_clover_packing(L):
+    """The 72 packed reals reproduce the oracle's 12x12 clover term in its two chiral blocks."""
+    lat, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = inputs.make_links(lat, 0.3, 5)
+    _, clov = run(L, lat, blk, -1, 1.3, U, inputs.make_spinor(lat, 1), 0.12, 0, 0)
+    C = dirac.clover_term(U, lat, 1.3)
+    for x in (0, 17, 255):
+        for b in range(2):
+            A = np.zeros((6, 6), complex)
+            A[np.diag_indices(6)] = clov[x, 6 * b:6 * b + 6]
+            off = clov[x, 12 + 30 * b:42 + 30 * b].reshape(15, 2)
+            iu = np.triu_indices(6, 1)
+            A[iu] = off[:, 0] + 1j * off[:, 1]
+            A[(iu[1], iu[0])] = np.conj(A[iu])
+            assert np.abs(A - C[x][6 * b:6 * b + 6, 6 * b:6 * b + 6]).max() < 1e-15
+        assert np.abs(C[x][:6, 6:]).max() == 0

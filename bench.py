@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""Benchmark: Schwarz-factorised two-flavour determinant-ratio estimates per second on MI355X.
+
+One step = one pass of the whole hot path over one batch: the Schur-complement
+estimator of Eq. (8) on the 48x24^3 lattice with 6^4 Schwarz blocks, all 12 noise
+vectors of the step as one multi-RHS batch: D_wb hop, four persistent block sweeps,
+D_bw hops, projector, one global mixed-precision solve (FP32 BiCGStab inside FP64
+defect correction), the FP64 reductions for x_ij and the log-domain combination.
+Inputs (synthetic links, complex Gaussian noise) are resident in HBM before timing.
+
+Also measured: the plain FP64 single-RHS GPU path on the same noise vectors, the
+agreement of both with the FP64 oracle, the dominant kernel's HBM roofline from HIP
+events over the timed region, and the C oracle timed on a bounded CPU sample.
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "Dslash GB/s (% HBM peak); det-ratio estimates/s, mixed vs FP64 at 1e-8"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
+    ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the estimates of Eq. (8) "
+              "are independent, so several GPUs would each run their own noise vectors).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1211_1214_amd as dd
+    from paper_1211_1214_amd import inputs
+
+    cfg = inputs.CONFIGS[3]
+    lat, blk, nhit = cfg["lat"], cfg["blk"], cfg["n_hit"]
+    k1, k2 = cfg["kappa1"], cfg["kappa2"]
+    dev = torch.device("cuda:0")
+    t = time.time()
+    U = inputs.make_links(lat, cfg["eps"], 3)
+    eta = inputs.make_noise_batch(lat, 3, 1, nhit)
+    log(f"inputs generated in {time.time() - t:.1f}s")
+    Ud = torch.from_numpy(U).to(dev)
+    etad = torch.from_numpy(eta).to(dev)
+    ctx = dd.Context(Ud, lat, blk, -1, cfg["csw"])
+    torch.cuda.synchronize()
+
+    def step():
+        return ctx.det_ratio_estimate(k1, k2, etad, op=dd.OP_SCHUR, tol=args.tol, prec=dd.MIXED32)
+
+    for w in range(args.warmup):
+        r = step()
+        log(f"warmup {w}: log W_gl {r['log_w_gl']:.10f}, {r['stats']}")
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step()
+        log(f"step {k}: log W_gl {r['log_w_gl']:.10f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {name: ctx.profile_read(kc) for name, kc in
+            (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32),
+             ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER))}
+    ctx.profile_enable(False)
+    elapsed = t1 - t0
+    value = nhit * args.steps / elapsed
+    x_mixed = r["x"][0]
+    log(f"timed {args.steps} steps in {elapsed:.3f}s: {value:.2f} estimates/s; profile {prof}")
+
+    # FP64 single-RHS path on the first noise vectors
+    fp64_t = 0.0
+    x64 = []
+    for j in range(args.fp64_samples):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r64 = ctx.det_ratio_estimate(k1, k2, etad[:, j:j + 1].contiguous(), op=dd.OP_SCHUR, tol=args.tol,
+                                     prec=dd.FP64)
+        torch.cuda.synchronize()
+        fp64_t += time.perf_counter() - ta
+        x64.append(r64["x"][0, 0])
+    fp64_rate = args.fp64_samples / fp64_t if args.fp64_samples else None
+
+    # parity against the stored oracle exponents (written by tests/golden/make_c3_golden.py)
+    parity = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    if golden:
+        for j, xo in golden["x_schur"].items():
+            j = int(j)
+            parity[f"x{j}_mixed_rel"] = abs(x_mixed[j] - xo) / max(abs(xo), 1.0)
+            if j < len(x64):
+                parity[f"x{j}_fp64_rel"] = abs(x64[j] - xo) / max(abs(xo), 1.0)
+    d = max((abs(x_mixed[j] - x64[j]) / max(abs(x64[j]), 1.0) for j in range(len(x64))), default=None)
+    parity["x_mixed_vs_fp64_rel_max"] = d
+
+    # roofline of the dominant kernel class (live HIP-event durations over the timed region)
+    dom = max(("dslash32", "block", "dslash64", "blas"), key=lambda k: prof[k]["ms"])
+    pd = prof[dom]
+    per_launch_ms = pd["ms"] / max(pd["launches"], 1)
+    per_launch_bytes = pd["bytes"] / max(pd["launches"], 1)
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
+    ds = prof["dslash32"]
+    dslash_gbs = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9 if ds["ms"] > 0 else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "launches": pd["launches"], "avg_launch_us": round(per_launch_ms * 1e3, 2),
+                "bytes_per_launch": per_launch_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
+        cpu = cpu_baseline(U, eta[0, 0], cfg, golden, args.cpu_cap)
+
+    total_ms = sum(p["ms"] for p in prof.values())
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
+        "config": {"workload": "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, "
+                               "kappa 0.1200->0.1205, N_hit=12 as one multi-RHS batch, FP32 block/inner "
+                               "solves + FP64 defect correction",
+                   "lattice": list(lat), "blocks": list(blk), "n_hit": nhit, "tol": args.tol},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "dslash32_gbs": None if dslash_gbs is None else round(dslash_gbs, 1),
+        "dslash32_frac": None if dslash_gbs is None else round(dslash_gbs / HBM_PEAK_GBS, 4),
+        "fp64_single_rhs_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 3),
+        "speedup_vs_fp64_single_rhs": None if not fp64_rate else round(value / fp64_rate, 2),
+        "parity": parity,
+        "log_w_gl": r["log_w_gl"],
+        "kernel_time_share": {k: round(p["ms"] / total_ms, 3) for k, p in prof.items()} if total_ms else None,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(U, eta0, cfg, golden, cap):
+    """The C oracle on a bounded sample: one Schur exponent with each of its five solves
+    capped at `cap` BiCGStab iterations; the per-iteration time of each solve times the
+    oracle's own iteration count for that solve (stored with the golden exponents) gives
+    the time of one estimate."""
+    from oracle import cref, dirac
+    t = time.time()
+    R = cref.CRef(U, cfg["lat"], cfg["blk"], cfg["csw"], -1)
+    setup = time.time() - t
+    m1, m2 = dirac.mass(cfg["kappa1"]), dirac.mass(cfg["kappa2"])
+    t = time.time()
+    _, iters, secs = R.exponent_recorded("schur", "diff", m1, m2, eta0, 1e-13, cap=cap)
+    wall = time.time() - t
+    full = golden["schur_solve_iterations"]
+    est = sum(s / max(i, 1) * f for s, i, f in zip(secs, iters, full)) + (wall - sum(secs))
+    R.close()
+    log(f"cpu sample: {wall:.1f}s (setup {setup:.1f}s), per-solve iters {iters} secs {secs}; "
+        f"one estimate ~ {est:.1f}s")
+    return {"value": round(1.0 / est, 5), "unit": "estimates/s", "cores": cref.CRef.threads(), "kind": "oracle",
+            "sample": f"one Schur exponent on the same 48x24^3 workload with each of its {len(iters)} BiCGStab "
+                      f"solves capped at {cap} iterations ({wall:.1f}s), scaled per solve by the oracle's own "
+                      f"iteration counts {full} for a full estimate (tests/golden/c3_oracle.json)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -276,6 +276,17 @@ static double nrm2(long n, const cplx *a) { return creal(dot(n, a, a)); }
 
 typedef void (*op_fn)(const ref_t *, int, double, const cplx *, cplx *);
 
+/*
+ * Optional bookkeeping of the solves done by ref_exponent, in call order: iterations and
+ * wall seconds of each, and an iteration cap applied to each solve (0 = none).  Used to
+ * time a bounded sample of one estimate.
+ */
+static int g_rec_on = 0, g_rec_n = 0, g_rec_cap = 0;
+static int g_rec_iters[16];
+static double g_rec_secs[16];
+
+#include <omp.h>
+
 static void op_full(const ref_t *h, int c, double m, const cplx *in, cplx *out) {
     (void)c;
     ref_dslash(h, m, in, out);
@@ -322,8 +333,21 @@ done:
     return ok ? it : -1;
 }
 
+static int recorded(const ref_t *h, op_fn A, int c, double m, const cplx *b, cplx *x, double tol, int maxit) {
+    if (!g_rec_on) return bicgstab(h, A, c, m, b, x, tol, maxit);
+    double t0 = omp_get_wtime();
+    int cap = g_rec_cap > 0 && g_rec_cap < maxit ? g_rec_cap : maxit;
+    int it = bicgstab(h, A, c, m, b, x, tol, cap);
+    if (g_rec_n < 16) {
+        g_rec_secs[g_rec_n] = omp_get_wtime() - t0;
+        g_rec_iters[g_rec_n] = it < 0 ? cap : it;
+        g_rec_n++;
+    }
+    return g_rec_cap > 0 && it < 0 ? cap : it;
+}
+
 int ref_solve(const ref_t *h, double m, const cplx *b, cplx *x, double tol, int maxit) {
-    return bicgstab(h, op_full, 0, m, b, x, tol, maxit);
+    return recorded(h, op_full, 0, m, b, x, tol, maxit);
 }
 
 int ref_block_solve(const ref_t *h, int colour, double m, const cplx *b, cplx *x, double tol, int maxit) {
@@ -331,10 +355,28 @@ int ref_block_solve(const ref_t *h, int colour, double m, const cplx *b, cplx *x
     cplx *bb = malloc(sizeof(cplx) * n);
     for (long s = 0; s < h->V; s++)
         for (int i = 0; i < 12; i++) bb[12 * s + i] = h->colour[s] == colour ? b[12 * s + i] : 0;
-    int it = bicgstab(h, ref_block_apply, colour, m, bb, x, tol, maxit);
+    int it = recorded(h, ref_block_apply, colour, m, bb, x, tol, maxit);
     free(bb);
     return it;
 }
+
+/* Start (cap >= 0) or read the solve record; returns the number of solves recorded. */
+int ref_record(int on, int cap, int *iters, double *secs) {
+    if (on) {
+        g_rec_on = 1;
+        g_rec_cap = cap;
+        g_rec_n = 0;
+        return 0;
+    }
+    g_rec_on = 0;
+    for (int k = 0; k < g_rec_n; k++) {
+        if (iters) iters[k] = g_rec_iters[k];
+        if (secs) secs[k] = g_rec_secs[k];
+    }
+    return g_rec_n;
+}
+
+int ref_threads(void) { return omp_get_max_threads(); }
 
 static void mask_P(const ref_t *h, const cplx *in, cplx *out) {
     for (long s = 0; s < h->V; s++)

@@ -52,6 +52,9 @@ def _load():
         L.ref_schur_inverse.restype = I
         L.ref_exponent.argtypes = [P, I, I, D, D, P, D, ctypes.POINTER(ctypes.c_double)]
         L.ref_exponent.restype = I
+        L.ref_record.argtypes = [I, I, P, P]
+        L.ref_record.restype = I
+        L.ref_threads.restype = I
         _lib = L
     return _lib
 
@@ -136,6 +139,23 @@ class CRef:
         if self.L.ref_schur_inverse(self.h, float(m), phi.ctypes.data, out.ctypes.data, float(tol)):
             raise RuntimeError("C oracle solve did not converge")
         return out
+
+    def exponent_recorded(self, op, form, m1, m2, eta, tol=1e-13, cap=0):
+        """exponent() with the solves' iterations and seconds recorded (each capped at `cap`
+        iterations when cap > 0, which gives a timing sample, not a converged result)."""
+        self.L.ref_record(1, int(cap), None, None)
+        eta = _c(eta)
+        x = ctypes.c_double()
+        self.L.ref_exponent(self.h, 0 if op == "full" else 1, 0 if form == "plain" else 1, float(m1), float(m2),
+                            eta.ctypes.data, float(tol), ctypes.byref(x))
+        iters = np.zeros(16, dtype=np.int32)
+        secs = np.zeros(16)
+        n = self.L.ref_record(0, 0, iters.ctypes.data, secs.ctypes.data)
+        return x.value, iters[:n].tolist(), secs[:n].tolist()
+
+    @staticmethod
+    def threads() -> int:
+        return int(_load().ref_threads())
 
     def exponent(self, op: str, form: str, m1, m2, eta, tol=1e-13) -> float:
         eta = _c(eta)

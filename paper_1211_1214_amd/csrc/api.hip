@@ -161,8 +161,8 @@ static size_t vec_words(const ddwc_ctx* C, int nrhs, bool fp64) {
 double ddwc_dslash_bytes(const ddwc_ctx* C, int nrhs, int prec) {
     if (!C) return 0;
     const double r = prec == DDWC_FP64 ? 8.0 : 4.0;
-    // per site: spinor in + out (24 reals each per RHS), 4 links (36 reals), clover (72 reals)
-    return (double)C->g.V * ((double)nrhs * 48.0 * r + 108.0 * r);
+    // per site: spinor in + out (24 reals each per RHS), 4 links (72 reals), clover (72 reals)
+    return (double)C->g.V * ((double)nrhs * 48.0 * r + 144.0 * r);
 }
 
 extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], int time_bc, double c_sw,
@@ -335,7 +335,7 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
         }
         launch_accumulate<R>(ex, g, xR, scale, x64, nrhs);
         launch_residual<double>(ex, g, C->U64, C->K64, mass4, x64, b64, r64, part, nrhs, DDWC_K_DSLASH64,
-                                ddwc_dslash_bytes(C, nrhs, DDWC_FP64) + 2 * (double)nrhs * g.V * 192.0);
+                                ddwc_dslash_bytes(C, nrhs, DDWC_FP64) + (double)nrhs * g.V * 192.0);
         launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
         HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
         HC(hipStreamSynchronize(sm));
@@ -423,6 +423,18 @@ static int block_internal(ddwc_ctx* C, Exec& ex, int colour, double mass, const 
         info->inner += imax;
         info->relres = fmax(info->relres, worst);
         info->block_iters += sum;
+    }
+    if (C->prof.on) {
+        // algorithmic bytes of this launch: per block site, an inner iteration streams 19 spinors
+        // and twice the links + clover (two operator applications); a defect-correction step
+        // streams 5 inner spinors, 3 FP64 spinors, the FP64 x update and the FP64 links + clover;
+        // the setup reads b and writes r64 and x once.
+        const double S = 24.0 * (fp64 ? 8 : 4), G = 144.0 * (fp64 ? 8 : 4);
+        double b = 0;
+        long long souter = 0;
+        for (size_t k = 0; k < nb; ++k) souter += ou[k];
+        b = (double)sum * (19 * S + 2 * G) + (double)souter * (2304.0 + 5 * S) + 576.0 * (double)nb;
+        C->prof.bytes[DDWC_K_BLOCK] += b * g.Vb;
     }
     if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
     if (worst > tol) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");

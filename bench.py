@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a device-to-device copy of this many GiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the estimates of Eq. (8) "
@@ -47,6 +49,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
 
     import paper_1211_1214_amd as dd
     from paper_1211_1214_amd import inputs

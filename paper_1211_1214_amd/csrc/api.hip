@@ -95,6 +95,7 @@ struct ddwc_ctx {
     cx<float>* U32 = nullptr;
     double2* K64 = nullptr;
     float4* K32 = nullptr;
+    int* nbr = nullptr;  // neighbour table [8][V]
     Profiler prof;
     struct Buf {
         void* p = nullptr;
@@ -194,11 +195,13 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
         hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
         hipMalloc(&C->K64, (size_t)36 * g.V * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&C->K32, (size_t)18 * g.V * sizeof(float4)) != hipSuccess) {
+        hipMalloc(&C->K32, (size_t)18 * g.V * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&C->nbr, (size_t)8 * g.V * sizeof(int)) != hipSuccess) {
         ddwc_destroy(C);
         return fail(DDWC_EHIP, "device allocation of links/clover failed");
     }
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    launch_nbr_build(ex, g, C->nbr);
     launch_links_import(ex, g, links_dev, C->U64, C->U32);
     launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
     hipError_t e1 = hipGetLastError();
@@ -219,6 +222,7 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     if (C->U32) (void)hipFree(C->U32);
     if (C->K64) (void)hipFree(C->K64);
     if (C->K32) (void)hipFree(C->K32);
+    if (C->nbr) (void)hipFree(C->nbr);
     for (auto& kv : C->ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (C->host) (void)hipHostFree(C->host);
@@ -454,7 +458,7 @@ extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void
                                  void* stream) {
     CK(check_common(C, kappa, nrhs, prec));
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     const Geom& g = C->g;
     const double mass4 = 4.0 + mass_of(kappa);
     if (prec == DDWC_FP64) {
@@ -485,7 +489,7 @@ extern "C" int ddwc_block_solve(ddwc_ctx* C, int colour, double kappa, const voi
     if (!rhs || !sol) return fail(DDWC_EINVAL, "null vector");
     if (colour != DDWC_BLACK && colour != DDWC_WHITE) return fail(DDWC_EINVAL, "colour must be 0 or 1");
     if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     double2 *b, *x;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &b));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &x));
@@ -506,7 +510,7 @@ extern "C" int ddwc_solve(ddwc_ctx* C, double kappa, const void* b, void* x, int
     CK(check_common(C, kappa, nrhs, prec));
     if (!b || !x) return fail(DDWC_EINVAL, "null vector");
     if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     double2 *bi, *xi;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &bi));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &xi));
@@ -556,7 +560,7 @@ extern "C" int ddwc_schur_apply(ddwc_ctx* C, double kappa, int inverse, const vo
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
     if (inverse != 0 && inverse != 1) return fail(DDWC_EINVAL, "inverse must be 0 or 1");
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     double2 *e, *o;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &e));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &o));
@@ -592,7 +596,7 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
     if (n_f != 2) return fail(DDWC_EINVAL, "only the two-flavour estimator (n_f = 2) is provided");
     if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
-    Exec ex{(hipStream_t)stream, &C->prof};
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     const Geom& g = C->g;
     const int nrhs = n_hit;
     const size_t nw = vec_words(C, nrhs, true);

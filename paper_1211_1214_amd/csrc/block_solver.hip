@@ -48,7 +48,7 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
     Geom g, const cx<double>* __restrict__ U64, const double2* __restrict__ K64, const cx<R>* __restrict__ UR,
     const typename Traits<R>::word* __restrict__ KR, const double2* __restrict__ b, double2* __restrict__ x,
     double2* __restrict__ r64, Inner<R> w, int colour, int nrhs, double mass4, double tol, int maxit,
-    double inner_floor, int* iters, int* outer, double* relres) {
+    double inner_floor, int* iters, int* outer, double* relres, const int* __restrict__ nbr, int ndir) {
     typedef typename Traits<R>::word W;
     __shared__ double lds[4 * 16];
     const int rank = blockIdx.x / nrhs;
@@ -62,6 +62,7 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
     // ||b||^2, x = 0, r64 = b
     double red[4];
     red[0] = 0;
+#pragma unroll 1
     for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
         const int s = base + l;
         cx<double> a[12], z[12];
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
         if (eps < inner_floor) eps = inner_floor;
         // r = rh = p = sc * r64, e = 0, rho = ||r||^2
         red[0] = 0;
-        for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
             const int s = base + l;
             cx<double> a[12];
             cx<R> q[12], z[12];
@@ -106,10 +108,11 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
         while (total < maxit) {
             // v = D_k p ; (rh, v)
             red[0] = red[1] = 0;
-            for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+    #pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
                 const int s = base + l;
                 cx<R> y[12], h[12];
-                site_operator<R, true, HOPS_INSIDE>(g, s, w.p + oR, UR, KR, m4, y);
+                site_operator<R, true, HOPS_INSIDE>(g, s, w.p + oR, UR, KR, nbr, m4, y, ndir);
                 stv<R>(w.v, oR, V, s, y);
                 ldv<R>(w.rh, oR, V, s, h);
                 acc_dot(h, y, red[0], red[1]);
@@ -118,7 +121,8 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
             if (!(red[0] * red[0] + red[1] * red[1] > 0)) break;
             const cx<R> alpha = cdiv<R>(rho, mk(red[0], red[1]));
             // s = r - alpha v (kept in r)
-            for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+    #pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
                 const int s = base + l;
                 cx<R> rr_[12], vv[12];
                 ldv<R>(w.r, oR, V, s, rr_);
@@ -129,10 +133,11 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
             __syncthreads();
             // t = D_k s ; (t, s), (t, t)
             red[0] = red[1] = red[2] = 0;
-            for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+    #pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
                 const int s = base + l;
                 cx<R> y[12], c[12];
-                site_operator<R, true, HOPS_INSIDE>(g, s, w.r + oR, UR, KR, m4, y);
+                site_operator<R, true, HOPS_INSIDE>(g, s, w.r + oR, UR, KR, nbr, m4, y, ndir);
                 stv<R>(w.t, oR, V, s, y);
                 ldv<R>(w.r, oR, V, s, c);
                 acc_dot(y, c, red[0], red[1]);
@@ -143,7 +148,8 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
             if (red[2] > 0) omega = mk((R)(red[0] / red[2]), (R)(red[1] / red[2]));
             // e += alpha p + omega s ; r = s - omega t ; (rh, r), (r, r)
             red[0] = red[1] = red[2] = 0;
-            for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+    #pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
                 const int s = base + l;
                 cx<R> ee[12], pp[12], ss[12], tt[12];
                 ldv<R>(w.e, oR, V, s, ee);
@@ -175,7 +181,8 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
             const cx<R> beta = mk((R)(q.re * ao.re - q.im * ao.im), (R)(q.re * ao.im + q.im * ao.re));
             rho = rn_;
             // p = r + beta (p - omega v)
-            for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+    #pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
                 const int s = base + l;
                 cx<R> rr_[12], pp[12], vv[12];
                 ldv<R>(w.r, oR, V, s, rr_);
@@ -187,7 +194,8 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
             __syncthreads();
         }
         // x += e / sc in FP64
-        for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
             const int s = base + l;
             cx<R> ee[12];
             cx<double> xx[12];
@@ -199,10 +207,11 @@ __global__ __launch_bounds__(BS_MAX_THREADS) void k_block_solve(
         __syncthreads();
         // r64 = b - D_k x in FP64
         red[0] = 0;
-        for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) {
             const int s = base + l;
             cx<double> y[12], bv[12];
-            site_operator<double, true, HOPS_INSIDE>(g, s, x + o64, U64, K64, mass4, y);
+            site_operator<double, true, HOPS_INSIDE>(g, s, x + o64, U64, K64, nbr, mass4, y, ndir);
             load_spinor(b + o64, V, s, bv);
             for (int k = 0; k < 12; ++k) y[k] = bv[k] - y[k];
             store_spinor(r64 + o64, V, s, y);
@@ -231,7 +240,7 @@ void launch_block_solve64(Exec& e, const Geom& g, const cx<double>* U, const dou
     w.e = (double2*)a.w[5];
     k_block_solve<double><<<g.NBc * a.nrhs, block_solver_threads(g), 0, e.stream>>>(
         g, U, K, U, K, a.b, a.x, a.r64, w, a.colour, a.nrhs, a.mass4, a.tol, a.maxit, 0.0, a.iters, a.outer,
-        a.relres);
+        a.relres, e.nbr, 8);
 }
 
 void launch_block_solve32(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const cx<float>* U32,
@@ -246,7 +255,7 @@ void launch_block_solve32(Exec& e, const Geom& g, const cx<double>* U64, const d
     w.e = (float4*)a.w[5];
     k_block_solve<float><<<g.NBc * a.nrhs, block_solver_threads(g), 0, e.stream>>>(
         g, U64, K64, U32, K32, a.b, a.x, a.r64, w, a.colour, a.nrhs, a.mass4, a.tol, a.maxit, 2e-6, a.iters,
-        a.outer, a.relres);
+        a.outer, a.relres, e.nbr, 8);
 }
 
 }  // namespace ddwc

@@ -56,6 +56,21 @@ DDWC_HD cx<R> times_i(cx<R> a) { return mk(-a.im, a.re); }
 template <class R>
 DDWC_HD cx<R> times_mi(cx<R> a) { return mk(a.im, -a.re); }
 
+DDWC_HD float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+DDWC_HD double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += a b and acc += conj(a) b as explicit fused multiply-adds.
+template <class R>
+DDWC_HD void cmadd(cx<R>& acc, cx<R> a, cx<R> b) {
+    acc.re = fmad(a.re, b.re, fmad(-a.im, b.im, acc.re));
+    acc.im = fmad(a.re, b.im, fmad(a.im, b.re, acc.im));
+}
+template <class R>
+DDWC_HD void cjmadd(cx<R>& acc, cx<R> a, cx<R> b) {
+    acc.re = fmad(a.re, b.re, fmad(a.im, b.im, acc.re));
+    acc.im = fmad(a.re, b.im, fmad(-a.im, b.re, acc.im));
+}
+
 // ------------------------------------------------------------------ geometry
 struct Geom {
     int L[4];      // T, L1, L2, L3
@@ -196,64 +211,74 @@ struct Traits<float> {
     static constexpr int NKW = 18;
 };
 
-DDWC_HD void load_spinor(const double2* __restrict__ f, int V, int s, cx<double> p[12]) {
+// Element i of an array whose byte size stays below 4 GiB: the byte offset is formed in
+// 32 bits, so a load is a uniform base plus a 32-bit per-lane offset.
+template <class T>
+DDWC_HD const T& at(const T* base, unsigned i) {
+    return *(const T*)((const char*)base + i * (unsigned)sizeof(T));
+}
+template <class T>
+DDWC_HD T& at(T* base, unsigned i) {
+    return *(T*)((char*)base + i * (unsigned)sizeof(T));
+}
+
+DDWC_HD void load_spinor(const double2* __restrict__ f, unsigned V, unsigned s, cx<double> p[12]) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        double2 w = f[(size_t)c * V + s];
+        double2 w = at(f + (size_t)c * V, s);
         p[c] = mk(w.x, w.y);
     }
 }
-DDWC_HD void load_spinor(const float4* __restrict__ f, int V, int s, cx<float> p[12]) {
+DDWC_HD void load_spinor(const float4* __restrict__ f, unsigned V, unsigned s, cx<float> p[12]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float4 w = f[(size_t)k * V + s];
+        float4 w = at(f + (size_t)k * V, s);
         p[2 * k] = mk(w.x, w.y);
         p[2 * k + 1] = mk(w.z, w.w);
     }
 }
-DDWC_HD void store_spinor(double2* __restrict__ f, int V, int s, const cx<double> p[12]) {
+DDWC_HD void store_spinor(double2* __restrict__ f, unsigned V, unsigned s, const cx<double> p[12]) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) f[(size_t)c * V + s] = make_double2(p[c].re, p[c].im);
+    for (int c = 0; c < 12; ++c) at(f + (size_t)c * V, s) = make_double2(p[c].re, p[c].im);
 }
-DDWC_HD void store_spinor(float4* __restrict__ f, int V, int s, const cx<float> p[12]) {
+DDWC_HD void store_spinor(float4* __restrict__ f, unsigned V, unsigned s, const cx<float> p[12]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-        f[(size_t)k * V + s] = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
+        at(f + (size_t)k * V, s) = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
 }
 
 template <class R>
-DDWC_HD void load_link(const cx<R>* __restrict__ U, int V, int mu, int s, cx<R> u[9]) {
-    const cx<R>* base = U + (size_t)mu * 9 * V + s;
+DDWC_HD void load_link(const cx<R>* __restrict__ U, unsigned V, int mu, unsigned s, cx<R> u[9]) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = base[(size_t)k * V];
+    for (int k = 0; k < 9; ++k) u[k] = at(U + (size_t)(mu * 9 + k) * V, s);
 }
 
 // The 36 reals of chiral block `blk` of the clover term at site s:
 // d[0..5] = diagonal, o[0..29] = upper off-diagonal (re, im) in row order.
-DDWC_HD void load_clover_block(const double2* __restrict__ K, int V, int s, int blk, double d[6],
+DDWC_HD void load_clover_block(const double2* __restrict__ K, unsigned V, unsigned s, int blk, double d[6],
                                                   double o[30]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double2 w = K[(size_t)(3 * blk + k) * V + s];
+        double2 w = at(K + (size_t)(3 * blk + k) * V, s);
         d[2 * k] = w.x;
         d[2 * k + 1] = w.y;
     }
 #pragma unroll
     for (int k = 0; k < 15; ++k) {
-        double2 w = K[(size_t)(6 + 15 * blk + k) * V + s];
+        double2 w = at(K + (size_t)(6 + 15 * blk + k) * V, s);
         o[2 * k] = w.x;
         o[2 * k + 1] = w.y;
     }
 }
 // FP32: reals 0..11 are words 0..2; block 0 off-diagonal reals 12..41 start in word 3,
 // block 1 reals 42..71 start at word 10 offset 2.  Load the 9 words that cover a block.
-DDWC_HD void load_clover_block(const float4* __restrict__ K, int V, int s, int blk, float d[6],
+DDWC_HD void load_clover_block(const float4* __restrict__ K, unsigned V, unsigned s, int blk, float d[6],
                                                   float o[30]) {
     float w[40];
     const int w0 = blk == 0 ? 3 : 10;  // first word holding off-diagonal reals of this block
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        float4 q = K[(size_t)(w0 + k) * V + s];
+        float4 q = at(K + (size_t)(w0 + k) * V, s);
         w[4 * k] = q.x;
         w[4 * k + 1] = q.y;
         w[4 * k + 2] = q.z;
@@ -263,8 +288,8 @@ DDWC_HD void load_clover_block(const float4* __restrict__ K, int V, int s, int b
 #pragma unroll
     for (int k = 0; k < 30; ++k) o[k] = w[sh + k];
     // diagonal reals 6*blk .. 6*blk+5 live in words 0..2
-    float4 q0 = K[(size_t)(blk == 0 ? 0 : 1) * V + s];
-    float4 q1 = K[(size_t)(blk == 0 ? 1 : 2) * V + s];
+    float4 q0 = at(K + (size_t)(blk == 0 ? 0 : 1) * V, s);
+    float4 q1 = at(K + (size_t)(blk == 0 ? 1 : 2) * V, s);
     if (blk == 0) {
         d[0] = q0.x; d[1] = q0.y; d[2] = q0.z; d[3] = q0.w; d[4] = q1.x; d[5] = q1.y;
     } else {
@@ -272,18 +297,11 @@ DDWC_HD void load_clover_block(const float4* __restrict__ K, int V, int s, int b
     }
 }
 
-// Keeps the instruction scheduler from hoisting the next direction's loads above the
-// current direction's arithmetic (which would hold all eight neighbours in registers).
-DDWC_HD void sched_fence() {
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_sched_barrier(0);
-#endif
-}
-
-// y = (4 + m) psi + C psi with the two packed Hermitian 6x6 blocks, one block at a time.
+// y = (4 + m) psi + C psi + hsc * y with the two packed Hermitian 6x6 blocks, one block at
+// a time (y holds the accumulated hop terms on entry, hsc = -1/2; hsc = 0 ignores them).
 template <class R>
-DDWC_HD void apply_diag(const typename Traits<R>::word* __restrict__ K, int V, int s, R mass4,
-                                           const cx<R> p[12], cx<R> y[12]) {
+DDWC_HD void apply_diag(const typename Traits<R>::word* __restrict__ K, unsigned V, unsigned s, R mass4,
+                        const cx<R> p[12], cx<R> y[12], R hsc) {
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
         R d[6], o[30];
@@ -291,127 +309,204 @@ DDWC_HD void apply_diag(const typename Traits<R>::word* __restrict__ K, int V, i
         const cx<R>* v = p + 6 * blk;
         cx<R>* w = y + 6 * blk;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) w[i] = (mass4 + d[i]) * v[i];
+        for (int i = 0; i < 6; ++i) {
+            const R di = mass4 + d[i];
+            w[i] = mk(fmad(di, v[i].re, hsc * w[i].re), fmad(di, v[i].im, hsc * w[i].im));
+        }
         int k = 0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
 #pragma unroll
             for (int j = i + 1; j < 6; ++j) {
-                cx<R> aij = mk(o[2 * k], o[2 * k + 1]);
-                w[i] = w[i] + aij * v[j];
-                w[j] = w[j] + conj_mul(aij, v[i]);
+                const cx<R> aij = mk(o[2 * k], o[2 * k + 1]);
+                cmadd(w[i], aij, v[j]);
+                cjmadd(w[j], aij, v[i]);
                 ++k;
             }
         }
-        sched_fence();
     }
 }
 
-// Spin structure of the hop terms in the chiral basis.  With q the neighbour spinor
-// (spins 0..3), the projected half spinor of (1 - dir g_mu) q is
-//     h0 = q0 + dir a0 q[i0],   h1 = q1 + dir a1 q[5 - i0],
-// and after k = U h (forward) or U^+ h (backward) the four spins of the hop are
-//     (k0, k1, dir b0 k[j0], dir b1 k[1 - j0]).
-// a0, a1, b0, b1 are in {+-1, +-i}; the backward (1 + g_mu) terms only flip their sign.
-struct HopSpin {
-    int i0, j0;
-    float a0r, a0i, a1r, a1i, b0r, b0i, b1r, b1i;
-};
-
-DDWC_HD HopSpin hop_spin(int mu) {
-    HopSpin h;
-    switch (mu) {
-        case 0: h = HopSpin{2, 0, 1, 0, 1, 0, 1, 0, 1, 0}; break;     // h = q_u + q_l,          l = k
-        case 1: h = HopSpin{3, 1, 0, 1, 0, 1, 0, -1, 0, -1}; break;   // h = q_u + i s1 q_l,     l = -i s1 k
-        case 2: h = HopSpin{3, 1, 1, 0, -1, 0, -1, 0, 1, 0}; break;   // h = q_u + i s2 q_l,     l = -i s2 k
-        default: h = HopSpin{2, 0, 0, 1, 0, -1, 0, -1, 0, 1}; break;  // h = q_u + i s3 q_l,     l = -i s3 k
-    }
-    return h;
-}
-
-template <class R>
-DDWC_HD cx<R> cscale(float re, float im, cx<R> z) {
-    return mk((R)re * z.re - (R)im * z.im, (R)re * z.im + (R)im * z.re);
-}
-
-// acc += fac * (1 - dir g_mu) W q, W = U (dir = +1) or U^+ (dir = -1).
-template <class R>
-DDWC_HD void hop_accumulate(int mu, int dir, const cx<R> u[9], const cx<R> q[12], R fac, cx<R> acc[12]) {
-    const HopSpin hs = hop_spin(mu);
-    const R sg = (R)dir;
+// One hop term in the chiral basis: acc += (1 - g_mu) U q (DIR = +1) or
+// (1 + g_mu) U^+ q (DIR = -1), through the spin-projected half spinor
+// h = (h0, h1) (2 spins x 3 colours):
+//   mu = 0:  h = q_u -+ q_l         lower spins of the term = +- k
+//   mu = k:  h = q_u +- i s_k q_l   lower spins = -+ i s_k k       (k = U h or U^+ h)
+// MU and DIR are compile-time, so each direction is straight-line code.
+template <class R, int MU, int DIR>
+DDWC_HD void hop_term(const cx<R> u[9], const cx<R> q[12], cx<R> acc[12]) {
     cx<R> h0[3], h1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const cx<R> x0 = hs.i0 == 2 ? q[6 + a] : q[9 + a];
-        const cx<R> x1 = hs.i0 == 2 ? q[9 + a] : q[6 + a];
-        h0[a] = q[a] + sg * cscale(hs.a0r, hs.a0i, x0);
-        h1[a] = q[3 + a] + sg * cscale(hs.a1r, hs.a1i, x1);
+        const cx<R> p0 = q[a], p1 = q[3 + a], p2 = q[6 + a], p3 = q[9 + a];
+        if (MU == 0) {
+            h0[a] = DIR > 0 ? p0 + p2 : p0 - p2;
+            h1[a] = DIR > 0 ? p1 + p3 : p1 - p3;
+        } else if (MU == 1) {
+            h0[a] = DIR > 0 ? p0 + times_i(p3) : p0 - times_i(p3);
+            h1[a] = DIR > 0 ? p1 + times_i(p2) : p1 - times_i(p2);
+        } else if (MU == 2) {
+            h0[a] = DIR > 0 ? p0 + p3 : p0 - p3;
+            h1[a] = DIR > 0 ? p1 - p2 : p1 + p2;
+        } else {
+            h0[a] = DIR > 0 ? p0 + times_i(p2) : p0 - times_i(p2);
+            h1[a] = DIR > 0 ? p1 - times_i(p3) : p1 + times_i(p3);
+        }
     }
-    cx<R> w[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) w[3 * a + b] = dir > 0 ? u[3 * a + b] : mk(u[3 * b + a].re, -u[3 * b + a].im);
     cx<R> k0[3], k1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        k0[a] = fac * (w[3 * a] * h0[0] + w[3 * a + 1] * h0[1] + w[3 * a + 2] * h0[2]);
-        k1[a] = fac * (w[3 * a] * h1[0] + w[3 * a + 1] * h1[1] + w[3 * a + 2] * h1[2]);
+        k0[a] = mk(R(0), R(0));
+        k1[a] = mk(R(0), R(0));
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (DIR > 0) {
+                cmadd(k0[a], u[3 * a + b], h0[b]);
+                cmadd(k1[a], u[3 * a + b], h1[b]);
+            } else {
+                cjmadd(k0[a], u[3 * b + a], h0[b]);
+                cjmadd(k1[a], u[3 * b + a], h1[b]);
+            }
+        }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         acc[a] = acc[a] + k0[a];
         acc[3 + a] = acc[3 + a] + k1[a];
-        const cx<R> y0 = hs.j0 == 0 ? k0[a] : k1[a];
-        const cx<R> y1 = hs.j0 == 0 ? k1[a] : k0[a];
-        acc[6 + a] = acc[6 + a] + sg * cscale(hs.b0r, hs.b0i, y0);
-        acc[9 + a] = acc[9 + a] + sg * cscale(hs.b1r, hs.b1i, y1);
+        cx<R> l0, l1;
+        if (MU == 0) {
+            l0 = DIR > 0 ? k0[a] : -k0[a];
+            l1 = DIR > 0 ? k1[a] : -k1[a];
+        } else if (MU == 1) {
+            l0 = DIR > 0 ? times_mi(k1[a]) : times_i(k1[a]);
+            l1 = DIR > 0 ? times_mi(k0[a]) : times_i(k0[a]);
+        } else if (MU == 2) {
+            l0 = DIR > 0 ? -k1[a] : k1[a];
+            l1 = DIR > 0 ? k0[a] : -k0[a];
+        } else {
+            l0 = DIR > 0 ? times_mi(k0[a]) : times_i(k0[a]);
+            l1 = DIR > 0 ? times_i(k1[a]) : times_mi(k1[a]);
+        }
+        acc[6 + a] = acc[6 + a] + l0;
+        acc[9 + a] = acc[9 + a] + l1;
     }
 }
 
-// Neighbour one step in direction dir (+1 / -1) along mu: index, same-block flag, and the
-// time-boundary factor of the hop.
-DDWC_HD int neighbour_rt(const Geom& g, int s, const Site& S, int mu, int dir, bool& inside, int& bc) {
-    return dir > 0 ? neighbour<+1>(g, s, S, mu, inside, bc) : neighbour<-1>(g, s, S, mu, inside, bc);
+// Direction d = 2 mu + (backward ? 1 : 0), chosen at run time (uniform across the wave).
+template <class R>
+DDWC_HD void hop_dispatch(int d, const cx<R> u[9], const cx<R> q[12], cx<R> acc[12]) {
+    switch (d) {
+        case 0: hop_term<R, 0, +1>(u, q, acc); break;
+        case 1: hop_term<R, 0, -1>(u, q, acc); break;
+        case 2: hop_term<R, 1, +1>(u, q, acc); break;
+        case 3: hop_term<R, 1, -1>(u, q, acc); break;
+        case 4: hop_term<R, 2, +1>(u, q, acc); break;
+        case 5: hop_term<R, 2, -1>(u, q, acc); break;
+        case 6: hop_term<R, 3, +1>(u, q, acc); break;
+        default: hop_term<R, 3, -1>(u, q, acc); break;
+    }
+}
+
+// Neighbour-table entry of site s in direction d = 2 mu + (backward ? 1 : 0): the
+// neighbour's internal index, bitwise-negated when the hop crosses an antiperiodic
+// time boundary.
+template <int DIR>
+DDWC_HD int table_entry(const Geom& g, int s, const Site& S, int mu) {
+    bool inside;
+    int bc;
+    const int t = neighbour<DIR>(g, s, S, mu, inside, bc);
+    return bc < 0 ? ~t : t;
 }
 
 // Which hops a site operator includes.
 enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 
-// y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops.  `in` points at one RHS.
-// The diagonal part is applied first; the hops then accumulate into y with the factor
-// -1/2 (times the time-boundary sign) folded into the half-spinor products.
-template <class R, bool DIAG, int HOPS>
-DDWC_HD void site_operator(const Geom& g, int s, const typename Traits<R>::word* __restrict__ in,
-                                              const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
-                                              R mass4, cx<R> y[12]) {
-    const int V = g.V;
+// y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops.  `in` points at one RHS,
+// nbr is the neighbour table [8][V].  A neighbour lies in the same Schwarz block exactly
+// when it has the same colour, i.e. lies in the same half of the block-major order.
+// `ndir` is 8; it is a run-time value so that the direction loop stays a loop and only
+// one neighbour spinor and link are live at a time (PIPE: the next direction's loads are
+// issued before the current one is computed).  The hops are summed unscaled (a hop across
+// an antiperiodic time boundary is subtracted) and scaled by -1/2 once.
+template <class R, bool DIAG, int HOPS, bool PIPE = false>
+DDWC_HD void site_operator(const Geom& g, unsigned s, const typename Traits<R>::word* __restrict__ in,
+                           const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
+                           const int* __restrict__ nbr, R mass4, cx<R> y[12], int ndir) {
+    const unsigned V = g.V;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c] = mk(R(0), R(0));
+    if (HOPS != HOPS_NONE) {
+        const bool s_black = s < V / 2;
+        if (!PIPE) {
+#pragma unroll 1
+            for (int d = 0; d < ndir; ++d) {
+                const int e = at(nbr + (size_t)d * V, s);
+                const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+                const bool inside = (t < V / 2) == s_black;
+                const bool take =
+                    HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+                if (take) {
+                    cx<R> q[12], u[9];
+                    load_spinor(in, V, t, q);
+                    load_link(U, V, d >> 1, (d & 1) ? t : s, u);
+                    if (e < 0) {
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) q[c] = -q[c];
+                    }
+                    hop_dispatch<R>(d, u, q, y);
+                }
+            }
+        } else {
+            // all eight table entries first, then a software-pipelined direction loop: the
+            // neighbour spinor and link of direction d + 1 are in flight while d is computed
+            int ent[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * V, s);
+            cx<R> q[12], u[9];
+            {
+                const int e = ent[0];
+                load_spinor(in, V, e < 0 ? (unsigned)~e : (unsigned)e, q);
+                load_link(U, V, 0, s, u);
+            }
+#pragma unroll 1
+            for (int d = 0; d < ndir; ++d) {
+                int e = ent[0];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) e = d == k ? ent[k] : e;
+                const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+                const bool inside = (t < V / 2) == s_black;
+                const bool take =
+                    HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+                cx<R> qn[12], un[9];
+                if (d + 1 < ndir) {
+                    int en = ent[1];
+#pragma unroll
+                    for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
+                    const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
+                    load_spinor(in, V, tn, qn);
+                    load_link(U, V, (d + 1) >> 1, ((d + 1) & 1) ? tn : s, un);
+                }
+                if (take) {
+                    if (e < 0) {
+#pragma unroll
+                        for (int c = 0; c < 12; ++c) q[c] = -q[c];
+                    }
+                    hop_dispatch<R>(d, u, q, y);
+                }
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = qn[c];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) u[c] = un[c];
+            }
+        }
+    }
     if (DIAG) {
         cx<R> c[12];
         load_spinor(in, V, s, c);
-        apply_diag<R>(K, V, s, mass4, c, y);
-        sched_fence();
+        apply_diag<R>(K, V, s, mass4, c, y, R(-0.5));
     } else {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) y[c] = mk(R(0), R(0));
-    }
-    if (HOPS != HOPS_NONE) {
-        const Site S = decode(g, s);
-        // one direction per trip: only one neighbour spinor and link are live at a time
-#pragma unroll 1
-        for (int d = 0; d < 8; ++d) {
-            const int mu = d >> 1, dir = (d & 1) ? -1 : 1;
-            bool inside;
-            int bc;
-            const int t = neighbour_rt(g, s, S, mu, dir, inside, bc);
-            const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
-            if (take) {
-                cx<R> q[12], u[9];
-                load_spinor(in, V, t, q);
-                load_link(U, V, mu, dir > 0 ? s : t, u);
-                hop_accumulate<R>(mu, dir, u, q, R(-0.5) * R(bc), y);
-            }
-        }
+        for (int c = 0; c < 12; ++c) y[c] = R(-0.5) * y[c];
     }
 }
 

@@ -46,6 +46,7 @@ struct Profiler {
 struct Exec {
     hipStream_t stream;
     Profiler* prof;
+    const int* nbr;  // neighbour table [8][V] of the context
 };
 
 // RAII-free scoped timing helper used by the launchers.
@@ -68,6 +69,7 @@ constexpr int NPART = 4; // doubles per partial-sum slot
 inline int tiles_of(int n) { return (n + WG - 1) / WG; }
 
 void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32);
+void launch_nbr_build(Exec& e, const Geom& g, int* nbr);
 void launch_clover_build(Exec& e, const Geom& g, const cx<double>* U64, double csw, double2* K64, float4* K32);
 
 template <class R>

@@ -65,6 +65,22 @@ void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* 
     k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32);
 }
 
+// Neighbour table [8][V] (setup, once per geometry).
+__global__ void k_nbr_build(Geom g, int* __restrict__ nbr) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const Site S = decode(g, s);
+    for (int mu = 0; mu < 4; ++mu) {
+        nbr[(size_t)(2 * mu) * g.V + s] = table_entry<+1>(g, s, S, mu);
+        nbr[(size_t)(2 * mu + 1) * g.V + s] = table_entry<-1>(g, s, S, mu);
+    }
+}
+
+void launch_nbr_build(Exec& e, const Geom& g, int* nbr) {
+    Timed t(e, 4, 0);
+    k_nbr_build<<<tiles_of(g.V), WG, 0, e.stream>>>(g, nbr);
+}
+
 // Clover term at every site (setup, once per gauge field).
 __global__ void k_clover_build(Geom g, const cx<double>* __restrict__ U, double csw, double2* __restrict__ K64,
                                float4* __restrict__ K32) {
@@ -142,7 +158,7 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
                                                const typename Traits<R>::word* __restrict__ in,
                                                typename Traits<R>::word* __restrict__ out,
                                                const typename Traits<R>::word* __restrict__ aux, double* part,
-                                               int nrhs, int ntiles) {
+                                               int nrhs, int ntiles, const int* __restrict__ nbr, int ndir) {
     typedef typename Traits<R>::word W;
     TileRhs tr = tile_rhs(ntiles, nrhs);
     const int s = tr.tile * WG + threadIdx.x;
@@ -150,7 +166,7 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
     double v[3] = {0, 0, 0};
     if (s < g.V) {
         cx<R> y[12];
-        site_operator<R, true, HOPS_ALL>(g, s, in + off, U, K, mass4, y);
+        site_operator<R, true, HOPS_ALL, true>(g, s, in + off, U, K, nbr, mass4, y, ndir);
         if (EPI == EPI_RESID) {
             cx<R> b[12];
             load_spinor((const W*)aux + off, g.V, s, b);
@@ -182,7 +198,7 @@ void launch_dslash(Exec& e, const Geom& g, const cx<R>* U, const typename Traits
                    double bytes) {
     Timed t(e, kclass, bytes);
     int nt = tiles_of(g.V);
-    k_dslash<R, EPI_NONE><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, nullptr, nrhs, nt);
+    k_dslash<R, EPI_NONE><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, nullptr, nrhs, nt, e.nbr, 8);
 }
 template <class R>
 void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
@@ -190,7 +206,7 @@ void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Tr
                        const typename Traits<R>::word* w, double* part, int nrhs, int kclass, double bytes) {
     Timed t(e, kclass, bytes);
     int nt = tiles_of(g.V);
-    k_dslash<R, EPI_DOT><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, w, part, nrhs, nt);
+    k_dslash<R, EPI_DOT><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, w, part, nrhs, nt, e.nbr, 8);
 }
 template <class R>
 void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
@@ -198,7 +214,7 @@ void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename T
                         int kclass, double bytes) {
     Timed t(e, kclass, bytes);
     int nt = tiles_of(g.V);
-    k_dslash<R, EPI_DOT2><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, part, nrhs, nt);
+    k_dslash<R, EPI_DOT2><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, part, nrhs, nt, e.nbr, 8);
 }
 template <class R>
 void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
@@ -206,20 +222,21 @@ void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Trai
                      typename Traits<R>::word* r, double* part, int nrhs, int kclass, double bytes) {
     Timed t(e, kclass, bytes);
     int nt = tiles_of(g.V);
-    k_dslash<R, EPI_RESID><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, x, r, b, part, nrhs, nt);
+    k_dslash<R, EPI_RESID><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, x, r, b, part, nrhs, nt, e.nbr, 8);
 }
 
 template <class R>
 __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __restrict__ U,
                                             const typename Traits<R>::word* __restrict__ in,
-                                            typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour) {
+                                            typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour,
+                                            const int* __restrict__ nbr, int ndir) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
     if (s >= g.V) return;
     const size_t off = (size_t)rhs * Traits<R>::NCW * g.V;
     cx<R> y[12];
     if ((s / (g.V / 2)) == to_colour) {
-        site_operator<R, false, HOPS_CROSSING>(g, s, in + off, U, nullptr, R(0), y);
+        site_operator<R, false, HOPS_CROSSING, true>(g, s, in + off, U, nullptr, nbr, R(0), y, ndir);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) y[k] = mk(R(0), R(0));
@@ -231,7 +248,7 @@ template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
                 typename Traits<R>::word* out, int nrhs, int to_colour) {
     Timed t(e, 4, 0);
-    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour);
+    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour, e.nbr, 8);
 }
 
 // ------------------------------------------------------------------ BiCGStab vector kernels

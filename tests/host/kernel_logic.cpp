@@ -26,6 +26,14 @@ extern "C" int host_apply(const int* lat, const int* blk, int tbc, double csw, c
                 U[((size_t)mu * 9 + k) * V + s] = mk(src[0], src[1]);
             }
     }
+    std::vector<int> nbr((size_t)8 * V);
+    for (int s = 0; s < V; ++s) {
+        const Site S = decode(g, s);
+        for (int mu = 0; mu < 4; ++mu) {
+            nbr[(size_t)(2 * mu) * V + s] = table_entry<+1>(g, s, S, mu);
+            nbr[(size_t)(2 * mu + 1) * V + s] = table_entry<-1>(g, s, S, mu);
+        }
+    }
     std::vector<double2> K((size_t)36 * V), in((size_t)12 * V);
     for (int s = 0; s < V; ++s) {
         double a[72];
@@ -43,11 +51,11 @@ extern "C" int host_apply(const int* lat, const int* blk, int tbc, double csw, c
         cx<double> y[12];
         const int c_s = s / (V / 2);
         if (mode == 0)
-            site_operator<double, true, HOPS_ALL>(g, s, in.data(), U.data(), K.data(), mass4, y);
+            site_operator<double, true, HOPS_ALL>(g, s, in.data(), U.data(), K.data(), nbr.data(), mass4, y, 8);
         else if (mode == 1 && c_s == colour)
-            site_operator<double, true, HOPS_INSIDE>(g, s, in.data(), U.data(), K.data(), mass4, y);
+            site_operator<double, true, HOPS_INSIDE>(g, s, in.data(), U.data(), K.data(), nbr.data(), mass4, y, 8);
         else if (mode == 2 && c_s == colour)
-            site_operator<double, false, HOPS_CROSSING>(g, s, in.data(), U.data(), nullptr, 0.0, y);
+            site_operator<double, false, HOPS_CROSSING>(g, s, in.data(), U.data(), nullptr, nbr.data(), 0.0, y, 8);
         else
             for (int c = 0; c < 12; ++c) y[c] = mk(0.0, 0.0);
         for (int c = 0; c < 12; ++c) {

@@ -96,6 +96,20 @@ struct ddwc_ctx {
     double2* K64 = nullptr;
     float4* K32 = nullptr;
     int* nbr = nullptr;  // neighbour table [8][V]
+    // even-odd half fields (allocated when every block extent is even)
+    cx<double>* Uh64 = nullptr;
+    cx<float>* Uh32 = nullptr;
+    double2* Kh64 = nullptr;
+    float4* Kh32 = nullptr;
+    int* nbr_eo = nullptr;
+    struct Ainv {
+        double mass4;
+        double2* a64;
+        float4* a32;
+        unsigned long long used;
+    };
+    std::vector<Ainv> ainv;  // odd-site inverses of 4 + m + C for the masses in use
+    unsigned long long clock = 0;
     Profiler prof;
     struct Buf {
         void* p = nullptr;
@@ -204,6 +218,18 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     launch_nbr_build(ex, g, C->nbr);
     launch_links_import(ex, g, links_dev, C->U64, C->U32);
     launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
+    if (g.eo) {
+        const size_t n2 = g.V / 2;
+        if (hipMalloc(&C->Uh64, (size_t)2 * 36 * n2 * sizeof(cx<double>)) != hipSuccess ||
+            hipMalloc(&C->Uh32, (size_t)2 * 36 * n2 * sizeof(cx<float>)) != hipSuccess ||
+            hipMalloc(&C->Kh64, (size_t)2 * 36 * n2 * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&C->Kh32, (size_t)2 * 18 * n2 * sizeof(float4)) != hipSuccess ||
+            hipMalloc(&C->nbr_eo, (size_t)2 * 8 * n2 * sizeof(int)) != hipSuccess) {
+            ddwc_destroy(C);
+            return fail(DDWC_EHIP, "device allocation of the even-odd fields failed");
+        }
+        launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Kh64, C->Kh32, C->nbr_eo);
+    }
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -223,6 +249,12 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     if (C->K64) (void)hipFree(C->K64);
     if (C->K32) (void)hipFree(C->K32);
     if (C->nbr) (void)hipFree(C->nbr);
+    for (void* q : {(void*)C->Uh64, (void*)C->Uh32, (void*)C->Kh64, (void*)C->Kh32, (void*)C->nbr_eo})
+        if (q) (void)hipFree(q);
+    for (auto& a : C->ainv) {
+        (void)hipFree(a.a64);
+        (void)hipFree(a.a32);
+    }
     for (auto& kv : C->ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (C->host) (void)hipHostFree(C->host);
@@ -360,8 +392,228 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
     return DDWC_OK;
 }
 
+// ------------------------------------------------------------------ even-odd global solver
+template <class R>
+static EoFields<R> eo_fields(const ddwc_ctx* C);
+template <>
+EoFields<double> eo_fields<double>(const ddwc_ctx* C) {
+    EoFields<double> F;
+    F.n2 = C->g.V / 2;
+    for (int p = 0; p < 2; ++p) {
+        F.U[p] = C->Uh64 + (size_t)p * 36 * F.n2;
+        F.K[p] = C->Kh64 + (size_t)p * 36 * F.n2;
+        F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
+    }
+    return F;
+}
+template <>
+EoFields<float> eo_fields<float>(const ddwc_ctx* C) {
+    EoFields<float> F;
+    F.n2 = C->g.V / 2;
+    for (int p = 0; p < 2; ++p) {
+        F.U[p] = C->Uh32 + (size_t)p * 36 * F.n2;
+        F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
+        F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
+    }
+    return F;
+}
+
+// Odd-site inverses of 4 + m + C for mass4 = 4 + m (kept for the last few masses).
+static int get_ainv(ddwc_ctx* C, Exec& ex, double mass4, const double2** a64, const float4** a32) {
+    const size_t n2 = C->g.V / 2;
+    for (auto& a : C->ainv)
+        if (a.mass4 == mass4) {
+            a.used = ++C->clock;
+            *a64 = a.a64;
+            *a32 = a.a32;
+            return DDWC_OK;
+        }
+    ddwc_ctx::Ainv* slot = nullptr;
+    if (C->ainv.size() < 4) {
+        ddwc_ctx::Ainv a{};
+        HC(hipMalloc(&a.a64, (size_t)36 * n2 * sizeof(double2)));
+        HC(hipMalloc(&a.a32, (size_t)18 * n2 * sizeof(float4)));
+        C->ainv.push_back(a);
+        slot = &C->ainv.back();
+    } else {
+        slot = &C->ainv[0];
+        for (auto& a : C->ainv)
+            if (a.used < slot->used) slot = &a;
+    }
+    slot->mass4 = mass4;
+    slot->used = ++C->clock;
+    launch_eo_inverse(ex, (unsigned)n2, C->Kh64 + (size_t)36 * n2, mass4, slot->a64, slot->a32);
+    HC(hipGetLastError());
+    *a64 = slot->a64;
+    *a32 = slot->a32;
+    return DDWC_OK;
+}
+
+// D(m) x = b with even-odd preconditioning: BiCGStab in precision R on
+// Mee = A_ee - 1/4 H_eo A_oo^-1 H_oe inside FP64 defect correction, then
+// x_o = A_oo^-1 (b_o + 1/2 H_oe x_e).  The FP64 residual of the even system equals the
+// residual of the full system, so the stopping rule is ||b'_e - Mee x_e|| <= tol ||b||.
+template <class R>
+static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
+                    int maxit, SolveInfo* info) {
+    typedef typename Traits<R>::word W;
+    const Geom& g = C->g;
+    const bool fp64 = sizeof(R) == 8;
+    const EoFields<double> F64 = eo_fields<double>(C);
+    const EoFields<R> FR = eo_fields<R>(C);
+    const unsigned n2 = F64.n2;
+    Geom gh = g;  // geometry of the half fields for the vector kernels (only V is used)
+    gh.V = (int)n2;
+    const int nt = tiles_of(n2);
+    const int ntf = tiles_of(g.V);
+    const double mass4 = 4.0 + mass;
+    const double2* A64;
+    const float4* A32;
+    CK(get_ainv(C, ex, mass4, &A64, &A32));
+    const W* AR = fp64 ? (const W*)A64 : (const W*)A32;
+    const size_t hw64 = (size_t)nrhs * 12 * n2, hwR = (size_t)nrhs * (fp64 ? 12 : 6) * n2;
+    const int kcl = fp64 ? DDWC_K_DSLASH64 : DDWC_K_DSLASH32;
+    // algorithmic bytes of one half operator (hop kernel): half input with neighbours, half
+    // output, the links of all sites, the site matrix of one parity
+    const double rs = 24.0 * sizeof(R);
+    const double hbytes = (double)n2 * (nrhs * 2 * rs + 8 * 18.0 * sizeof(R) + 72.0 * sizeof(R));
+    double2 *be, *bo, *bpe, *xe, *xo, *re, *to;
+    W *r, *rh, *p, *v, *s, *t, *xR, *tmp;
+    double *part, *sums, *scale, *thr;
+    BiState* st;
+    CK(ws_t(C, "eo_be", hw64, &be));
+    CK(ws_t(C, "eo_bo", hw64, &bo));
+    CK(ws_t(C, "eo_bpe", hw64, &bpe));
+    CK(ws_t(C, "eo_xe", hw64, &xe));
+    CK(ws_t(C, "eo_xo", hw64, &xo));
+    CK(ws_t(C, "eo_re", hw64, &re));
+    CK(ws_t(C, "eo_to", hw64, &to));
+    const std::string pre = fp64 ? "eo64_" : "eo32_";
+    CK(ws_t(C, pre + "r", hwR, &r));
+    CK(ws_t(C, pre + "rh", hwR, &rh));
+    CK(ws_t(C, pre + "p", hwR, &p));
+    CK(ws_t(C, pre + "v", hwR, &v));
+    CK(ws_t(C, pre + "s", hwR, &s));
+    CK(ws_t(C, pre + "t", hwR, &t));
+    CK(ws_t(C, pre + "x", hwR, &xR));
+    CK(ws_t(C, pre + "tmp", hwR, &tmp));
+    CK(ws_t(C, "g_part", (size_t)ntf * nrhs * NPART, &part));
+    CK(ws_t(C, "g_sums", (size_t)nrhs * NPART, &sums));
+    CK(ws_t(C, "g_scale", (size_t)nrhs, &scale));
+    CK(ws_t(C, "g_thr", (size_t)nrhs, &thr));
+    CK(ws_t(C, "g_state", (size_t)nrhs, &st));
+    double* hb;
+    const size_t nst = (sizeof(BiState) + 7) / 8;
+    CK(host_buf(C, (size_t)nrhs * (NPART + 2 + nst) + 16, &hb));
+    double* h_sums = hb;
+    double* h_scale = hb + (size_t)nrhs * NPART;
+    double* h_thr = h_scale + nrhs;
+    BiState* h_st = (BiState*)(h_thr + nrhs);
+    hipStream_t sm = ex.stream;
+
+    // ||b||^2 of the full system
+    launch_dots(ex, g, b64, b64, part, nrhs);
+    launch_finalize(ex, part, ntf, nrhs, sums, nullptr, ST_SUM, nullptr);
+    HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
+    HC(hipStreamSynchronize(sm));
+    std::vector<double> bb(nrhs), rr(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+        bb[k] = h_sums[k * NPART + 2];
+        if (!isfinite(bb[k])) return fail(DDWC_ENONFINITE, "non-finite right-hand side");
+    }
+    // b'_e = b_e + 1/2 H_eo A_oo^-1 b_o ; x_e = 0 ; r_e = b'_e
+    launch_eo_split(ex, g, b64, be, bo, nrhs);
+    launch_eo_hopinv<double>(ex, F64, 1, nullptr, bo, 0.0, A64, to, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_diaghop<double>(ex, F64, 0, 0, false, be, to, 0.5, 0.0, nullptr, bpe, nullptr, nrhs, DDWC_K_OTHER, 0);
+    HC(hipMemsetAsync(xe, 0, sizeof(double2) * hw64, sm));
+    HC(hipMemcpyAsync(re, bpe, sizeof(double2) * hw64, hipMemcpyDeviceToDevice, sm));
+    launch_dots(ex, gh, re, re, part, nrhs);
+    launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+    HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
+    HC(hipStreamSynchronize(sm));
+    for (int k = 0; k < nrhs; ++k) rr[k] = h_sums[k * NPART + 2];
+    const double floor_eps = fp64 ? 0.0 : 2e-6;
+    const int poll = 2;
+    int total = 0, nout = 0;
+    bool converged = false;
+    auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
+        launch_eo_hopinv<R>(ex, FR, 1, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
+        launch_eo_diaghop<R>(ex, FR, 0, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
+                             hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
+    };
+    while (true) {
+        bool all = true;
+        for (int k = 0; k < nrhs; ++k)
+            if (bb[k] > 0 && rr[k] > tol * tol * bb[k]) all = false;
+        if (all) {
+            converged = true;
+            break;
+        }
+        if (total >= maxit || nout >= 100) break;
+        ++nout;
+        for (int k = 0; k < nrhs; ++k) {
+            bool done = !(bb[k] > 0 && rr[k] > tol * tol * bb[k]);
+            h_scale[k] = done ? 0.0 : 1.0 / sqrt(rr[k]);
+            double eps = done ? 0.0 : 0.5 * tol * sqrt(bb[k] / rr[k]);
+            if (eps < floor_eps) eps = floor_eps;
+            h_thr[k] = done ? 2.0 : eps * eps;
+        }
+        HC(hipMemcpyAsync(scale, h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
+        HC(hipMemcpyAsync(thr, h_thr, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
+        launch_bicg_init<R>(ex, gh, re, scale, r, rh, p, xR, part, nrhs);
+        launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_INIT, thr);
+        while (total < maxit) {
+            for (int k = 0; k < poll && total < maxit; ++k, ++total) {
+                apply_M(p, v, 1, rh);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_ALPHA, nullptr);
+                launch_bicg_s<R>(ex, gh, st, r, v, s, nrhs);
+                apply_M(s, t, 2, nullptr);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_OMEGA, nullptr);
+                launch_bicg_xr<R>(ex, gh, st, xR, p, s, t, rh, r, part, nrhs);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_BETA, nullptr);
+                launch_bicg_p<R>(ex, gh, st, r, v, p, nrhs);
+            }
+            HC(hipGetLastError());
+            HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
+            HC(hipStreamSynchronize(sm));
+            bool any = false;
+            for (int k = 0; k < nrhs; ++k) any = any || h_st[k].active;
+            if (!any) break;
+        }
+        launch_accumulate<R>(ex, gh, xR, scale, xe, nrhs);
+        // r_e = b'_e - Mee x_e in FP64
+        launch_eo_hopinv<double>(ex, F64, 1, xe, nullptr, 1.0, A64, to, nrhs, DDWC_K_DSLASH64, 0);
+        launch_eo_diaghop<double>(ex, F64, 0, 3, true, xe, to, -0.25, mass4, bpe, re, part, nrhs, DDWC_K_DSLASH64, 0);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
+        HC(hipStreamSynchronize(sm));
+        for (int k = 0; k < nrhs; ++k) {
+            rr[k] = h_sums[k * NPART];
+            if (!isfinite(rr[k])) return fail(DDWC_ENONFINITE, "non-finite residual in the global solve");
+        }
+    }
+    // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e), x = (x_e, x_o)
+    launch_eo_hopinv<double>(ex, F64, 1, xe, bo, 0.5, A64, xo, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_merge(ex, g, xe, xo, x64, nrhs);
+    HC(hipGetLastError());
+    double worst = 0;
+    for (int k = 0; k < nrhs; ++k)
+        if (bb[k] > 0) worst = fmax(worst, sqrt(rr[k] / bb[k]));
+    if (info) {
+        info->outer += nout;
+        info->inner += total;
+        info->relres = fmax(info->relres, worst);
+    }
+    if (!converged) return fail(DDWC_ENOCONV, "global solve did not reach its tolerance within maxit");
+    return DDWC_OK;
+}
+
 static int solve_internal(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs,
                           double tol, int maxit, int prec, SolveInfo* info) {
+    if (C->g.eo) {
+        if (prec == DDWC_FP64) return eo_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
+        return eo_solve<float>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
+    }
     if (prec == DDWC_FP64) return global_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
     return global_solve<float>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
 }
@@ -373,8 +625,103 @@ struct BlockInfo {
     long long block_iters = 0;  // summed over blocks and RHS
 };
 
+// Even-odd preconditioned block solves (every block extent even): FP64 prep, then FP64
+// defect-correction steps around the persistent inner solver until every block of the
+// colour has ||b'_e - M_k x_e|| <= tol ||b_k||, then the odd sites.
+static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, const double2* b64, double2* x64,
+                             int nrhs, double tol, int maxit, int prec, BlockInfo* info) {
+    const Geom& g = C->g;
+    const bool fp64 = prec == DDWC_FP64;
+    const double mass4 = 4.0 + mass;
+    const double2* A64;
+    const float4* A32;
+    CK(get_ainv(C, ex, mass4, &A64, &A32));
+    const EoFields<double> F64 = eo_fields<double>(C);
+    const unsigned n2 = F64.n2;
+    const size_t hw64 = (size_t)nrhs * 12 * n2, hwR = (size_t)nrhs * (fp64 ? 12 : 6) * n2;
+    double2 *bpe, *re, *xe, *to;
+    CK(ws_t(C, "be_bpe", hw64, &bpe));
+    CK(ws_t(C, "be_re", hw64, &re));
+    CK(ws_t(C, "be_xe", hw64, &xe));
+    CK(ws_t(C, "be_to", hw64, &to));
+    void* w[7];
+    const char* names[7] = {"be_r", "be_rh", "be_p", "be_v", "be_t", "be_e", "be_tmp"};
+    for (int k = 0; k < 7; ++k) CK(ws_get(C, std::string(names[k]) + (fp64 ? "64" : "32"), hwR * 16, &w[k]));
+    const size_t nb = (size_t)nrhs * g.NBc;
+    double *bb, *rr;
+    int* iters;
+    CK(ws_t(C, "be_bb", nb, &bb));
+    CK(ws_t(C, "be_rr", nb, &rr));
+    CK(ws_t(C, "be_iters", nb, &iters));
+    HC(hipMemsetAsync(iters, 0, nb * sizeof(int), ex.stream));
+    const size_t half = (size_t)g.V / 2;
+    for (int k = 0; k < nrhs; ++k)
+        for (int c = 0; c < 12; ++c)
+            HC(hipMemsetAsync(x64 + ((size_t)k * 12 + c) * g.V + (colour == 0 ? half : 0), 0, half * sizeof(double2),
+                              ex.stream));
+    launch_blk_prep(ex, g, F64, A64, b64, bpe, re, xe, to, bb, rr, colour, nrhs);
+    std::vector<double> hbb(nb), hrr(nb);
+    std::vector<int> hit(nb);
+    HC(hipMemcpyAsync(hbb.data(), bb, nb * sizeof(double), hipMemcpyDeviceToHost, ex.stream));
+    int nout = 0, imax = 0;
+    long long isum = 0;
+    bool converged = false, finite = true;
+    while (true) {
+        HC(hipMemcpyAsync(hrr.data(), rr, nb * sizeof(double), hipMemcpyDeviceToHost, ex.stream));
+        HC(hipMemcpyAsync(hit.data(), iters, nb * sizeof(int), hipMemcpyDeviceToHost, ex.stream));
+        HC(hipStreamSynchronize(ex.stream));
+        bool all = true;
+        imax = 0;
+        isum = 0;
+        for (size_t k = 0; k < nb; ++k) {
+            if (!isfinite(hrr[k]) || !isfinite(hbb[k])) finite = false;
+            if (hbb[k] > 0 && hrr[k] > tol * tol * hbb[k]) all = false;
+            imax = hit[k] > imax ? hit[k] : imax;
+            isum += hit[k];
+        }
+        if (!finite) break;
+        if (all) {
+            converged = true;
+            break;
+        }
+        if (imax >= maxit || nout >= 30) break;
+        ++nout;
+        if (fp64) {
+            const EoFields<double> F = F64;
+            launch_blk_inner<double>(ex, g, F, A64, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
+        } else {
+            const EoFields<float> F = eo_fields<float>(C);
+            launch_blk_inner<float>(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
+        }
+        launch_blk_resid(ex, g, F64, A64, bpe, xe, re, to, rr, mass4, colour, nrhs);
+    }
+    launch_blk_recon(ex, g, F64, A64, b64, xe, x64, colour, nrhs);
+    HC(hipGetLastError());
+    double worst = 0;
+    for (size_t k = 0; k < nb; ++k)
+        if (hbb[k] > 0) worst = fmax(worst, sqrt(hrr[k] / hbb[k]));
+    if (info) {
+        info->outer += nout;
+        info->inner += imax;
+        info->relres = fmax(info->relres, worst);
+        info->block_iters += isum;
+    }
+    if (C->prof.on) {
+        // algorithmic bytes per even site and inner iteration: 25 half-spinor passes and two
+        // applications of M_k, each reading both parities' links twice (16 links per
+        // even-odd pair), the even clover and the odd inverse.
+        const double S = 24.0 * (fp64 ? 8 : 4), Gk = (16 * 18.0 + 144.0) * (fp64 ? 8 : 4);
+        C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * (25 * S + 2 * Gk) +
+                                       (double)nout * nb * g.hvb * (6 * 192.0 + 16 * 18 * 8.0 + 144 * 8.0);
+    }
+    if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
+    if (!converged) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");
+    return DDWC_OK;
+}
+
 static int block_internal(ddwc_ctx* C, Exec& ex, int colour, double mass, const double2* b64, double2* x64,
                           int nrhs, double tol, int maxit, int prec, BlockInfo* info) {
+    if (C->g.eo) return block_internal_eo(C, ex, colour, mass, b64, x64, nrhs, tol, maxit, prec, info);
     const Geom& g = C->g;
     const bool fp64 = prec == DDWC_FP64;
     const size_t nw = vec_words(C, nrhs, fp64);

@@ -1,0 +1,395 @@
+// Even-odd preconditioned Schwarz block solves: x_k = D_k(m)^-1 b_k for every block k of
+// one colour, with D_k the Dirichlet block operator (Sec. 1 of the paper).  Inside a
+// block the odd sites are eliminated (eo.h):
+//     M_k = A_ee - 1/4 H^k_eo A_oo^-1 H^k_oe,  b'_e = b_e + 1/2 H^k_eo A_oo^-1 b_o,
+//     x_o = A_oo^-1 (b_o + 1/2 H^k_oe x_e),
+// H^k the hops inside block k.  Every kernel here runs one workgroup per (block, RHS); the
+// block's even and odd sites occupy the same contiguous range of the two half fields.
+//   k_blk_prep    FP64: b'_e, r_e = b'_e, x_e = 0, ||b_k||^2, ||r_e||^2
+//   k_blk_inner   persistent BiCGStab in precision R on M_k for r_e / ||r_e||, adds the
+//                 correction to x_e in FP64 (blocks already converged return at once)
+//   k_blk_resid   FP64: r_e = b'_e - M_k x_e and ||r_e||^2 (defect correction)
+//   k_blk_recon   FP64: x_o, and (x_e, x_o) written to the full solution
+#include "ddwc_internal.h"
+#include "eo.h"
+
+namespace ddwc {
+
+constexpr int BE_MAX_THREADS = 256;
+
+int block_eo_threads(const Geom& g) {
+    int t = ((g.hvb + 63) / 64) * 64;
+    return t < BE_MAX_THREADS ? t : BE_MAX_THREADS;
+}
+
+struct BlkIdx {
+    int rank, rhs, B;
+    unsigned h0;  // half index of the block's first site (both parities)
+    size_t key;   // (rhs, rank) slot of the per-block arrays
+};
+
+__device__ __forceinline__ BlkIdx blk_idx(const Geom& g, int colour, int nrhs) {
+    BlkIdx b;
+    b.rank = blockIdx.x / nrhs;
+    b.rhs = blockIdx.x - b.rank * nrhs;
+    b.B = colour * g.NBc + b.rank;
+    b.h0 = (unsigned)b.B * g.hvb;
+    b.key = (size_t)b.rhs * g.NBc + b.rank;
+    return b;
+}
+
+// Ainv (c + alpha H^k x) at odd half site j (x even), into y (odd).
+template <class R>
+__device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename Traits<R>::word* x,
+                                         const typename Traits<R>::word* c, R alpha, const EoFields<R>& F,
+                                         const typename Traits<R>::word* Ainv, cx<R> w[12]) {
+    cx<R> acc[12];
+    hop_sum<R, HOPS_INSIDE, false>(n2, j, x, F.U[1], F.U[0], F.nbr[1], acc, 8);
+    if (c) {
+        cx<R> cc[12];
+        load_spinor(c, n2, j, cc);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cc[k] + alpha * acc[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = alpha * acc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = mk(R(0), R(0));
+    apply_diag<R>(Ainv, n2, j, R(0), acc, w, R(0));
+}
+
+// [A_ee] c + beta H^k t at even half site i (t odd).
+template <class R, bool USE_A>
+__device__ __forceinline__ void even_pass(unsigned n2, unsigned i, const typename Traits<R>::word* c,
+                                          const typename Traits<R>::word* t, R beta, const EoFields<R>& F, R mass4,
+                                          cx<R> y[12]) {
+    cx<R> cc[12];
+    hop_sum<R, HOPS_INSIDE, false>(n2, i, t, F.U[0], F.U[1], F.nbr[0], y, 8);
+    load_spinor(c, n2, i, cc);
+    if (USE_A) {
+        apply_diag<R>(F.K[0], n2, i, mass4, cc, y, beta);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) y[k] = cc[k] + beta * y[k];
+    }
+}
+
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_prep(Geom g, EoFields<double> F, const double2* __restrict__ Ainv,
+                                                            const double2* __restrict__ b, double2* __restrict__ bpe,
+                                                            double2* __restrict__ re, double2* __restrict__ xe,
+                                                            double2* __restrict__ to, double* bb, double* rr,
+                                                            int colour, int nrhs) {
+    __shared__ double lds[16];
+    const BlkIdx k = blk_idx(g, colour, nrhs);
+    const unsigned n2 = F.n2;
+    const size_t of = (size_t)k.rhs * 12 * g.V, oh = (size_t)k.rhs * 12 * n2;
+    double red[1] = {0};
+    // odd pass: t_o = A_oo^-1 b_o ; ||b_o||^2
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned j = k.h0 + l, s = full_index(g, j, 1);
+        cx<double> bo[12], w[12], z[12];
+        load_spinor(b + of, g.V, s, bo);
+        red[0] += acc_nrm(bo);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = z[c] = mk(0.0, 0.0);
+        apply_diag<double>(Ainv, n2, j, 0.0, bo, w, 0.0);
+        store_spinor(to + oh, n2, j, w);
+    }
+    __syncthreads();
+    // even pass: b'_e = b_e + 1/2 H^k t_o ; r_e = b'_e ; x_e = 0 ; ||b_e||^2, ||r_e||^2
+    double red2[1] = {0};
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned i = k.h0 + l, s = full_index(g, i, 0);
+        cx<double> be[12], y[12], z[12];
+        load_spinor(b + of, g.V, s, be);
+        red[0] += acc_nrm(be);
+        hop_sum<double, HOPS_INSIDE, false>(n2, i, to + oh, F.U[0], F.U[1], F.nbr[0], y, 8);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            y[c] = be[c] + 0.5 * y[c];
+            z[c] = mk(0.0, 0.0);
+        }
+        store_spinor(bpe + oh, n2, i, y);
+        store_spinor(re + oh, n2, i, y);
+        store_spinor(xe + oh, n2, i, z);
+        red2[0] += acc_nrm(y);
+    }
+    block_sum<1>(red, lds);
+    block_sum<1>(red2, lds);
+    if (threadIdx.x == 0) {
+        bb[k.key] = red[0];
+        rr[k.key] = red2[0];
+    }
+}
+
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_resid(Geom g, EoFields<double> F, const double2* __restrict__ Ainv,
+                                                             const double2* __restrict__ bpe, const double2* __restrict__ xe,
+                                                             double2* __restrict__ re, double2* __restrict__ to, double* rr,
+                                                             double mass4, int colour, int nrhs) {
+    __shared__ double lds[16];
+    const BlkIdx k = blk_idx(g, colour, nrhs);
+    const unsigned n2 = F.n2;
+    const size_t oh = (size_t)k.rhs * 12 * n2;
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        cx<double> w[12];
+        odd_pass<double>(n2, k.h0 + l, xe + oh, nullptr, 1.0, F, Ainv, w);
+        store_spinor(to + oh, n2, k.h0 + l, w);
+    }
+    __syncthreads();
+    double red[1] = {0};
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned i = k.h0 + l;
+        cx<double> y[12], bv[12];
+        even_pass<double, true>(n2, i, xe + oh, to + oh, -0.25, F, mass4, y);
+        load_spinor(bpe + oh, n2, i, bv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) y[c] = bv[c] - y[c];
+        store_spinor(re + oh, n2, i, y);
+        red[0] += acc_nrm(y);
+    }
+    block_sum<1>(red, lds);
+    if (threadIdx.x == 0) rr[k.key] = red[0];
+}
+
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, EoFields<double> F, const double2* __restrict__ Ainv,
+                                                             const double2* __restrict__ b, const double2* __restrict__ xe,
+                                                             double2* __restrict__ x, int colour, int nrhs) {
+    const BlkIdx k = blk_idx(g, colour, nrhs);
+    const unsigned n2 = F.n2;
+    const size_t of = (size_t)k.rhs * 12 * g.V, oh = (size_t)k.rhs * 12 * n2;
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned j = k.h0 + l;
+        cx<double> bo[12], w[12], e[12];
+        // x_o = A_oo^-1 (b_o + 1/2 H^k x_e)
+        load_spinor(b + of, g.V, full_index(g, j, 1), bo);
+        cx<double> acc[12];
+        hop_sum<double, HOPS_INSIDE, false>(n2, j, xe + oh, F.U[1], F.U[0], F.nbr[1], acc, 8);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            acc[c] = bo[c] + 0.5 * acc[c];
+            w[c] = mk(0.0, 0.0);
+        }
+        apply_diag<double>(Ainv, n2, j, 0.0, acc, w, 0.0);
+        store_spinor(x + of, g.V, full_index(g, j, 1), w);
+        load_spinor(xe + oh, n2, j, e);
+        store_spinor(x + of, g.V, full_index(g, j, 0), e);
+    }
+}
+
+template <class R>
+struct BlkInner {
+    typedef typename Traits<R>::word W;
+    W *r, *rh, *p, *v, *t, *e, *tmp;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> cdiv_r(cx<double> a, cx<double> b) {
+    const double d = b.re * b.re + b.im * b.im;
+    return mk((R)((a.re * b.re + a.im * b.im) / d), (R)((a.im * b.re - a.re * b.im) / d));
+}
+
+// v = M_k p on the block (two passes separated by a workgroup barrier), with the dot
+// products requested: (rh, v) when DOT1, (v, p) and (v, v) when DOT2.
+template <class R, int DOT>
+__device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
+                                         unsigned h0, size_t oR, const typename Traits<R>::word* in,
+                                         typename Traits<R>::word* tmp, typename Traits<R>::word* out,
+                                         const typename Traits<R>::word* rh, R mass4, double red[3]) {
+    const unsigned n2 = F.n2;
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        cx<R> w[12];
+        odd_pass<R>(n2, h0 + l, in + oR, nullptr, R(1), F, Ainv, w);
+        store_spinor(tmp + oR, n2, h0 + l, w);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned i = h0 + l;
+        cx<R> y[12];
+        even_pass<R, true>(n2, i, in + oR, tmp + oR, R(-0.25), F, mass4, y);
+        store_spinor(out + oR, n2, i, y);
+        if (DOT == 1) {
+            cx<R> h[12];
+            load_spinor(rh + oR, n2, i, h);
+            acc_dot(h, y, red[0], red[1]);
+        } else {
+            cx<R> c[12];
+            load_spinor(in + oR, n2, i, c);
+            acc_dot(y, c, red[0], red[1]);
+            red[2] += acc_nrm(y);
+        }
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R> F,
+                                                             const typename Traits<R>::word* __restrict__ Ainv,
+                                                             const double2* __restrict__ re, double2* __restrict__ xe,
+                                                             BlkInner<R> w, const double* __restrict__ bb,
+                                                             const double* __restrict__ rr, double mass4, double tol,
+                                                             double inner_floor, int maxit, int* iters, int colour,
+                                                             int nrhs) {
+    __shared__ double lds[3 * 16];
+    const BlkIdx k = blk_idx(g, colour, nrhs);
+    const double b2 = bb[k.key], r2 = rr[k.key];
+    if (!(b2 > 0) || !(r2 > tol * tol * b2) || !isfinite(r2)) return;  // uniform over the workgroup
+    const unsigned n2 = F.n2;
+    const size_t oh = (size_t)k.rhs * 12 * n2, oR = (size_t)k.rhs * Traits<R>::NCW * n2;
+    const R m4 = (R)mass4;
+    const double rn = sqrt(r2), sc = 1.0 / rn;
+    double eps = 0.5 * tol * sqrt(b2) / rn;
+    if (eps < inner_floor) eps = inner_floor;
+    double red[3] = {0, 0, 0};
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned i = k.h0 + l;
+        cx<double> a[12];
+        cx<R> q[12], z[12];
+        load_spinor(re + oh, n2, i, a);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            q[c] = mk((R)(sc * a[c].re), (R)(sc * a[c].im));
+            z[c] = mk(R(0), R(0));
+        }
+        store_spinor(w.r + oR, n2, i, q);
+        store_spinor(w.rh + oR, n2, i, q);
+        store_spinor(w.p + oR, n2, i, q);
+        store_spinor(w.e + oR, n2, i, z);
+        red[0] += acc_nrm(q);
+    }
+    block_sum<1>(red, lds);
+    cx<double> rho = mk(red[0], 0.0);
+    const double thr2 = eps * eps * red[0];
+    int it = 0;
+    while (it < maxit) {
+        red[0] = red[1] = red[2] = 0;
+        apply_Mk<R, 1>(g, F, Ainv, k.h0, oR, w.p, w.tmp, w.v, w.rh, m4, red);
+        block_sum<2>(red, lds);
+        if (!(red[0] * red[0] + red[1] * red[1] > 0)) break;
+        const cx<R> alpha = cdiv_r<R>(rho, mk(red[0], red[1]));
+        // s = r - alpha v (kept in r)
+#pragma unroll 1
+        for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+            const unsigned i = k.h0 + l;
+            cx<R> a[12], vv[12];
+            load_spinor(w.r + oR, n2, i, a);
+            load_spinor(w.v + oR, n2, i, vv);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) a[c] = a[c] - alpha * vv[c];
+            store_spinor(w.r + oR, n2, i, a);
+        }
+        __syncthreads();
+        red[0] = red[1] = red[2] = 0;
+        apply_Mk<R, 2>(g, F, Ainv, k.h0, oR, w.r, w.tmp, w.t, nullptr, m4, red);
+        block_sum<3>(red, lds);
+        cx<R> omega = mk(R(0), R(0));
+        if (red[2] > 0) omega = mk((R)(red[0] / red[2]), (R)(red[1] / red[2]));
+        // e += alpha p + omega s ; r = s - omega t ; (rh, r), (r, r)
+        red[0] = red[1] = red[2] = 0;
+#pragma unroll 1
+        for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+            const unsigned i = k.h0 + l;
+            cx<R> ee[12], pp[12], ss[12], tt[12];
+            load_spinor(w.e + oR, n2, i, ee);
+            load_spinor(w.p + oR, n2, i, pp);
+            load_spinor(w.r + oR, n2, i, ss);
+            load_spinor(w.t + oR, n2, i, tt);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                ee[c] = ee[c] + alpha * pp[c] + omega * ss[c];
+                ss[c] = ss[c] - omega * tt[c];
+            }
+            store_spinor(w.e + oR, n2, i, ee);
+            store_spinor(w.r + oR, n2, i, ss);
+            load_spinor(w.rh + oR, n2, i, pp);
+            acc_dot(pp, ss, red[0], red[1]);
+            red[2] += acc_nrm(ss);
+        }
+        block_sum<3>(red, lds);
+        ++it;
+        if (red[2] <= thr2 || !isfinite(red[2])) break;
+        if (omega.re == R(0) && omega.im == R(0)) break;
+        const double d1 = rho.re * rho.re + rho.im * rho.im;
+        if (!(d1 > 0)) break;
+        const cx<double> q = mk((red[0] * rho.re + red[1] * rho.im) / d1, (red[1] * rho.re - red[0] * rho.im) / d1);
+        const double d2 = (double)omega.re * omega.re + (double)omega.im * omega.im;
+        const cx<double> ao = mk(((double)alpha.re * omega.re + (double)alpha.im * omega.im) / d2,
+                                 ((double)alpha.im * omega.re - (double)alpha.re * omega.im) / d2);
+        const cx<R> beta = mk((R)(q.re * ao.re - q.im * ao.im), (R)(q.re * ao.im + q.im * ao.re));
+        rho = mk(red[0], red[1]);
+#pragma unroll 1
+        for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+            const unsigned i = k.h0 + l;
+            cx<R> a[12], pp[12], vv[12];
+            load_spinor(w.r + oR, n2, i, a);
+            load_spinor(w.p + oR, n2, i, pp);
+            load_spinor(w.v + oR, n2, i, vv);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) pp[c] = a[c] + beta * (pp[c] - omega * vv[c]);
+            store_spinor(w.p + oR, n2, i, pp);
+        }
+        __syncthreads();
+    }
+    // x_e += ||r_e|| e in FP64
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
+        const unsigned i = k.h0 + l;
+        cx<R> e[12];
+        cx<double> x[12];
+        load_spinor(w.e + oR, n2, i, e);
+        load_spinor(xe + oh, n2, i, x);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) x[c] = x[c] + mk(rn * (double)e[c].re, rn * (double)e[c].im);
+        store_spinor(xe + oh, n2, i, x);
+    }
+    if (threadIdx.x == 0) iters[k.key] += it;
+}
+
+void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
+                     double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs) {
+    Timed t(e, 2, 0);
+    k_blk_prep<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, bpe, re, xe, to, bb, rr, colour, nrhs);
+}
+void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,
+                      const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs) {
+    Timed t(e, 2, 0);
+    k_blk_resid<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, bpe, xe, re, to, rr, mass4, colour,
+                                                                    nrhs);
+}
+void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
+                      const double2* xe, double2* x, int colour, int nrhs) {
+    Timed t(e, 2, 0);
+    k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
+}
+template <class R>
+void launch_blk_inner(Exec& e, const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
+                      const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,
+                      double mass4, double tol, int maxit, int* iters, int colour, int nrhs) {
+    Timed t(e, 2, 0);
+    BlkInner<R> bw;
+    typedef typename Traits<R>::word W;
+    bw.r = (W*)w[0];
+    bw.rh = (W*)w[1];
+    bw.p = (W*)w[2];
+    bw.v = (W*)w[3];
+    bw.t = (W*)w[4];
+    bw.e = (W*)w[5];
+    bw.tmp = (W*)w[6];
+    k_blk_inner<R><<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(
+        g, F, Ainv, re, xe, bw, bb, rr, mass4, tol, sizeof(R) == 8 ? 0.0 : 2e-6, maxit, iters, colour, nrhs);
+}
+template void launch_blk_inner<double>(Exec&, const Geom&, const EoFields<double>&, const double2*, const double2*,
+                                       double2*, void* const[7], const double*, const double*, double, double, int,
+                                       int*, int, int);
+template void launch_blk_inner<float>(Exec&, const Geom&, const EoFields<float>&, const float4*, const double2*,
+                                      double2*, void* const[7], const double*, const double*, double, double, int,
+                                      int*, int, int);
+
+}  // namespace ddwc

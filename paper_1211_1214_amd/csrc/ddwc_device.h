@@ -2,7 +2,9 @@
 //
 // Internal site order is block-major: site s = ((c * NBc + rank) * Vb) + local,
 // with c the Schwarz colour (black = 0), rank the block's number among the blocks of
-// that colour and local the lexicographic site inside the block.  Black sites are
+// that colour and local the site inside the block: lexicographic, or, when every block
+// extent is even, parity-major (the even sites of the block, then the odd ones, each
+// in lexicographic order) so that even and odd half-vectors are contiguous per block.  Black sites are
 // the first half of every field, and each block's sites are contiguous, so a
 // workgroup that owns one block reads it with unit stride.
 //
@@ -76,9 +78,12 @@ struct Geom {
     int L[4];      // T, L1, L2, L3
     int b[4];      // block extents
     int nb[4];     // blocks per direction
-    int lstr[4];   // stride of a unit step inside a block (local index)
+    int lstr[4];   // lexicographic stride of a unit step inside a block
     int V, Vb, NB, NBc, nb3h;
     int tbc;       // time boundary factor (-1 antiperiodic, +1 periodic)
+    int eo;        // 1 when every block extent is even: sites inside a block are ordered
+                   // parity-major (even sites first), parity = (x0+x1+x2+x3) mod 2
+    int hvb;       // Vb / 2
 };
 
 // Geometry of a T x L1 x L2 x L3 lattice split into blocks blk (extents already validated).
@@ -99,6 +104,8 @@ inline Geom make_geom(const int lat[4], const int blk[4], int time_bc) {
     g.NBc = g.NB / 2;
     g.nb3h = g.nb[3] / 2;
     g.tbc = time_bc;
+    g.eo = (blk[0] % 2 == 0 && blk[1] % 2 == 0 && blk[2] % 2 == 0 && blk[3] % 2 == 0) ? 1 : 0;
+    g.hvb = g.Vb / 2;
     return g;
 }
 
@@ -112,12 +119,20 @@ DDWC_HD Site decode(const Geom& g, int s) {
     Site S;
     int loc = s % g.Vb;
     int B = s / g.Vb;
+    int p = 0;
+    if (g.eo) {
+        // parity-major: loc = p * Vb/2 + (lexicographic index >> 1); rows of even length b3
+        // alternate parity, so the lexicographic index is 2h or 2h + 1
+        p = loc / g.hvb;
+        loc = 2 * (loc - p * g.hvb);
+    }
     S.l[3] = loc % g.b[3];
     loc /= g.b[3];
     S.l[2] = loc % g.b[2];
     loc /= g.b[2];
     S.l[1] = loc % g.b[1];
     S.l[0] = loc / g.b[1];
+    if (g.eo && ((S.l[0] + S.l[1] + S.l[2] + S.l[3]) & 1) != p) S.l[3] += 1;
     S.c = B / g.NBc;
     int r = B % g.NBc;
     int h = r % g.nb3h;
@@ -137,7 +152,9 @@ DDWC_HD int block_base(const Geom& g, const int n[4]) {
 }
 
 DDWC_HD int local_index(const Geom& g, const int l[4]) {
-    return ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
+    const int lex = ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
+    if (!g.eo) return lex;
+    return ((l[0] + l[1] + l[2] + l[3]) & 1) * g.hvb + (lex >> 1);
 }
 
 // Neighbour of site s (decoded as S) one step forward (+1) or backward (-1) in mu.
@@ -149,7 +166,9 @@ DDWC_HD int neighbour(const Geom& g, int s, const Site& S, int mu, bool& inside,
     if (DIR > 0) {
         if (S.l[mu] < g.b[mu] - 1) {
             inside = true;
-            return s + g.lstr[mu];
+            int l[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+            l[mu] += 1;
+            return (s - s % g.Vb) + local_index(g, l);
         }
         inside = false;
         int n[4] = {S.n[0], S.n[1], S.n[2], S.n[3]};
@@ -164,7 +183,9 @@ DDWC_HD int neighbour(const Geom& g, int s, const Site& S, int mu, bool& inside,
     } else {
         if (S.l[mu] > 0) {
             inside = true;
-            return s - g.lstr[mu];
+            int l[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+            l[mu] -= 1;
+            return (s - s % g.Vb) + local_index(g, l);
         }
         inside = false;
         int n[4] = {S.n[0], S.n[1], S.n[2], S.n[3]};
@@ -421,85 +442,98 @@ DDWC_HD int table_entry(const Geom& g, int s, const Site& S, int mu) {
 // Which hops a site operator includes.
 enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 
-// y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops.  `in` points at one RHS,
-// nbr is the neighbour table [8][V].  A neighbour lies in the same Schwarz block exactly
-// when it has the same colour, i.e. lies in the same half of the block-major order.
-// `ndir` is 8; it is a run-time value so that the direction loop stays a loop and only
-// one neighbour spinor and link are live at a time (PIPE: the next direction's loads are
-// issued before the current one is computed).  The hops are summed unscaled (a hop across
-// an antiperiodic time boundary is subtracted) and scaled by -1/2 once.
+// acc = sum over the selected hops of site s of (1 -+ g_mu) W psi(neighbour), unscaled; a
+// hop across an antiperiodic time boundary is subtracted.  The index space has length n
+// (V for full fields, V/2 for even-odd half fields); nbr is its neighbour table [8][n];
+// forward links are read from Uf at s, backward links from Ub at the neighbour.  Both
+// index spaces are colour-major, so a neighbour lies in the same Schwarz block exactly
+// when it lies in the same half.  `ndir` is 8; it is a run-time value so that the
+// direction loop stays a loop and only one neighbour spinor and link are live at a time
+// (PIPE: the next direction's loads are issued before the current one is computed).
+template <class R, int HOPS, bool PIPE>
+DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __restrict__ in,
+                     const cx<R>* __restrict__ Uf, const cx<R>* __restrict__ Ub, const int* __restrict__ nbr,
+                     cx<R> acc[12], int ndir) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));
+    if (HOPS == HOPS_NONE) return;
+    const bool s_black = s < n / 2;
+    if (!PIPE) {
+#pragma unroll 1
+        for (int d = 0; d < ndir; ++d) {
+            const int e = at(nbr + (size_t)d * n, s);
+            const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+            const bool inside = (t < n / 2) == s_black;
+            const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+            if (take) {
+                cx<R> q[12], u[9];
+                load_spinor(in, n, t, q);
+                if (d & 1)
+                    load_link(Ub, n, d >> 1, t, u);
+                else
+                    load_link(Uf, n, d >> 1, s, u);
+                if (e < 0) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) q[c] = -q[c];
+                }
+                hop_dispatch<R>(d, u, q, acc);
+            }
+        }
+    } else {
+        // all eight table entries first, then a software-pipelined direction loop: the
+        // neighbour spinor and link of direction d + 1 are in flight while d is computed
+        int ent[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * n, s);
+        cx<R> q[12], u[9];
+        {
+            const int e = ent[0];
+            load_spinor(in, n, e < 0 ? (unsigned)~e : (unsigned)e, q);
+            load_link(Uf, n, 0, s, u);
+        }
+#pragma unroll 1
+        for (int d = 0; d < ndir; ++d) {
+            int e = ent[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) e = d == k ? ent[k] : e;
+            const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+            const bool inside = (t < n / 2) == s_black;
+            const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
+            cx<R> qn[12], un[9];
+            if (d + 1 < ndir) {
+                int en = ent[1];
+#pragma unroll
+                for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
+                const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
+                load_spinor(in, n, tn, qn);
+                if ((d + 1) & 1)
+                    load_link(Ub, n, (d + 1) >> 1, tn, un);
+                else
+                    load_link(Uf, n, (d + 1) >> 1, s, un);
+            }
+            if (take) {
+                if (e < 0) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) q[c] = -q[c];
+                }
+                hop_dispatch<R>(d, u, q, acc);
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[c] = qn[c];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) u[c] = un[c];
+        }
+    }
+}
+
+// y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops, on full fields.  `in`
+// points at one RHS, nbr is the neighbour table [8][V].
 template <class R, bool DIAG, int HOPS, bool PIPE = false>
 DDWC_HD void site_operator(const Geom& g, unsigned s, const typename Traits<R>::word* __restrict__ in,
                            const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
                            const int* __restrict__ nbr, R mass4, cx<R> y[12], int ndir) {
     const unsigned V = g.V;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) y[c] = mk(R(0), R(0));
-    if (HOPS != HOPS_NONE) {
-        const bool s_black = s < V / 2;
-        if (!PIPE) {
-#pragma unroll 1
-            for (int d = 0; d < ndir; ++d) {
-                const int e = at(nbr + (size_t)d * V, s);
-                const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
-                const bool inside = (t < V / 2) == s_black;
-                const bool take =
-                    HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
-                if (take) {
-                    cx<R> q[12], u[9];
-                    load_spinor(in, V, t, q);
-                    load_link(U, V, d >> 1, (d & 1) ? t : s, u);
-                    if (e < 0) {
-#pragma unroll
-                        for (int c = 0; c < 12; ++c) q[c] = -q[c];
-                    }
-                    hop_dispatch<R>(d, u, q, y);
-                }
-            }
-        } else {
-            // all eight table entries first, then a software-pipelined direction loop: the
-            // neighbour spinor and link of direction d + 1 are in flight while d is computed
-            int ent[8];
-#pragma unroll
-            for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * V, s);
-            cx<R> q[12], u[9];
-            {
-                const int e = ent[0];
-                load_spinor(in, V, e < 0 ? (unsigned)~e : (unsigned)e, q);
-                load_link(U, V, 0, s, u);
-            }
-#pragma unroll 1
-            for (int d = 0; d < ndir; ++d) {
-                int e = ent[0];
-#pragma unroll
-                for (int k = 1; k < 8; ++k) e = d == k ? ent[k] : e;
-                const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
-                const bool inside = (t < V / 2) == s_black;
-                const bool take =
-                    HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
-                cx<R> qn[12], un[9];
-                if (d + 1 < ndir) {
-                    int en = ent[1];
-#pragma unroll
-                    for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
-                    const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
-                    load_spinor(in, V, tn, qn);
-                    load_link(U, V, (d + 1) >> 1, ((d + 1) & 1) ? tn : s, un);
-                }
-                if (take) {
-                    if (e < 0) {
-#pragma unroll
-                        for (int c = 0; c < 12; ++c) q[c] = -q[c];
-                    }
-                    hop_dispatch<R>(d, u, q, y);
-                }
-#pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = qn[c];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) u[c] = un[c];
-            }
-        }
-    }
+    hop_sum<R, HOPS, PIPE>(V, s, in, U, U, nbr, y, ndir);
     if (DIAG) {
         cx<R> c[12];
         load_spinor(in, V, s, c);

@@ -135,6 +135,47 @@ void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, 
 // partials: (x, y) complex and (y, y) per RHS; x may equal y.
 void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs);
 
+// ------------------------------------------------------------------ even-odd (eo.hip)
+// Half-field data of one precision: links, clover and neighbour table of each parity.
+template <class R>
+struct EoFields {
+    unsigned n2;                            // V / 2
+    const cx<R>* U[2];                      // [4][9][n2] links of the sites of parity p
+    const typename Traits<R>::word* K[2];   // clover of the sites of parity p
+    const int* nbr[2];                      // [8][n2] neighbour half indices (other parity)
+};
+
+void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
+                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo);
+void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
+void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs);
+void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);
+// y_p = Ainv (c + alpha H_{p,1-p} x); c may be null, alpha = 0 skips the hops.
+template <class R>
+void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, const typename Traits<R>::word* x,
+                      const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
+                      typename Traits<R>::word* y, int nrhs, int kclass, double bytes);
+// y_p = [A_pp] c + beta H_{p,1-p} t with epilogue epi (0 none, 1 dot(aux, y), 2 dots (y, c), (y, y),
+// 3 residual y = aux - y with ||y||^2).
+template <class R>
+void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, int epi, bool use_a, const typename Traits<R>::word* c,
+                       const typename Traits<R>::word* tv, double beta, double mass4,
+                       const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part, int nrhs,
+                       int kclass, double bytes);
+
+// ------------------------------------------------------------------ even-odd block solver (block_eo.hip)
+int block_eo_threads(const Geom& g);
+void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
+                     double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs);
+void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,
+                      const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs);
+void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
+                      const double2* xe, double2* x, int colour, int nrhs);
+template <class R>
+void launch_blk_inner(Exec& e, const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
+                      const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,
+                      double mass4, double tol, int maxit, int* iters, int colour, int nrhs);
+
 // ------------------------------------------------------------------ block solver (block_solver.hip)
 struct BlockSolveArgs {
     const double2* b;     // FP64 right-hand sides, internal layout

@@ -1,0 +1,248 @@
+// Even-odd preconditioned operator kernels on half fields (see eo.h for the algebra).
+#include "ddwc_internal.h"
+#include "eo.h"
+
+namespace ddwc {
+
+__device__ __forceinline__ int xcd_remap_eo(int i, int n) {
+    if ((n & 7) != 0) return i;
+    return (i & 7) * (n >> 3) + (i >> 3);
+}
+
+// ------------------------------------------------------------------ setup
+__global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const double2* __restrict__ K64,
+                           const int* __restrict__ nbr, cx<double>* __restrict__ Uh64, cx<float>* __restrict__ Uh32,
+                           double2* __restrict__ Kh64, float4* __restrict__ Kh32, int* __restrict__ nbr_eo) {
+    const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= (unsigned)g.V) return;
+    const size_t V = g.V, V2 = g.V / 2;
+    int p;
+    const unsigned i = half_index(g, s, p);
+    for (int mu = 0; mu < 4; ++mu)
+        for (int k = 0; k < 9; ++k) {
+            const cx<double> u = U64[((size_t)mu * 9 + k) * V + s];
+            const size_t o = (((size_t)p * 4 + mu) * 9 + k) * V2 + i;
+            Uh64[o] = u;
+            Uh32[o] = mk((float)u.re, (float)u.im);
+        }
+    double a[72];
+    for (int k = 0; k < 36; ++k) {
+        const double2 w = K64[(size_t)k * V + s];
+        a[2 * k] = w.x;
+        a[2 * k + 1] = w.y;
+        Kh64[((size_t)p * 36 + k) * V2 + i] = w;
+    }
+    for (int k = 0; k < 18; ++k)
+        Kh32[((size_t)p * 18 + k) * V2 + i] =
+            make_float4((float)a[4 * k], (float)a[4 * k + 1], (float)a[4 * k + 2], (float)a[4 * k + 3]);
+    for (int d = 0; d < 8; ++d) nbr_eo[((size_t)p * 8 + d) * V2 + i] = half_entry(g, nbr[(size_t)d * V + s]);
+}
+
+void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
+                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo) {
+    Timed t(e, 4, 0);
+    k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Kh64, Kh32, nbr_eo);
+}
+
+// A_pp^-1 for the sites of parity p of half clover Kp (once per mass).
+__global__ void k_eo_inverse(unsigned V2, const double2* __restrict__ Kp, double mass4, double2* __restrict__ A64,
+                             float4* __restrict__ A32) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V2) return;
+    double a[72], b[72];
+    for (int k = 0; k < 36; ++k) {
+        const double2 w = Kp[(size_t)k * V2 + i];
+        a[2 * k] = w.x;
+        a[2 * k + 1] = w.y;
+    }
+    clover_inverse_site(a, mass4, b);
+    for (int k = 0; k < 36; ++k) A64[(size_t)k * V2 + i] = make_double2(b[2 * k], b[2 * k + 1]);
+    for (int k = 0; k < 18; ++k)
+        A32[(size_t)k * V2 + i] = make_float4((float)b[4 * k], (float)b[4 * k + 1], (float)b[4 * k + 2], (float)b[4 * k + 3]);
+}
+
+void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32) {
+    Timed t(e, 4, 0);
+    k_eo_inverse<<<(V2 + 127) / 128, 128, 0, e.stream>>>(V2, Kp, mass4, A64, A32);
+}
+
+// full FP64 field <-> (even, odd) FP64 half fields
+__global__ void k_eo_split(Geom g, const double2* __restrict__ full, double2* __restrict__ he, double2* __restrict__ ho,
+                           int merge) {
+    const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (s >= (unsigned)g.V) return;
+    const size_t V = g.V, V2 = g.V / 2;
+    int p;
+    const unsigned i = half_index(g, s, p);
+    double2* h = p ? ho : he;
+    for (int c = 0; c < 12; ++c) {
+        if (merge)
+            ((double2*)full)[((size_t)rhs * 12 + c) * V + s] = h[((size_t)rhs * 12 + c) * V2 + i];
+        else
+            h[((size_t)rhs * 12 + c) * V2 + i] = full[((size_t)rhs * 12 + c) * V + s];
+    }
+}
+
+void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs) {
+    Timed t(e, 4, 0);
+    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, he, ho, 0);
+}
+void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs) {
+    Timed t(e, 4, 0);
+    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, (double2*)he, (double2*)ho, 1);
+}
+
+// ------------------------------------------------------------------ operator kernels
+struct EoTile {
+    int tile, rhs;
+};
+__device__ __forceinline__ EoTile eo_tile(int ntiles, int nrhs) {
+    const int L = xcd_remap_eo(blockIdx.x, ntiles * nrhs);
+    EoTile t;
+    t.tile = L / nrhs;
+    t.rhs = L - t.tile * nrhs;
+    return t;
+}
+
+template <int NV>
+__device__ __forceinline__ void eo_partials(double v[NV], double* part, int ntiles, EoTile tr) {
+    __shared__ double lds[NV * 16];
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+        double* p = part + ((size_t)tr.rhs * ntiles + tr.tile) * NPART;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) p[k] = v[k];
+    }
+}
+
+// y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
+// alpha = 0 skips the hops.
+template <class R>
+__global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<R>::word* __restrict__ x,
+                                                  const typename Traits<R>::word* __restrict__ c, R alpha,
+                                                  const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
+                                                  const int* __restrict__ nbrp,
+                                                  const typename Traits<R>::word* __restrict__ Ainv,
+                                                  typename Traits<R>::word* __restrict__ y, int nrhs, int ntiles) {
+    const EoTile tr = eo_tile(ntiles, nrhs);
+    const unsigned i = tr.tile * WG + threadIdx.x;
+    if (i >= n2) return;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * n2;
+    cx<R> acc[12], w[12];
+    if (alpha != R(0))
+        hop_sum<R, HOPS_ALL, true>(n2, i, x + off, Up, Uq, nbrp, acc, 8);
+    else
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = mk(R(0), R(0));
+    if (c) {
+        cx<R> cc[12];
+        load_spinor(c + off, n2, i, cc);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cc[k] + alpha * acc[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = alpha * acc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = mk(R(0), R(0));
+    apply_diag<R>(Ainv, n2, i, R(0), acc, w, R(0));
+    store_spinor(y + off, n2, i, w);
+}
+
+enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
+
+// y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
+// Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
+// RESID: y = aux - y and partial ||y||^2.
+template <class R, int EPI, bool USE_A>
+__global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<R>::word* __restrict__ c,
+                                                   const typename Traits<R>::word* __restrict__ t, R beta,
+                                                   const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
+                                                   const int* __restrict__ nbrp,
+                                                   const typename Traits<R>::word* __restrict__ Kp, R mass4,
+                                                   const typename Traits<R>::word* __restrict__ aux,
+                                                   typename Traits<R>::word* __restrict__ y, double* part, int nrhs,
+                                                   int ntiles) {
+    const EoTile tr = eo_tile(ntiles, nrhs);
+    const unsigned i = tr.tile * WG + threadIdx.x;
+    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * n2;
+    double v[3] = {0, 0, 0};
+    if (i < n2) {
+        cx<R> acc[12], cc[12];
+        hop_sum<R, HOPS_ALL, true>(n2, i, t + off, Up, Uq, nbrp, acc, 8);
+        load_spinor(c + off, n2, i, cc);
+        if (USE_A) {
+            apply_diag<R>(Kp, n2, i, mass4, cc, acc, beta);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = cc[k] + beta * acc[k];
+        }
+        if (EPI == EOE_RESID) {
+            cx<R> b[12];
+            load_spinor(aux + off, n2, i, b);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = b[k] - acc[k];
+            v[0] = acc_nrm(acc);
+        }
+        store_spinor(y + off, n2, i, acc);
+        if (EPI == EOE_DOT) {
+            cx<R> w[12];
+            load_spinor(aux + off, n2, i, w);
+            acc_dot(w, acc, v[0], v[1]);
+        }
+        if (EPI == EOE_DOT2) {
+            acc_dot(acc, cc, v[0], v[1]);
+            v[2] = acc_nrm(acc);
+        }
+    }
+    if (EPI == EOE_DOT) eo_partials<2>(v, part, ntiles, tr);
+    if (EPI == EOE_DOT2) eo_partials<3>(v, part, ntiles, tr);
+    if (EPI == EOE_RESID) eo_partials<1>(v, part, ntiles, tr);
+}
+
+template <class R>
+void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, const typename Traits<R>::word* x,
+                      const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
+                      typename Traits<R>::word* y, int nrhs, int kclass, double bytes) {
+    Timed t(e, kclass, bytes);
+    const int nt = tiles_of(F.n2);
+    k_eo_hopinv<R><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y, nrhs,
+                                                   nt);
+}
+
+template <class R>
+void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, int epi, bool use_a, const typename Traits<R>::word* c,
+                       const typename Traits<R>::word* tv, double beta, double mass4,
+                       const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part, int nrhs,
+                       int kclass, double bytes) {
+    Timed tm(e, kclass, bytes);
+    const int nt = tiles_of(F.n2);
+    const int ng = nt * nrhs;
+#define EOL(EP, UA)                                                                                               \
+    k_eo_diaghop<R, EP, UA><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], \
+                                                     (R)mass4, aux, y, part, nrhs, nt)
+    if (use_a) {
+        switch (epi) {
+            case EOE_DOT: EOL(EOE_DOT, true); break;
+            case EOE_DOT2: EOL(EOE_DOT2, true); break;
+            case EOE_RESID: EOL(EOE_RESID, true); break;
+            default: EOL(EOE_NONE, true); break;
+        }
+    } else {
+        EOL(EOE_NONE, false);
+    }
+#undef EOL
+}
+
+#define EO_INST(R)                                                                                                 \
+    template void launch_eo_hopinv<R>(Exec&, const EoFields<R>&, int, const Traits<R>::word*,                      \
+                                      const Traits<R>::word*, double, const Traits<R>::word*, Traits<R>::word*, int, \
+                                      int, double);                                                                \
+    template void launch_eo_diaghop<R>(Exec&, const EoFields<R>&, int, int, bool, const Traits<R>::word*,          \
+                                       const Traits<R>::word*, double, double, const Traits<R>::word*,             \
+                                       Traits<R>::word*, double*, int, int, double);
+EO_INST(double)
+EO_INST(float)
+
+}  // namespace ddwc

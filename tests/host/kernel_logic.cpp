@@ -65,3 +65,76 @@ extern "C" int host_apply(const int* lat, const int* blk, int tbc, double csw, c
     }
     return 0;
 }
+
+// Even-odd operator on the host with the library's own helpers: y_e = Mee x_e with
+// Mee = A_ee - 1/4 H_eo A_oo^-1 H_oe, half fields built as the setup kernel builds them.
+// Output in canonical layout, zero on odd sites.  Requires every block extent even.
+#include "../../paper_1211_1214_amd/csrc/eo.h"
+extern "C" int host_eo_apply(const int* lat, const int* blk, int tbc, double csw, const double* links_canon,
+                             const double* in_canon, double kappa, double* out_canon) {
+    Geom g = make_geom(lat, blk, tbc);
+    if (!g.eo) return -1;
+    const int V = g.V, n2 = V / 2;
+    std::vector<cx<double>> U((size_t)36 * V);
+    std::vector<int> can(V), nbr((size_t)8 * V);
+    for (int s = 0; s < V; ++s) {
+        const Site S = decode(g, s);
+        can[s] = canonical_index(g, S);
+        for (int mu = 0; mu < 4; ++mu) {
+            for (int k = 0; k < 9; ++k) {
+                const double* src = links_canon + 2 * (((size_t)mu * V + can[s]) * 9 + k);
+                U[((size_t)mu * 9 + k) * V + s] = mk(src[0], src[1]);
+            }
+            nbr[(size_t)(2 * mu) * V + s] = table_entry<+1>(g, s, S, mu);
+            nbr[(size_t)(2 * mu + 1) * V + s] = table_entry<-1>(g, s, S, mu);
+        }
+    }
+    const double mass4 = 4.0 + (1.0 / (2.0 * kappa) - 4.0);
+    std::vector<cx<double>> Uh((size_t)2 * 36 * n2);
+    std::vector<double2> Kh((size_t)2 * 36 * n2), Ah((size_t)36 * n2), xe((size_t)12 * n2), xo((size_t)12 * n2, make_double2(0, 0));
+    std::vector<int> nh((size_t)2 * 8 * n2);
+    for (int s = 0; s < V; ++s) {
+        int p;
+        const unsigned i = half_index(g, s, p);
+        if (full_index(g, i, p) != (unsigned)s) return -2;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int k = 0; k < 9; ++k) Uh[(((size_t)p * 4 + mu) * 9 + k) * n2 + i] = U[((size_t)mu * 9 + k) * V + s];
+        double a[72], b[72];
+        clover_site(g, U.data(), csw, s, a);
+        for (int k = 0; k < 36; ++k) Kh[((size_t)p * 36 + k) * n2 + i] = make_double2(a[2 * k], a[2 * k + 1]);
+        if (p == 1) {
+            clover_inverse_site(a, mass4, b);
+            for (int k = 0; k < 36; ++k) Ah[(size_t)k * n2 + i] = make_double2(b[2 * k], b[2 * k + 1]);
+        }
+        for (int d = 0; d < 8; ++d) nh[((size_t)p * 8 + d) * n2 + i] = half_entry(g, nbr[(size_t)d * V + s]);
+        if (p == 0)
+            for (int c = 0; c < 12; ++c) {
+                const double* src = in_canon + 2 * ((size_t)can[s] * 12 + c);
+                xe[(size_t)c * n2 + i] = make_double2(src[0], src[1]);
+            }
+    }
+    const cx<double>* U0 = Uh.data();
+    const cx<double>* U1 = Uh.data() + (size_t)36 * n2;
+    // t_o = A_oo^-1 H_oe x_e
+    for (int i = 0; i < n2; ++i) {
+        cx<double> acc[12], w[12];
+        hop_sum<double, HOPS_ALL, false>(n2, i, xe.data(), U1, U0, nh.data() + (size_t)8 * n2, acc, 8);
+        for (int c = 0; c < 12; ++c) w[c] = mk(0.0, 0.0);
+        apply_diag<double>(Ah.data(), n2, i, 0.0, acc, w, 0.0);
+        store_spinor(xo.data(), n2, i, w);
+    }
+    for (size_t k = 0; k < (size_t)24 * V; ++k) out_canon[k] = 0;
+    // y_e = A_ee x_e - 1/4 H_eo t_o
+    for (int i = 0; i < n2; ++i) {
+        cx<double> acc[12], c[12];
+        hop_sum<double, HOPS_ALL, false>(n2, i, xo.data(), U0, U1, nh.data(), acc, 8);
+        load_spinor(xe.data(), n2, i, c);
+        apply_diag<double>(Kh.data(), n2, i, mass4, c, acc, -0.25);
+        const int s = can[full_index(g, i, 0)];
+        for (int k = 0; k < 12; ++k) {
+            out_canon[2 * ((size_t)s * 12 + k)] = acc[k].re;
+            out_canon[2 * ((size_t)s * 12 + k) + 1] = acc[k].im;
+        }
+    }
+    return 0;
+}

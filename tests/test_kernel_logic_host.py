@@ -78,3 +78,28 @@ def test_host_clover_packing(L):
             A[(iu[1], iu[0])] = np.conj(A[iu])
             assert np.abs(A - C[x][6 * b:6 * b + 6, 6 * b:6 * b + 6]).max() < 1e-15
         assert np.abs(C[x][:6, 6:]).max() == 0
+
+
+@pytest.mark.parametrize("lat,blk,tbc", [((4, 4, 4, 4), (2, 2, 2, 2), -1), ((8, 4, 4, 8), (2, 2, 2, 4), 1)])
+def test_host_even_odd_operator(L, lat, blk, tbc):
+    """Mee = A_ee - D_eo A_oo^-1 D_oe on sites of even parity (x0+x1+x2+x3 even), from the
+    library's half-field helpers, against the oracle's assembled operator."""
+    import scipy.sparse.linalg as sla
+    from oracle import lattice as lt
+    P = ctypes.c_void_p
+    L.host_eo_apply.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_double, P]
+    U = inputs.make_links(lat, 0.3, 6)
+    psi = inputs.make_spinor(lat, 9)
+    out = np.zeros_like(psi)
+    rc = L.host_eo_apply((ctypes.c_int * 4)(*lat), (ctypes.c_int * 4)(*blk), tbc, 1.0, U.ctypes.data,
+                         psi.ctypes.data, 0.1213, out.ctypes.data)
+    assert rc == 0
+    D = dirac.dirac(U, lat, dirac.mass(0.1213), 1.0, tbc).tocsc()
+    par = lt.coords(lat).sum(axis=1) % 2
+    ev = (12 * np.nonzero(par == 0)[0][:, None] + np.arange(12)).ravel()
+    od = (12 * np.nonzero(par == 1)[0][:, None] + np.arange(12)).ravel()
+    x = psi.reshape(-1)
+    want = D[ev][:, ev] @ x[ev] - D[ev][:, od] @ sla.spsolve(D[od][:, od], D[od][:, ev] @ x[ev])
+    got = out.reshape(-1)
+    assert np.abs(got[ev] - want).max() < 1e-12 * np.abs(want).max()
+    assert np.all(got[od] == 0)

@@ -348,19 +348,19 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
         }
         HC(hipMemcpyAsync(scale, h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
         HC(hipMemcpyAsync(thr, h_thr, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
-        launch_bicg_init<R>(ex, g, r64, scale, r, rh, p, xR, part, nrhs);
+        launch_bicg_init<R>(ex, g.V, false, r64, scale, r, rh, p, xR, part, nrhs);
         launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_INIT, thr);
         int it = 0;
         while (total < maxit) {
             for (int k = 0; k < poll && total < maxit; ++k, ++it, ++total) {
                 launch_dslash_dot<R>(ex, g, U, K, mass4, p, v, rh, part, nrhs, kcl, dbytes + rb);
                 launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_ALPHA, nullptr);
-                launch_bicg_s<R>(ex, g, st, r, v, s, nrhs);
+                launch_bicg_s<R>(ex, g.V, false, st, r, v, s, nrhs);
                 launch_dslash_dot2<R>(ex, g, U, K, mass4, s, t, part, nrhs, kcl, dbytes);
                 launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_OMEGA, nullptr);
-                launch_bicg_xr<R>(ex, g, st, xR, p, s, t, rh, r, part, nrhs);
+                launch_bicg_xr<R>(ex, g.V, false, st, xR, p, s, t, rh, r, part, nrhs);
                 launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_BETA, nullptr);
-                launch_bicg_p<R>(ex, g, st, r, v, p, nrhs);
+                launch_bicg_p<R>(ex, g.V, false, st, r, v, p, nrhs);
             }
             HC(hipGetLastError());
             HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
@@ -369,7 +369,7 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
             for (int k = 0; k < nrhs; ++k) any = any || h_st[k].active;
             if (!any) break;
         }
-        launch_accumulate<R>(ex, g, xR, scale, x64, nrhs);
+        launch_accumulate<R>(ex, g.V, false, xR, scale, x64, nrhs);
         launch_residual<double>(ex, g, C->U64, C->K64, mass4, x64, b64, r64, part, nrhs, DDWC_K_DSLASH64,
                                 ddwc_dslash_bytes(C, nrhs, DDWC_FP64) + (double)nrhs * g.V * 192.0);
         launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
@@ -466,6 +466,9 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     gh.V = (int)n2;
     const int nt = tiles_of(n2);
     const int ntf = tiles_of(g.V);
+    // precision-R fields RHS-innermost: the RHS of a site share its links, clover and table
+    const bool ri = nrhs > 1 && nrhs <= WG;
+    const int ntR = vector_tiles(n2, nrhs, ri);
     const double mass4 = 4.0 + mass;
     const double2* A64;
     const float4* A32;
@@ -497,7 +500,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     CK(ws_t(C, pre + "t", hwR, &t));
     CK(ws_t(C, pre + "x", hwR, &xR));
     CK(ws_t(C, pre + "tmp", hwR, &tmp));
-    CK(ws_t(C, "g_part", (size_t)ntf * nrhs * NPART, &part));
+    CK(ws_t(C, "g_part", (size_t)(ntf > ntR ? ntf : ntR) * nrhs * NPART, &part));
     CK(ws_t(C, "g_sums", (size_t)nrhs * NPART, &sums));
     CK(ws_t(C, "g_scale", (size_t)nrhs, &scale));
     CK(ws_t(C, "g_thr", (size_t)nrhs, &thr));
@@ -523,8 +526,8 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     }
     // b'_e = b_e + 1/2 H_eo A_oo^-1 b_o ; x_e = 0 ; r_e = b'_e
     launch_eo_split(ex, g, b64, be, bo, nrhs);
-    launch_eo_hopinv<double>(ex, F64, 1, nullptr, bo, 0.0, A64, to, nrhs, DDWC_K_OTHER, 0);
-    launch_eo_diaghop<double>(ex, F64, 0, 0, false, be, to, 0.5, 0.0, nullptr, bpe, nullptr, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_hopinv<double>(ex, F64, 1, false, nullptr, bo, 0.0, A64, to, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_diaghop<double>(ex, F64, 0, false, 0, false, be, to, 0.5, 0.0, nullptr, bpe, nullptr, nrhs, DDWC_K_OTHER, 0);
     HC(hipMemsetAsync(xe, 0, sizeof(double2) * hw64, sm));
     HC(hipMemcpyAsync(re, bpe, sizeof(double2) * hw64, hipMemcpyDeviceToDevice, sm));
     launch_dots(ex, gh, re, re, part, nrhs);
@@ -537,8 +540,8 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     int total = 0, nout = 0;
     bool converged = false;
     auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
-        launch_eo_hopinv<R>(ex, FR, 1, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
-        launch_eo_diaghop<R>(ex, FR, 0, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
+        launch_eo_hopinv<R>(ex, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
+        launch_eo_diaghop<R>(ex, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
                              hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
     };
     while (true) {
@@ -560,18 +563,18 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         }
         HC(hipMemcpyAsync(scale, h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
         HC(hipMemcpyAsync(thr, h_thr, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
-        launch_bicg_init<R>(ex, gh, re, scale, r, rh, p, xR, part, nrhs);
-        launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_INIT, thr);
+        launch_bicg_init<R>(ex, n2, ri, re, scale, r, rh, p, xR, part, nrhs);
+        launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_INIT, thr);
         while (total < maxit) {
             for (int k = 0; k < poll && total < maxit; ++k, ++total) {
                 apply_M(p, v, 1, rh);
-                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_ALPHA, nullptr);
-                launch_bicg_s<R>(ex, gh, st, r, v, s, nrhs);
+                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_ALPHA, nullptr);
+                launch_bicg_s<R>(ex, n2, ri, st, r, v, s, nrhs);
                 apply_M(s, t, 2, nullptr);
-                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_OMEGA, nullptr);
-                launch_bicg_xr<R>(ex, gh, st, xR, p, s, t, rh, r, part, nrhs);
-                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_BETA, nullptr);
-                launch_bicg_p<R>(ex, gh, st, r, v, p, nrhs);
+                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_OMEGA, nullptr);
+                launch_bicg_xr<R>(ex, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
+                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
+                launch_bicg_p<R>(ex, n2, ri, st, r, v, p, nrhs);
             }
             HC(hipGetLastError());
             HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
@@ -580,10 +583,10 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
             for (int k = 0; k < nrhs; ++k) any = any || h_st[k].active;
             if (!any) break;
         }
-        launch_accumulate<R>(ex, gh, xR, scale, xe, nrhs);
+        launch_accumulate<R>(ex, n2, ri, xR, scale, xe, nrhs);
         // r_e = b'_e - Mee x_e in FP64
-        launch_eo_hopinv<double>(ex, F64, 1, xe, nullptr, 1.0, A64, to, nrhs, DDWC_K_DSLASH64, 0);
-        launch_eo_diaghop<double>(ex, F64, 0, 3, true, xe, to, -0.25, mass4, bpe, re, part, nrhs, DDWC_K_DSLASH64, 0);
+        launch_eo_hopinv<double>(ex, F64, 1, false, xe, nullptr, 1.0, A64, to, nrhs, DDWC_K_DSLASH64, 0);
+        launch_eo_diaghop<double>(ex, F64, 0, false, 3, true, xe, to, -0.25, mass4, bpe, re, part, nrhs, DDWC_K_DSLASH64, 0);
         launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
         HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
         HC(hipStreamSynchronize(sm));
@@ -593,7 +596,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         }
     }
     // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e), x = (x_e, x_o)
-    launch_eo_hopinv<double>(ex, F64, 1, xe, bo, 0.5, A64, xo, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_hopinv<double>(ex, F64, 1, false, xe, bo, 0.5, A64, xo, nrhs, DDWC_K_OTHER, 0);
     launch_eo_merge(ex, g, xe, xo, x64, nrhs);
     HC(hipGetLastError());
     double worst = 0;

@@ -450,10 +450,14 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // when it lies in the same half.  `ndir` is 8; it is a run-time value so that the
 // direction loop stays a loop and only one neighbour spinor and link are live at a time
 // (PIPE: the next direction's loads are issued before the current one is computed).
+//
+// Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
+// component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).
 template <class R, int HOPS, bool PIPE>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __restrict__ in,
                      const cx<R>* __restrict__ Uf, const cx<R>* __restrict__ Ub, const int* __restrict__ nbr,
-                     cx<R> acc[12], int ndir) {
+                     cx<R> acc[12], int ndir, unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
+    if (sstride == 0) sstride = n;
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));
     if (HOPS == HOPS_NONE) return;
@@ -467,7 +471,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __r
             const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
             if (take) {
                 cx<R> q[12], u[9];
-                load_spinor(in, n, t, q);
+                load_spinor(in, sstride, t * smul + sadd, q);
                 if (d & 1)
                     load_link(Ub, n, d >> 1, t, u);
                 else
@@ -488,7 +492,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __r
         cx<R> q[12], u[9];
         {
             const int e = ent[0];
-            load_spinor(in, n, e < 0 ? (unsigned)~e : (unsigned)e, q);
+            load_spinor(in, sstride, (e < 0 ? (unsigned)~e : (unsigned)e) * smul + sadd, q);
             load_link(Uf, n, 0, s, u);
         }
 #pragma unroll 1
@@ -505,7 +509,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __r
 #pragma unroll
                 for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
-                load_spinor(in, n, tn, qn);
+                load_spinor(in, sstride, tn * smul + sadd, qn);
                 if ((d + 1) & 1)
                     load_link(Ub, n, (d + 1) >> 1, tn, un);
                 else
@@ -567,6 +571,31 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
         double t = 0;
         for (int w = 0; w < nw; ++w) t += lds[k * 16 + w];
         v[k] = t;
+    }
+}
+
+// Per-RHS partial sums of a workgroup whose thread j holds values of RHS (g0 + j) mod nrhs
+// (RHS-innermost work items): thread r < nrhs sums its RHS in a fixed order and writes
+// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= 256.
+template <int NV>
+__device__ __forceinline__ void seg_partials(const double v[NV], double* part, int ntiles, int tile, unsigned g0,
+                                             int nrhs, int stride) {
+    __shared__ double lds[NV][256];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+        const int r = threadIdx.x;
+        const int j0 = (int)((r + nrhs - (int)(g0 % (unsigned)nrhs)) % nrhs);
+        double acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = 0;
+        for (int j = j0; j < (int)blockDim.x; j += nrhs)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k] += lds[k][j];
+        double* p = part + ((size_t)r * ntiles + tile) * stride;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) p[k] = acc[k];
     }
 }
 

@@ -103,25 +103,28 @@ template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
                 typename Traits<R>::word* out, int nrhs, int to_colour);
 
-// BiCGStab vector kernels (nrhs multi-vectors, per-RHS scalars in st).
+// BiCGStab vector kernels on fields of n sites, nrhs RHS, per-RHS scalars in st.  ri selects
+// the RHS-innermost layout [NCW][n][nrhs] for the precision-R fields (else [nrhs][NCW][n]);
+// FP64 fields (r64, x64) are always RHS-major.  Partial sums use vector_tiles() tiles per RHS.
+int vector_tiles(unsigned n, int nrhs, bool ri);
 template <class R>
-void launch_bicg_init(Exec& e, const Geom& g, const double2* r64, const double* scale,
+void launch_bicg_init(Exec& e, unsigned n, bool ri, const double2* r64, const double* scale,
                       typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
                       typename Traits<R>::word* x, double* part, int nrhs);
 template <class R>
-void launch_bicg_s(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
                    const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs);
 template <class R>
-void launch_bicg_xr(Exec& e, const Geom& g, const BiState* st, typename Traits<R>::word* x,
+void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<R>::word* x,
                     const typename Traits<R>::word* p, const typename Traits<R>::word* s,
                     const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
                     typename Traits<R>::word* r, double* part, int nrhs);
 template <class R>
-void launch_bicg_p(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
                    const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs);
-// x64 += (1/scale) * x_R (per RHS); only RHS with active_mask set are touched.
+// x64 += (1/scale) * x_R per RHS (RHS with scale 0 untouched).
 template <class R>
-void launch_accumulate(Exec& e, const Geom& g, const typename Traits<R>::word* x, const double* scale,
+void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<R>::word* x, const double* scale,
                        double2* x64, int nrhs);
 
 // Sums partials per RHS in a fixed order and applies the BiCGStab stage update.
@@ -150,15 +153,16 @@ void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double
 void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
 void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs);
 void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);
-// y_p = Ainv (c + alpha H_{p,1-p} x); c may be null, alpha = 0 skips the hops.
+// y_p = Ainv (c + alpha H_{p,1-p} x); c may be null, alpha = 0 skips the hops.  ri: the fields
+// are RHS-innermost (as for the vector kernels).
 template <class R>
-void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, const typename Traits<R>::word* x,
+void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, bool ri, const typename Traits<R>::word* x,
                       const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
                       typename Traits<R>::word* y, int nrhs, int kclass, double bytes);
 // y_p = [A_pp] c + beta H_{p,1-p} t with epilogue epi (0 none, 1 dot(aux, y), 2 dots (y, c), (y, y),
 // 3 residual y = aux - y with ||y||^2).
 template <class R>
-void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, int epi, bool use_a, const typename Traits<R>::word* c,
+void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, bool ri, int epi, bool use_a, const typename Traits<R>::word* c,
                        const typename Traits<R>::word* tv, double beta, double mass4,
                        const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part, int nrhs,
                        int kclass, double bytes);

@@ -1,13 +1,9 @@
 // Even-odd preconditioned operator kernels on half fields (see eo.h for the algebra).
 #include "ddwc_internal.h"
 #include "eo.h"
+#include "vec_items.h"
 
 namespace ddwc {
-
-__device__ __forceinline__ int xcd_remap_eo(int i, int n) {
-    if ((n & 7) != 0) return i;
-    return (i & 7) * (n >> 3) + (i >> 3);
-}
 
 // ------------------------------------------------------------------ setup
 __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const double2* __restrict__ K64,
@@ -94,50 +90,30 @@ void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* h
 }
 
 // ------------------------------------------------------------------ operator kernels
-struct EoTile {
-    int tile, rhs;
-};
-__device__ __forceinline__ EoTile eo_tile(int ntiles, int nrhs) {
-    const int L = xcd_remap_eo(blockIdx.x, ntiles * nrhs);
-    EoTile t;
-    t.tile = L / nrhs;
-    t.rhs = L - t.tile * nrhs;
-    return t;
-}
-
-template <int NV>
-__device__ __forceinline__ void eo_partials(double v[NV], double* part, int ntiles, EoTile tr) {
-    __shared__ double lds[NV * 16];
-    block_sum<NV>(v, lds);
-    if (threadIdx.x == 0) {
-        double* p = part + ((size_t)tr.rhs * ntiles + tr.tile) * NPART;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) p[k] = v[k];
-    }
-}
+// Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the
+// RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
 // y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
 // alpha = 0 skips the hops.
-template <class R>
+template <class R, bool RI>
 __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<R>::word* __restrict__ x,
                                                   const typename Traits<R>::word* __restrict__ c, R alpha,
                                                   const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
                                                   const int* __restrict__ nbrp,
                                                   const typename Traits<R>::word* __restrict__ Ainv,
                                                   typename Traits<R>::word* __restrict__ y, int nrhs, int ntiles) {
-    const EoTile tr = eo_tile(ntiles, nrhs);
-    const unsigned i = tr.tile * WG + threadIdx.x;
-    if (i >= n2) return;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * n2;
-    cx<R> acc[12], w[12];
+    const VItem it = vitem<RI>(n2, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<RI, R> w(n2, nrhs, it.i, it.r);
+    cx<R> acc[12], out[12];
     if (alpha != R(0))
-        hop_sum<R, HOPS_ALL, true>(n2, i, x + off, Up, Uq, nbrp, acc, 8);
+        hop_sum<R, HOPS_ALL, true>(n2, it.i, x + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
     else
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = mk(R(0), R(0));
     if (c) {
         cx<R> cc[12];
-        load_spinor(c + off, n2, i, cc);
+        load_spinor(c + w.base, w.stride, w.idx, cc);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cc[k] + alpha * acc[k];
     } else {
@@ -145,9 +121,9 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
         for (int k = 0; k < 12; ++k) acc[k] = alpha * acc[k];
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = mk(R(0), R(0));
-    apply_diag<R>(Ainv, n2, i, R(0), acc, w, R(0));
-    store_spinor(y + off, n2, i, w);
+    for (int k = 0; k < 12; ++k) out[k] = mk(R(0), R(0));
+    apply_diag<R>(Ainv, n2, it.i, R(0), acc, out, R(0));
+    store_spinor(y + w.base, w.stride, w.idx, out);
 }
 
 enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
@@ -155,7 +131,7 @@ enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
 // y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
 // Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
 // RESID: y = aux - y and partial ||y||^2.
-template <class R, int EPI, bool USE_A>
+template <class R, int EPI, bool USE_A, bool RI>
 __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<R>::word* __restrict__ c,
                                                    const typename Traits<R>::word* __restrict__ t, R beta,
                                                    const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
@@ -164,82 +140,92 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
                                                    const typename Traits<R>::word* __restrict__ aux,
                                                    typename Traits<R>::word* __restrict__ y, double* part, int nrhs,
                                                    int ntiles) {
-    const EoTile tr = eo_tile(ntiles, nrhs);
-    const unsigned i = tr.tile * WG + threadIdx.x;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * n2;
+    const VItem it = vitem<RI>(n2, nrhs, ntiles);
     double v[3] = {0, 0, 0};
-    if (i < n2) {
+    if (it.ok) {
+        const VView<RI, R> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
-        hop_sum<R, HOPS_ALL, true>(n2, i, t + off, Up, Uq, nbrp, acc, 8);
-        load_spinor(c + off, n2, i, cc);
+        hop_sum<R, HOPS_ALL, true>(n2, it.i, t + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
+        load_spinor(c + w.base, w.stride, w.idx, cc);
         if (USE_A) {
-            apply_diag<R>(Kp, n2, i, mass4, cc, acc, beta);
+            apply_diag<R>(Kp, n2, it.i, mass4, cc, acc, beta);
         } else {
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = cc[k] + beta * acc[k];
         }
         if (EPI == EOE_RESID) {
             cx<R> b[12];
-            load_spinor(aux + off, n2, i, b);
+            load_spinor(aux + w.base, w.stride, w.idx, b);
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = b[k] - acc[k];
             v[0] = acc_nrm(acc);
         }
-        store_spinor(y + off, n2, i, acc);
+        store_spinor(y + w.base, w.stride, w.idx, acc);
         if (EPI == EOE_DOT) {
-            cx<R> w[12];
-            load_spinor(aux + off, n2, i, w);
-            acc_dot(w, acc, v[0], v[1]);
+            cx<R> q[12];
+            load_spinor(aux + w.base, w.stride, w.idx, q);
+            acc_dot(q, acc, v[0], v[1]);
         }
         if (EPI == EOE_DOT2) {
             acc_dot(acc, cc, v[0], v[1]);
             v[2] = acc_nrm(acc);
         }
     }
-    if (EPI == EOE_DOT) eo_partials<2>(v, part, ntiles, tr);
-    if (EPI == EOE_DOT2) eo_partials<3>(v, part, ntiles, tr);
-    if (EPI == EOE_RESID) eo_partials<1>(v, part, ntiles, tr);
+    if (EPI == EOE_DOT) vpartials<2, RI>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_DOT2) vpartials<3, RI>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_RESID) vpartials<1, RI>(v, part, ntiles, it, nrhs);
 }
 
 template <class R>
-void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, const typename Traits<R>::word* x,
+void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, bool ri, const typename Traits<R>::word* x,
                       const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
                       typename Traits<R>::word* y, int nrhs, int kclass, double bytes) {
     Timed t(e, kclass, bytes);
-    const int nt = tiles_of(F.n2);
-    k_eo_hopinv<R><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y, nrhs,
-                                                   nt);
+    const int nt = vector_tiles(F.n2, nrhs, ri);
+    if (ri)
+        k_eo_hopinv<R, true><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y,
+                                                      nrhs, nt);
+    else
+        k_eo_hopinv<R, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
+                                                              Ainv, y, nrhs, nt);
 }
 
 template <class R>
-void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, int epi, bool use_a, const typename Traits<R>::word* c,
-                       const typename Traits<R>::word* tv, double beta, double mass4,
-                       const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part, int nrhs,
-                       int kclass, double bytes) {
+void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, bool ri, int epi, bool use_a,
+                       const typename Traits<R>::word* c, const typename Traits<R>::word* tv, double beta,
+                       double mass4, const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part,
+                       int nrhs, int kclass, double bytes) {
     Timed tm(e, kclass, bytes);
-    const int nt = tiles_of(F.n2);
-    const int ng = nt * nrhs;
-#define EOL(EP, UA)                                                                                               \
-    k_eo_diaghop<R, EP, UA><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], \
-                                                     (R)mass4, aux, y, part, nrhs, nt)
-    if (use_a) {
-        switch (epi) {
-            case EOE_DOT: EOL(EOE_DOT, true); break;
-            case EOE_DOT2: EOL(EOE_DOT2, true); break;
-            case EOE_RESID: EOL(EOE_RESID, true); break;
-            default: EOL(EOE_NONE, true); break;
-        }
-    } else {
-        EOL(EOE_NONE, false);
+    const int nt = vector_tiles(F.n2, nrhs, ri);
+    const int ng = ri ? nt : nt * nrhs;
+#define EOL(EP, UA, RIV)                                                                                            \
+    k_eo_diaghop<R, EP, UA, RIV><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p],       \
+                                                          F.K[p], (R)mass4, aux, y, part, nrhs, nt)
+#define EOSW(RIV)                                            \
+    if (use_a) {                                             \
+        switch (epi) {                                       \
+            case EOE_DOT: EOL(EOE_DOT, true, RIV); break;    \
+            case EOE_DOT2: EOL(EOE_DOT2, true, RIV); break;  \
+            case EOE_RESID: EOL(EOE_RESID, true, RIV); break; \
+            default: EOL(EOE_NONE, true, RIV); break;        \
+        }                                                    \
+    } else {                                                 \
+        EOL(EOE_NONE, false, RIV);                           \
     }
+    if (ri) {
+        EOSW(true)
+    } else {
+        EOSW(false)
+    }
+#undef EOSW
 #undef EOL
 }
 
 #define EO_INST(R)                                                                                                 \
-    template void launch_eo_hopinv<R>(Exec&, const EoFields<R>&, int, const Traits<R>::word*,                      \
+    template void launch_eo_hopinv<R>(Exec&, const EoFields<R>&, int, bool, const Traits<R>::word*,                \
                                       const Traits<R>::word*, double, const Traits<R>::word*, Traits<R>::word*, int, \
                                       int, double);                                                                \
-    template void launch_eo_diaghop<R>(Exec&, const EoFields<R>&, int, int, bool, const Traits<R>::word*,          \
+    template void launch_eo_diaghop<R>(Exec&, const EoFields<R>&, int, bool, int, bool, const Traits<R>::word*,    \
                                        const Traits<R>::word*, double, double, const Traits<R>::word*,             \
                                        Traits<R>::word*, double*, int, int, double);
 EO_INST(double)

@@ -8,39 +8,12 @@
 // blocks stay in the same L2.
 #include "ddwc_internal.h"
 #include "clover_build.h"
+#include "vec_items.h"
 
 namespace ddwc {
 
 // Operator kernels are memory bound: ask for at least 4 waves per SIMD (<= 128 VGPRs).
 #define DDWC_OCC
-
-__device__ __forceinline__ int xcd_remap(int i, int n) {
-    if ((n & 7) != 0) return i;
-    return (i & 7) * (n >> 3) + (i >> 3);
-}
-
-struct TileRhs {
-    int tile, rhs;
-};
-
-__device__ __forceinline__ TileRhs tile_rhs(int ntiles, int nrhs) {
-    int L = xcd_remap(blockIdx.x, ntiles * nrhs);
-    TileRhs t;
-    t.tile = L / nrhs;
-    t.rhs = L - t.tile * nrhs;
-    return t;
-}
-
-template <int NV>
-__device__ __forceinline__ void write_partials(double v[NV], double* part, int ntiles, TileRhs tr) {
-    __shared__ double lds[NV * 16];
-    block_sum<NV>(v, lds);
-    if (threadIdx.x == 0) {
-        double* p = part + ((size_t)tr.rhs * ntiles + tr.tile) * NPART;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) p[k] = v[k];
-    }
-}
 
 // ------------------------------------------------------------------ conversions
 __global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<double>* __restrict__ U64,
@@ -257,54 +230,52 @@ __device__ __forceinline__ cx<R> cxs(const double* a) {
     return mk((R)a[0], (R)a[1]);
 }
 
-template <class R>
-__global__ __launch_bounds__(WG) void k_bicg_init(Geom g, const double2* __restrict__ r64, const double* __restrict__ scale,
-                                                  typename Traits<R>::word* r, typename Traits<R>::word* rh,
-                                                  typename Traits<R>::word* p, typename Traits<R>::word* x,
-                                                  double* part, int nrhs, int ntiles) {
-    TileRhs tr = tile_rhs(ntiles, nrhs);
-    const int s = tr.tile * WG + threadIdx.x;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+template <class R, bool RI>
+__global__ __launch_bounds__(WG) void k_bicg_init(unsigned n, const double2* __restrict__ r64,
+                                                  const double* __restrict__ scale, typename Traits<R>::word* r,
+                                                  typename Traits<R>::word* rh, typename Traits<R>::word* p,
+                                                  typename Traits<R>::word* x, double* part, int nrhs, int ntiles) {
+    const VItem it = vitem<RI>(n, nrhs, ntiles);
     double v[1] = {0};
-    if (s < g.V) {
+    if (it.ok) {
+        const VView<RI, R> w(n, nrhs, it.i, it.r);
         cx<double> a[12];
-        load_spinor(r64 + (size_t)tr.rhs * 12 * g.V, g.V, s, a);
-        const double sc = scale[tr.rhs];
+        load_spinor(r64 + (size_t)it.r * 12 * n, n, it.i, a);
+        const double sc = scale[it.r];
         cx<R> q[12], z[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             q[k] = mk((R)(sc * a[k].re), (R)(sc * a[k].im));
             z[k] = mk(R(0), R(0));
         }
-        store_spinor(r + off, g.V, s, q);
-        store_spinor(rh + off, g.V, s, q);
-        store_spinor(p + off, g.V, s, q);
-        store_spinor(x + off, g.V, s, z);
+        store_spinor(r + w.base, w.stride, w.idx, q);
+        store_spinor(rh + w.base, w.stride, w.idx, q);
+        store_spinor(p + w.base, w.stride, w.idx, q);
+        store_spinor(x + w.base, w.stride, w.idx, z);
         v[0] = acc_nrm(q);
     }
-    write_partials<1>(v, part, ntiles, tr);
+    vpartials<1, RI>(v, part, ntiles, it, nrhs);
 }
 
-template <class R>
-__global__ __launch_bounds__(WG) void k_bicg_s(Geom g, const BiState* __restrict__ st,
+template <class R, bool RI>
+__global__ __launch_bounds__(WG) void k_bicg_s(unsigned n, const BiState* __restrict__ st,
                                                const typename Traits<R>::word* __restrict__ r,
                                                const typename Traits<R>::word* __restrict__ v,
                                                typename Traits<R>::word* __restrict__ s_out, int nrhs, int ntiles) {
-    TileRhs tr = tile_rhs(ntiles, nrhs);
-    const int s = tr.tile * WG + threadIdx.x;
-    if (s >= g.V) return;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
-    const cx<R> al = cxs<R>(st[tr.rhs].alpha);
+    const VItem it = vitem<RI>(n, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<RI, R> w(n, nrhs, it.i, it.r);
+    const cx<R> al = cxs<R>(st[it.r].alpha);
     cx<R> a[12], b[12];
-    load_spinor(r + off, g.V, s, a);
-    load_spinor(v + off, g.V, s, b);
+    load_spinor(r + w.base, w.stride, w.idx, a);
+    load_spinor(v + w.base, w.stride, w.idx, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) a[k] = a[k] - al * b[k];
-    store_spinor(s_out + off, g.V, s, a);
+    store_spinor(s_out + w.base, w.stride, w.idx, a);
 }
 
-template <class R>
-__global__ __launch_bounds__(WG) void k_bicg_xr(Geom g, const BiState* __restrict__ st,
+template <class R, bool RI>
+__global__ __launch_bounds__(WG) void k_bicg_xr(unsigned n, const BiState* __restrict__ st,
                                                 typename Traits<R>::word* __restrict__ x,
                                                 const typename Traits<R>::word* __restrict__ p,
                                                 const typename Traits<R>::word* __restrict__ sv,
@@ -312,108 +283,114 @@ __global__ __launch_bounds__(WG) void k_bicg_xr(Geom g, const BiState* __restric
                                                 const typename Traits<R>::word* __restrict__ rh,
                                                 typename Traits<R>::word* __restrict__ r, double* part, int nrhs,
                                                 int ntiles) {
-    TileRhs tr = tile_rhs(ntiles, nrhs);
-    const int s = tr.tile * WG + threadIdx.x;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
+    const VItem it = vitem<RI>(n, nrhs, ntiles);
     double v[3] = {0, 0, 0};
-    if (s < g.V) {
-        const cx<R> al = cxs<R>(st[tr.rhs].alpha), om = cxs<R>(st[tr.rhs].omega);
+    if (it.ok) {
+        const VView<RI, R> w(n, nrhs, it.i, it.r);
+        const cx<R> al = cxs<R>(st[it.r].alpha), om = cxs<R>(st[it.r].omega);
         cx<R> xx[12], pp[12], ss[12], tt[12];
-        load_spinor(x + off, g.V, s, xx);
-        load_spinor(p + off, g.V, s, pp);
-        load_spinor(sv + off, g.V, s, ss);
-        load_spinor(t + off, g.V, s, tt);
+        load_spinor(x + w.base, w.stride, w.idx, xx);
+        load_spinor(p + w.base, w.stride, w.idx, pp);
+        load_spinor(sv + w.base, w.stride, w.idx, ss);
+        load_spinor(t + w.base, w.stride, w.idx, tt);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             xx[k] = xx[k] + al * pp[k] + om * ss[k];
             ss[k] = ss[k] - om * tt[k];
         }
-        store_spinor(x + off, g.V, s, xx);
-        store_spinor(r + off, g.V, s, ss);
-        load_spinor(rh + off, g.V, s, pp);
+        store_spinor(x + w.base, w.stride, w.idx, xx);
+        store_spinor(r + w.base, w.stride, w.idx, ss);
+        load_spinor(rh + w.base, w.stride, w.idx, pp);
         acc_dot(pp, ss, v[0], v[1]);
         v[2] = acc_nrm(ss);
     }
-    write_partials<3>(v, part, ntiles, tr);
+    vpartials<3, RI>(v, part, ntiles, it, nrhs);
 }
 
-template <class R>
-__global__ __launch_bounds__(WG) void k_bicg_p(Geom g, const BiState* __restrict__ st,
+template <class R, bool RI>
+__global__ __launch_bounds__(WG) void k_bicg_p(unsigned n, const BiState* __restrict__ st,
                                                const typename Traits<R>::word* __restrict__ r,
                                                const typename Traits<R>::word* __restrict__ v,
                                                typename Traits<R>::word* __restrict__ p, int nrhs, int ntiles) {
-    TileRhs tr = tile_rhs(ntiles, nrhs);
-    const int s = tr.tile * WG + threadIdx.x;
-    if (s >= g.V) return;
-    const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
-    const cx<R> be = cxs<R>(st[tr.rhs].beta), om = cxs<R>(st[tr.rhs].omega);
+    const VItem it = vitem<RI>(n, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<RI, R> w(n, nrhs, it.i, it.r);
+    const cx<R> be = cxs<R>(st[it.r].beta), om = cxs<R>(st[it.r].omega);
     cx<R> rr[12], pp[12], vv[12];
-    load_spinor(r + off, g.V, s, rr);
-    load_spinor(p + off, g.V, s, pp);
-    load_spinor(v + off, g.V, s, vv);
+    load_spinor(r + w.base, w.stride, w.idx, rr);
+    load_spinor(p + w.base, w.stride, w.idx, pp);
+    load_spinor(v + w.base, w.stride, w.idx, vv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) pp[k] = rr[k] + be * (pp[k] - om * vv[k]);
-    store_spinor(p + off, g.V, s, pp);
+    store_spinor(p + w.base, w.stride, w.idx, pp);
 }
 
-template <class R>
-__global__ __launch_bounds__(WG) void k_accumulate(Geom g, const typename Traits<R>::word* __restrict__ x,
+template <class R, bool RI>
+__global__ __launch_bounds__(WG) void k_accumulate(unsigned n, const typename Traits<R>::word* __restrict__ x,
                                                    const double* __restrict__ scale, double2* __restrict__ x64,
                                                    int nrhs, int ntiles) {
-    TileRhs tr = tile_rhs(ntiles, nrhs);
-    const int s = tr.tile * WG + threadIdx.x;
-    if (s >= g.V) return;
-    const double sc = scale[tr.rhs];
+    const VItem it = vitem<RI>(n, nrhs, ntiles);
+    if (!it.ok) return;
+    const double sc = scale[it.r];
     if (sc == 0.0) return;
     const double inv = 1.0 / sc;
+    const VView<RI, R> w(n, nrhs, it.i, it.r);
     cx<R> a[12];
     cx<double> b[12];
-    load_spinor(x + (size_t)tr.rhs * Traits<R>::NCW * g.V, g.V, s, a);
-    double2* dst = x64 + (size_t)tr.rhs * 12 * g.V;
-    load_spinor(dst, g.V, s, b);
+    load_spinor(x + w.base, w.stride, w.idx, a);
+    double2* dst = x64 + (size_t)it.r * 12 * n;
+    load_spinor(dst, n, it.i, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) b[k] = b[k] + mk(inv * (double)a[k].re, inv * (double)a[k].im);
-    store_spinor(dst, g.V, s, b);
+    store_spinor(dst, n, it.i, b);
 }
 
+int vector_tiles(unsigned n, int nrhs, bool ri) { return ri ? tiles_of((int)(n * (unsigned)nrhs)) : tiles_of((int)n); }
+static int vector_grid(unsigned n, int nrhs, bool ri) { return ri ? vector_tiles(n, nrhs, ri) : tiles_of((int)n) * nrhs; }
+
+#define VDISPATCH(KERNEL, R, ...)                                                                          \
+    do {                                                                                                   \
+        const int nt = vector_tiles(n, nrhs, ri), ng = vector_grid(n, nrhs, ri);                           \
+        if (ri)                                                                                            \
+            KERNEL<R, true><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                             \
+        else                                                                                               \
+            KERNEL<R, false><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                            \
+    } while (0)
+
 template <class R>
-void launch_bicg_init(Exec& e, const Geom& g, const double2* r64, const double* scale,
+void launch_bicg_init(Exec& e, unsigned n, bool ri, const double2* r64, const double* scale,
                       typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
                       typename Traits<R>::word* x, double* part, int nrhs) {
     Timed t(e, 3, 0);
-    int nt = tiles_of(g.V);
-    k_bicg_init<R><<<nt * nrhs, WG, 0, e.stream>>>(g, r64, scale, r, rh, p, x, part, nrhs, nt);
+    VDISPATCH(k_bicg_init, R, r64, scale, r, rh, p, x, part);
 }
 template <class R>
-void launch_bicg_s(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
                    const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs) {
     Timed t(e, 3, 0);
-    int nt = tiles_of(g.V);
-    k_bicg_s<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, r, v, s, nrhs, nt);
+    VDISPATCH(k_bicg_s, R, st, r, v, s);
 }
 template <class R>
-void launch_bicg_xr(Exec& e, const Geom& g, const BiState* st, typename Traits<R>::word* x,
+void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<R>::word* x,
                     const typename Traits<R>::word* p, const typename Traits<R>::word* s,
                     const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
                     typename Traits<R>::word* r, double* part, int nrhs) {
     Timed tm(e, 3, 0);
-    int nt = tiles_of(g.V);
-    k_bicg_xr<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, x, p, s, t, rh, r, part, nrhs, nt);
+    VDISPATCH(k_bicg_xr, R, st, x, p, s, t, rh, r, part);
 }
 template <class R>
-void launch_bicg_p(Exec& e, const Geom& g, const BiState* st, const typename Traits<R>::word* r,
+void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
                    const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs) {
     Timed t(e, 3, 0);
-    int nt = tiles_of(g.V);
-    k_bicg_p<R><<<nt * nrhs, WG, 0, e.stream>>>(g, st, r, v, p, nrhs, nt);
+    VDISPATCH(k_bicg_p, R, st, r, v, p);
 }
 template <class R>
-void launch_accumulate(Exec& e, const Geom& g, const typename Traits<R>::word* x, const double* scale,
+void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<R>::word* x, const double* scale,
                        double2* x64, int nrhs) {
     Timed t(e, 3, 0);
-    int nt = tiles_of(g.V);
-    k_accumulate<R><<<nt * nrhs, WG, 0, e.stream>>>(g, x, scale, x64, nrhs, nt);
+    VDISPATCH(k_accumulate, R, x, scale, x64);
 }
+#undef VDISPATCH
 
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
@@ -564,16 +541,16 @@ void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, dou
                                      int, int, double);                                                           \
     template void launch_hop<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, Traits<R>::word*, int,  \
                                 int);                                                                             \
-    template void launch_bicg_init<R>(Exec&, const Geom&, const double2*, const double*, Traits<R>::word*,        \
+    template void launch_bicg_init<R>(Exec&, unsigned, bool, const double2*, const double*, Traits<R>::word*,      \
                                       Traits<R>::word*, Traits<R>::word*, Traits<R>::word*, double*, int);        \
-    template void launch_bicg_s<R>(Exec&, const Geom&, const BiState*, const Traits<R>::word*,                    \
+    template void launch_bicg_s<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \
                                    const Traits<R>::word*, Traits<R>::word*, int);                                \
-    template void launch_bicg_xr<R>(Exec&, const Geom&, const BiState*, Traits<R>::word*, const Traits<R>::word*, \
+    template void launch_bicg_xr<R>(Exec&, unsigned, bool, const BiState*, Traits<R>::word*,                      \
                                     const Traits<R>::word*, const Traits<R>::word*, const Traits<R>::word*,       \
-                                    Traits<R>::word*, double*, int);                                              \
-    template void launch_bicg_p<R>(Exec&, const Geom&, const BiState*, const Traits<R>::word*,                    \
+                                    const Traits<R>::word*, Traits<R>::word*, double*, int);                      \
+    template void launch_bicg_p<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \
                                    const Traits<R>::word*, Traits<R>::word*, int);                                \
-    template void launch_accumulate<R>(Exec&, const Geom&, const Traits<R>::word*, const double*, double2*, int);
+    template void launch_accumulate<R>(Exec&, unsigned, bool, const Traits<R>::word*, const double*, double2*, int);
 
 INST(double)
 INST(float)

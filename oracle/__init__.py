@@ -13,7 +13,8 @@ Contents
                 sparse Wilson-clover operator D(m) in the mass normalisation
   schwarz.py    D_bb, D_ww, D_bw, D_wb, the Schur complement and its
                 P-restricted form and inverse (Sec. 1, Eq. 1)
-  estimator.py  the two-flavour noise estimator of Eq. (3) and W_gl of Eq. (8)
+  estimator.py  the two-flavour noise estimator of Eq. (3), W_gl of Eq. (8) and the
+                one-flavour estimator of Eq. (11)
                 with mass interpolation, log-domain combination, variances
   cref.py       ctypes wrapper of c/ddref.c, a matrix-free FP64 C version of
                 the operator, block solves and estimator for lattices too large

@@ -21,6 +21,13 @@ The estimate is combined in the log domain (the exponentials under- or
 overflow FP64 on large lattices): log W_gl = sum_i [logsumexp_j(-x_ij) - ln N_hit].
 The per-step relative sample variance var_j(e^-x)/mean_j(e^-x)^2 (N_hit - 1 in
 the denominator) is the quantity Sec. 2.1 asks to monitor with N_hit >= 6.
+
+One flavour (Sec. 3, Eq. 11): 1/det M = E exp(-eta^dag (M - 1) eta), defined while every
+eigenvalue of M has a positive real part.  The exponent x = eta^dag (M - 1) eta is complex;
+by gamma_5-hermiticity the expectation is real, so only the real part of the sample mean is
+kept.  Plain form x = <eta, M eta> - ||eta||^2; difference forms x = dm <eta, psi> (full)
+and x = <e, zeta> (Schur), with psi and zeta as above.  Per step,
+log W_i = ln Re[(1/N_hit) sum_j exp(-x_ij)], undefined (nan) when that real part is <= 0.
 """
 from __future__ import annotations
 
@@ -42,6 +49,11 @@ def _nrm2(v):
 
 def _redot(a, b):
     return float(np.vdot(np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)).real)
+
+
+def _dot(a, b) -> complex:
+    """<a, b> = sum conj(a) b."""
+    return complex(np.vdot(np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)))
 
 
 def x_full_plain(S: Schwarz, m_prev: float, m_next: float, eta) -> float:
@@ -80,14 +92,45 @@ def x_schur_diff(S: Schwarz, m_prev: float, m_next: float, eta) -> float:
     return 2 * _redot(e, zeta) + _nrm2(zeta)
 
 
-def exponents(S: Schwarz, m1: float, m2: float, eta, op: str = "schur", form: str = "diff"):
-    """x[i][j] for noise eta of shape (N, N_hit, V, 4, 3)."""
+# ---------------------------------------------------------------- one flavour (Eq. 11)
+def x1_full_plain(S: Schwarz, m_prev: float, m_next: float, eta) -> complex:
+    """eta^dag (M - 1) eta with M = D(m_next)^-1 D(m_prev)."""
+    y = S.inv_full(m_next)(S.D(m_prev) @ S.flat(eta))
+    return _dot(eta, y) - _nrm2(eta)
+
+
+def x1_full_diff(S: Schwarz, m_prev: float, m_next: float, eta) -> complex:
+    dm = m_prev - m_next
+    psi = S.inv_full(m_next)(S.flat(eta))
+    return dm * _dot(eta, psi)
+
+
+def x1_schur_plain(S: Schwarz, m_prev: float, m_next: float, eta) -> complex:
+    e = S.restrict_P(eta)
+    y = S.hat_inverse(m_next, S.hat_apply(m_prev, e))
+    return _dot(e, y) - _nrm2(e)
+
+
+def x1_schur_diff(S: Schwarz, m_prev: float, m_next: float, eta) -> complex:
+    e = S.restrict_P(eta)
+    zeta = S.hat_inverse(m_next, schur_difference_source(S, m_prev, m_next, e))
+    return _dot(e, zeta)
+
+
+def exponents(S: Schwarz, m1: float, m2: float, eta, op: str = "schur", form: str = "diff", n_f: int = 2):
+    """x[i][j] for noise eta of shape (N, N_hit, V, 4, 3); complex for n_f = 1."""
     eta = np.asarray(eta)
     n, nhit = eta.shape[:2]
     ms = interpolation_masses(m1, m2, n)
-    f = {("full", "plain"): x_full_plain, ("full", "diff"): x_full_diff,
-         ("schur", "plain"): x_schur_plain, ("schur", "diff"): x_schur_diff}[(op, form)]
-    x = np.empty((n, nhit))
+    if n_f == 2:
+        f = {("full", "plain"): x_full_plain, ("full", "diff"): x_full_diff,
+             ("schur", "plain"): x_schur_plain, ("schur", "diff"): x_schur_diff}[(op, form)]
+    elif n_f == 1:
+        f = {("full", "plain"): x1_full_plain, ("full", "diff"): x1_full_diff,
+             ("schur", "plain"): x1_schur_plain, ("schur", "diff"): x1_schur_diff}[(op, form)]
+    else:
+        raise ValueError("n_f must be 1 or 2")
+    x = np.empty((n, nhit), dtype=float if n_f == 2 else complex)
     for i in range(n):
         for j in range(nhit):
             x[i, j] = f(S, ms[i], ms[i + 1], eta[i, j])
@@ -107,4 +150,29 @@ def step_variance(x) -> np.ndarray:
     w = np.exp(a - a.max(axis=1, keepdims=True))
     mean = w.mean(axis=1)
     var = w.var(axis=1, ddof=1) if a.shape[1] > 1 else np.zeros(a.shape[0])
+    return var / mean ** 2
+
+
+def _one_flavour_weights(x):
+    """Re exp(-x_ij + a_i) = exp(-Re x_ij + a_i) cos(Im x_ij), a_i = max_j(-Re x_ij)."""
+    x = np.asarray(x, dtype=complex)
+    a = -x.real
+    amax = a.max(axis=1)
+    return amax, np.exp(a - amax[:, None]) * np.cos(x.imag)
+
+
+def log_w_one_flavour(x) -> float:
+    """sum_i ln Re[(1/N_hit) sum_j exp(-x_ij)] (Eq. 11 per step); nan if a step's mean is <= 0."""
+    amax, w = _one_flavour_weights(x)
+    s = w.sum(axis=1)
+    if np.any(s <= 0):
+        return float("nan")
+    return float(np.sum(amax + np.log(s) - np.log(w.shape[1])))
+
+
+def step_variance_one_flavour(x) -> np.ndarray:
+    """Relative sample variance of Re exp(-x_ij) over j, per step i."""
+    _, w = _one_flavour_weights(x)
+    mean = w.mean(axis=1)
+    var = w.var(axis=1, ddof=1) if w.shape[1] > 1 else np.zeros(w.shape[0])
     return var / mean ** 2

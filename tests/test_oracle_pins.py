@@ -350,9 +350,11 @@ def test_exponents_gauge_invariant():
     eta = inputs.make_noise_batch(lat, 1, 1, 1)
     etag = dirac.gauge_transform_spinor(eta[0, 0], Om)[None, None]
     for op in ("full", "schur"):
-        a = estimator.exponents(Schwarz(U, lat, blk, 1.0), m1, m2, eta, op)
-        b = estimator.exponents(Schwarz(dirac.gauge_transform_links(U, lat, Om), lat, blk, 1.0), m1, m2, etag, op)
-        assert abs(a - b).max() < 1e-10 * abs(a).max()
+        for n_f in (2, 1):
+            a = estimator.exponents(Schwarz(U, lat, blk, 1.0), m1, m2, eta, op, n_f=n_f)
+            b = estimator.exponents(Schwarz(dirac.gauge_transform_links(U, lat, Om), lat, blk, 1.0), m1, m2, etag,
+                                    op, n_f=n_f)
+            assert abs(a - b).max() < 1e-10 * abs(a).max()
 
 
 def test_log_domain_combination():
@@ -362,3 +364,91 @@ def test_log_domain_combination():
     assert estimator.step_variance(x)[1] == 0
     w = np.exp(-(x[0] - 1000))
     assert abs(estimator.step_variance(x)[0] - w.var(ddof=1) / w.mean() ** 2) < 1e-14
+
+
+# --------------------------------------------------------------------------- one flavour (Eq. 11, 12)
+def test_one_flavour_plane_wave_closed_form():
+    """U = 1: a plane wave e^{ipx} u c with u an eigenvector of sum gamma_mu sin p_mu (eigenvalue
+    sigma = +-s_p) is an eigenvector of D(m) with eigenvalue a_p + i sigma, so
+    x = eta^dag (M - 1) eta = dm ||eta||^2 / (a_p(m2) + i sigma) in both forms."""
+    lat, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    S = Schwarz(inputs.unit_links(lat), lat, blk, 1.0)
+    m1, m2 = dirac.mass(0.12), dirac.mass(0.121)
+    x = lt.coords(lat)
+    rng = np.random.default_rng(3)
+    for n in [(0, 0, 0, 0), (1, 1, 0, 3), (3, 2, 1, 1)]:
+        p = np.array([(2 * n[0] + 1) * np.pi / lat[0]] + [2 * np.pi * n[k] / lat[k] for k in (1, 2, 3)])
+        G = np.einsum("m,mst->st", np.sin(p), dirac.GAMMA)
+        sig, vecs = np.linalg.eigh(G)
+        a = m2 + np.sum(1 - np.cos(p))
+        for k in (0, 3):
+            c = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+            eta = np.exp(1j * (x @ p))[:, None, None] * np.outer(vecs[:, k], c)[None]
+            want = (m1 - m2) * np.sum(np.abs(eta) ** 2) / (a + 1j * sig[k])
+            for form in ("plain", "diff"):
+                got = estimator.exponents(S, m1, m2, eta[None, None], "full", form, n_f=1)[0, 0]
+                assert abs(got - want) < 1e-10 * abs(want), (n, k, form)
+
+
+@pytest.mark.parametrize("op", ["full", "schur"])
+def test_one_flavour_brute_force(op):
+    """Sampling 2e5 noise vectors with the dense ratio matrix on a 2^4 lattice: the mean of
+    exp(-eta^dag (M - 1) eta) is 1/det M (Eq. 11, real by gamma_5-hermiticity) and the
+    variance E|w|^2 - |E w|^2 is 1/det(M^dag + M - 1) - 1/|det M|^2 (Eq. 12)."""
+    lat, blk = (2, 2, 2, 2), (1, 1, 1, 1)
+    S = Schwarz(inputs.make_links(lat, 0.3, 5), lat, blk, 1.0)
+    m1, m2 = dirac.mass(0.1200), dirac.mass(0.1215)
+    if op == "full":
+        M = np.linalg.solve(S.D(m2).toarray(), S.D(m1).toarray())
+    else:
+        M = np.linalg.solve(S.hat_dense(m2), S.hat_dense(m1))
+    n = M.shape[0]
+    A = M - np.eye(n)
+    H = M.conj().T + M
+    assert np.linalg.eigvalsh(H).min() > 1  # the variance exists
+    detM = np.linalg.det(M)
+    assert abs(detM.imag) < 1e-10 * abs(detM)
+    target = 1 / detM.real
+    var = 1 / np.linalg.det(H - np.eye(n)).real - target ** 2
+    rng = np.random.default_rng(11)
+    N, chunk = 200000, 20000
+    w = np.empty(N, dtype=complex)
+    for s in range(0, N, chunk):
+        eta = (rng.standard_normal((n, chunk)) + 1j * rng.standard_normal((n, chunk))) * np.sqrt(0.5)
+        w[s:s + chunk] = np.exp(-np.sum(eta.conj() * (A @ eta), axis=0))
+    se = np.sqrt(var / N)
+    assert abs(w.mean().real - target) < 5 * se
+    assert abs(w.mean().imag) < 5 * se
+    assert abs(np.mean(np.abs(w - w.mean()) ** 2) - var) < 0.1 * var
+
+
+def test_one_flavour_exponents_match_dense():
+    """The oracle's solve-based one-flavour x (both forms) equals eta^dag (M - 1) eta with dense M."""
+    lat, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    S = Schwarz(inputs.make_links(lat, 0.3, 1), lat, blk, 1.0)
+    m1, m2 = dirac.mass(0.12), dirac.mass(0.121)
+    eta = inputs.make_noise_batch(lat, 1, 1, 2)
+    Mf = np.linalg.solve(S.D(m2).toarray(), S.D(m1).toarray())
+    Ms = np.linalg.solve(S.hat_dense(m2), S.hat_dense(m1))
+    for j in range(2):
+        e = eta[0, j].reshape(-1)
+        xf = np.vdot(e, Mf @ e) - np.vdot(e, e)
+        eP = e[S.P]
+        xs = np.vdot(eP, Ms @ eP) - np.vdot(eP, eP)
+        for form in ("plain", "diff"):
+            got = estimator.exponents(S, m1, m2, eta[:, j:j + 1], "full", form, n_f=1)[0, 0]
+            assert abs(got - xf) < 1e-9 * abs(xf)
+            got = estimator.exponents(S, m1, m2, eta[:, j:j + 1], "schur", form, n_f=1)[0, 0]
+            assert abs(got - xs) < 1e-9 * abs(xs)
+
+
+def test_one_flavour_log_domain_combination():
+    """ln Re mean_j exp(-x_j) per step, summed; nan when a step's real mean is not positive."""
+    x = np.array([[700.0 + 0.3j, 701.0 - 1.2j, 702.5 + 2.0j], [3.0 + 0.1j, 2.0 - 0.4j, 4.0 + 0.0j]])
+    want = (np.log(np.mean(np.exp(-(x[0] - 700))).real) - 700
+            + np.log(np.mean(np.exp(-x[1])).real))
+    assert abs(estimator.log_w_one_flavour(x) - want) < 1e-12 * abs(want)
+    w0 = np.exp(-(x[0] - 700)).real
+    assert abs(estimator.step_variance_one_flavour(x)[0] - w0.var(ddof=1) / w0.mean() ** 2) < 1e-13
+    neg = np.array([[1.0 + np.pi * 1j, 1.5 + 0.9 * np.pi * 1j]])
+    assert np.isnan(estimator.log_w_one_flavour(neg))

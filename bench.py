@@ -39,6 +39,7 @@ def main():
     ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dslash-reps", type=int, default=20, help="launches per standalone Dslash measurement")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
@@ -112,6 +113,8 @@ def main():
         x64.append(r64["x"][0, 0])
     fp64_rate = args.fp64_samples / fp64_t if args.fp64_samples else None
 
+    dslash = dslash_rates(ctx, dd, inputs, lat, dev, args.dslash_reps) if args.dslash_reps > 0 else None
+
     # parity against the stored oracle exponents (written by tests/golden/make_c3_golden.py)
     parity = {}
     gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
@@ -153,8 +156,9 @@ def main():
                    "lattice": list(lat), "blocks": list(blk), "n_hit": nhit, "tol": args.tol},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "dslash32_gbs": None if dslash_gbs is None else round(dslash_gbs, 1),
-        "dslash32_frac": None if dslash_gbs is None else round(dslash_gbs / HBM_PEAK_GBS, 4),
+        "dslash": dslash,
+        "dslash32_in_solver_gbs": None if dslash_gbs is None else round(dslash_gbs, 1),
+        "dslash32_in_solver_frac": None if dslash_gbs is None else round(dslash_gbs / HBM_PEAK_GBS, 4),
         "fp64_single_rhs_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 3),
         "speedup_vs_fp64_single_rhs": None if not fp64_rate else round(value / fp64_rate, 2),
         "parity": parity,
@@ -163,6 +167,33 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def dslash_rates(ctx, dd, inputs, lat, dev, reps):
+    """Standalone full-lattice Dslash D(m) psi through ddwc_dslash_apply: FP64 with one RHS and
+    FP32 with 12 RHS.  The kernel's own HIP-event time (layout conversion excluded) and the
+    algorithmic bytes of the library's byte model give GB/s."""
+    import torch
+    out = {}
+    for name, nrhs, prec, kc in (("fp64_1rhs", 1, dd.FP64, dd.binding.K_DSLASH64),
+                                 ("fp32_12rhs", 12, dd.MIXED32, dd.binding.K_DSLASH32)):
+        psi = torch.from_numpy(inputs.make_spinor(lat, 5, nrhs=nrhs)).to(dev)
+        ctx.dslash_apply(0.1205, psi, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        for _ in range(reps):
+            ctx.dslash_apply(0.1205, psi, prec=prec)
+        torch.cuda.synchronize()
+        p = ctx.profile_read(kc)
+        ctx.profile_enable(False)
+        us = 1e3 * p["ms"] / max(p["launches"], 1)
+        gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
+        out[name] = {"launches": p["launches"], "avg_launch_us": round(us, 2),
+                     "bytes_per_launch": p["bytes"] / max(p["launches"], 1),
+                     "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"standalone Dslash {name}: {us:.1f} us/launch, {gbs:.0f} GB/s")
+        del psi
+    return out
 
 
 def cpu_baseline(U, eta0, cfg, golden, cap):

@@ -114,15 +114,22 @@ int ddwc_solve(ddwc_ctx *ctx, double kappa, const void *b, void *x, int nrhs, do
                ddwc_stats *stats, void *stream);
 
 /*
- * Two-flavour determinant-ratio estimate (Eq. 3 for op = FULL, Eq. 8 for SCHUR).
+ * Determinant-ratio estimate (Eq. 3 for op = FULL, Eq. 8 for SCHUR; n_f = 1: Eq. 11).
  *   eta         = noise, device, [n_interp][n_hit][V][4][3] (complex Gaussian, E|eta_k|^2 = 1;
  *                 for SCHUR it is projected with P first).
- *   x_host      = [n_interp][n_hit] exponents x_ij = eta^+ (M^+ M - 1) eta, computed in the
- *                 cancellation-free form x = 2 Re<eta, y> + ||y||^2 with y = M eta - eta.
- *   log_w_gl    = sum_i [logsumexp_j(-x_ij) - ln n_hit]   (FP64, log domain).
- *   step_var_host = [n_interp] relative sample variance var_j(e^-x)/mean_j(e^-x)^2.
+ *   n_f = 2:  x_host = [n_interp][n_hit] exponents x_ij = eta^+ (M^+ M - 1) eta, computed in the
+ *                 cancellation-free form x = 2 Re<eta, y> + ||y||^2 with y = M eta - eta;
+ *             the estimate is of 1/det(M^+ M) = W for two degenerate flavours.
+ *   n_f = 1:  x_host = [n_interp][n_hit][2] complex exponents (re, im) x_ij = eta^+ (M - 1) eta
+ *                 = <eta, y>; the estimate is of 1/det M, and only the real part of each step's
+ *                 sample mean is kept (the expectation is real by gamma_5-hermiticity).
+ *   log_w_gl    = sum_i ln Re[(1/n_hit) sum_j exp(-x_ij)]   (FP64, log domain).
+ *   step_var_host = [n_interp] relative sample variance var_j(w)/mean_j(w)^2 of the weights
+ *                 w_j = Re exp(-x_ij).  May be null.
  * Masses m_i = (i/N) m2 + ((N-i)/N) m1 linear in m (Sec. 2.1); all n_hit noise vectors of
- * a step go through the solvers as one multi-RHS batch.  n_f must be 2.
+ * a step go through the solvers as one multi-RHS batch; both flavour numbers use the same
+ * solves.  Returns DDWC_EUNDEF (x_host filled, *log_w_gl = NaN) when a step's real mean is
+ * not positive or a mean or variance is not finite.
  */
 int ddwc_det_ratio_estimate(ddwc_ctx *ctx, double kappa1, double kappa2, int n_interp, int op, int n_f,
                             const void *eta, int n_hit, double tol, int prec, double *x_host, double *log_w_gl,

@@ -178,21 +178,24 @@ class Context:
                                 ctypes.byref(st), _stream()), "ddwc_solve")
         return out, st.as_dict()
 
-    def det_ratio_estimate(self, kappa1, kappa2, eta, op=OP_SCHUR, tol=1e-12, prec=FP64, n_f=2):
-        """eta: complex128 [n_interp, n_hit, V, 4, 3] on the device."""
+    def det_ratio_estimate(self, kappa1, kappa2, eta, op=OP_SCHUR, tol=1e-12, prec=FP64, n_f=2, allow=()):
+        """eta: complex128 [n_interp, n_hit, V, 4, 3] on the device.  x is complex for n_f = 1.
+        Status codes in `allow` (e.g. (EUNDEF,)) are returned in "status" instead of raised."""
         sh = tuple(eta.shape)
         if len(sh) != 5 or sh[2:] != (self.V, 4, 3):
             raise ValueError(f"eta must have shape (n_interp, n_hit, {self.V}, 4, 3)")
         n_interp, n_hit = sh[:2]
-        x = np.zeros((n_interp, n_hit))
+        x = np.zeros((n_interp, n_hit) if n_f == 2 else (n_interp, n_hit, 2))
         var = np.zeros(n_interp)
         lw = ctypes.c_double()
         st = Stats()
-        _check(lib().ddwc_det_ratio_estimate(
+        code = _check(lib().ddwc_det_ratio_estimate(
             self._h, float(kappa1), float(kappa2), int(n_interp), int(op), int(n_f), _ptr(eta), int(n_hit),
             float(tol), int(prec), x.ctypes.data_as(_PD), ctypes.byref(lw), var.ctypes.data_as(_PD),
-            ctypes.byref(st), _stream()), "ddwc_det_ratio_estimate")
-        return {"x": x, "log_w_gl": lw.value, "step_var": var, "stats": st.as_dict()}
+            ctypes.byref(st), _stream()), "ddwc_det_ratio_estimate", allow=allow)
+        if n_f == 1:
+            x = x[..., 0] + 1j * x[..., 1]
+        return {"x": x, "log_w_gl": lw.value, "step_var": var, "stats": st.as_dict(), "status": code}
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

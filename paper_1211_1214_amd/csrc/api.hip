@@ -943,7 +943,7 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
     if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
     if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
     if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
-    if (n_f != 2) return fail(DDWC_EINVAL, "only the two-flavour estimator (n_f = 2) is provided");
+    if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
     if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
     Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
@@ -1001,36 +1001,50 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
         HC(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, ex.stream));
         HC(hipStreamSynchronize(ex.stream));
         for (int j = 0; j < nrhs; ++j) {
-            double x = ca * hs[j * NPART] + cb * hs[j * NPART + 2];
-            if (!isfinite(x)) return fail(DDWC_ENONFINITE, "non-finite exponent");
-            x_host[(size_t)i * nrhs + j] = x;
+            const double dre = hs[j * NPART], dim = hs[j * NPART + 1], nz = hs[j * NPART + 2];
+            if (n_f == 2) {
+                const double x = ca * dre + cb * nz;
+                if (!isfinite(x)) return fail(DDWC_ENONFINITE, "non-finite exponent");
+                x_host[(size_t)i * nrhs + j] = x;
+            } else {
+                // x = eta^+ (M - 1) eta = <eta, y> with y = M eta - eta: dm <eta, psi> or <e, zeta>
+                const double f = op == DDWC_OP_FULL ? dm : 1.0;
+                const double xr = f * dre, xi = f * dim;
+                if (!isfinite(xr) || !isfinite(xi)) return fail(DDWC_ENONFINITE, "non-finite exponent");
+                x_host[2 * ((size_t)i * nrhs + j)] = xr;
+                x_host[2 * ((size_t)i * nrhs + j) + 1] = xi;
+            }
         }
     }
-    // log W_gl = sum_i [max_j a_ij + ln sum_j exp(a_ij - max) - ln n_hit], a = -x; step variances
+    // Per step, with a = -Re x and a_max = max_j a_j, the weights w_j = Re exp(-x_j + a_max)
+    // = exp(a_j - a_max) cos(Im x_j) (cos = 1 for two flavours): log W_i = a_max + ln sum_j w_j
+    // - ln n_hit, and the step variance is var_j(w)/mean_j(w)^2.
     double lw = 0;
     bool undefined = false;
+    std::vector<double> a(nrhs), w(nrhs);
     for (int i = 0; i < n_interp; ++i) {
-        const double* xi = x_host + (size_t)i * nrhs;
-        double amax = -xi[0];
-        for (int j = 1; j < nrhs; ++j) amax = fmax(amax, -xi[j]);
+        for (int j = 0; j < nrhs; ++j)
+            a[j] = n_f == 2 ? -x_host[(size_t)i * nrhs + j] : -x_host[2 * ((size_t)i * nrhs + j)];
+        double amax = a[0];
+        for (int j = 1; j < nrhs; ++j) amax = fmax(amax, a[j]);
         double sw = 0, sw2 = 0;
         for (int j = 0; j < nrhs; ++j) {
-            double w = exp(-xi[j] - amax);
-            sw += w;
+            w[j] = exp(a[j] - amax);
+            if (n_f == 1) w[j] *= cos(x_host[2 * ((size_t)i * nrhs + j) + 1]);
+            sw += w[j];
         }
         const double mean = sw / nrhs;
-        for (int j = 0; j < nrhs; ++j) {
-            double d = exp(-xi[j] - amax) - mean;
-            sw2 += d * d;
-        }
+        for (int j = 0; j < nrhs; ++j) sw2 += (w[j] - mean) * (w[j] - mean);
+        if (!(sw > 0)) undefined = true;  // one flavour: the real part of the step mean is not positive
         lw += amax + log(sw) - log((double)nrhs);
-        double var = nrhs > 1 ? (sw2 / (nrhs - 1)) / (mean * mean) : 0.0;
+        const double var = nrhs > 1 ? (sw2 / (nrhs - 1)) / (mean * mean) : 0.0;
         if (!isfinite(var)) undefined = true;
         if (step_var_host) step_var_host[i] = var;
     }
-    *log_w_gl = lw;
+    *log_w_gl = undefined ? NAN : lw;
     fill_stats(stats, si.outer, si.inner, si.relres, t0);
-    if (!isfinite(lw) || undefined) return fail(DDWC_EUNDEF, "estimate undefined (non-finite step mean or variance)");
+    if (!isfinite(lw) || undefined)
+        return fail(DDWC_EUNDEF, "estimate undefined (non-positive real step mean, or non-finite mean or variance)");
     return DDWC_OK;
 }
 

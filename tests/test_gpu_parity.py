@@ -163,6 +163,37 @@ def test_det_ratio_c1(dev, op, prec):
     assert np.allclose(res["step_var"], estimator.step_variance(xo), rtol=1e-6)
 
 
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32])
+@pytest.mark.parametrize("op", ["full", "schur"])
+def test_det_ratio_one_flavour(dev, op, prec):
+    """n_f = 1 (Eq. 11): complex exponents eta^+ (M - 1) eta and ln Re mean exp(-x)."""
+    cfg = inputs.CONFIGS[1]
+    lat, blk, U, ctx, S = setup("4x4^3/2^4", dev)
+    say("det ratio one flavour C1", op, prec)
+    eta = inputs.make_noise_batch(lat, 1, 1, cfg["n_hit"])
+    k1, k2 = cfg["kappa1"], cfg["kappa2"]
+    res = ctx.det_ratio_estimate(k1, k2, T(eta, dev), op=dd.OP_FULL if op == "full" else dd.OP_SCHUR,
+                                 tol=1e-12, prec=prec, n_f=1)
+    xo = estimator.exponents(S, dirac.mass(k1), dirac.mass(k2), eta, op, "diff", n_f=1)
+    assert res["x"].dtype == np.complex128
+    assert np.all(np.abs(res["x"] - xo) <= 1e-8 * np.maximum(np.abs(xo), 1))
+    lw = estimator.log_w_one_flavour(xo)
+    assert np.isfinite(lw)
+    assert abs(res["log_w_gl"] - lw) <= 1e-8 * max(abs(lw), 1)
+    assert np.allclose(res["step_var"], estimator.step_variance_one_flavour(xo), rtol=1e-6)
+
+
+def test_det_ratio_one_flavour_interpolation(dev):
+    lat, blk, U, ctx, S = setup("8x4x4x12/2x2x2x3", dev)
+    say("det ratio one flavour N=4")
+    eta = inputs.make_noise_batch(lat, 7, 4, 3)
+    res = ctx.det_ratio_estimate(0.1200, 0.1205, T(eta, dev), op=dd.OP_SCHUR, tol=1e-12, prec=dd.MIXED32, n_f=1)
+    xo = estimator.exponents(S, dirac.mass(0.12), dirac.mass(0.1205), eta, "schur", "diff", n_f=1)
+    assert np.all(np.abs(res["x"] - xo) <= 1e-8 * np.maximum(np.abs(xo), 1))
+    lw = estimator.log_w_one_flavour(xo)
+    assert abs(res["log_w_gl"] - lw) <= 1e-8 * max(abs(lw), 1)
+
+
 def test_det_ratio_interpolation(dev):
     lat, blk, U, ctx, S = setup("8x4x4x12/2x2x2x3", dev)
     say("det ratio interpolation N=4")
@@ -217,3 +248,8 @@ def test_error_paths(dev):
     assert e.value.code == -4
     with pytest.raises(ValueError):
         ctx.dslash_apply(0.12, T(b[:-1], dev))
+    eta = inputs.make_noise_batch(lat, 1, 1, 2)
+    for n_f in (0, 3):
+        with pytest.raises(dd.DDWCError) as e:
+            ctx.det_ratio_estimate(0.12, 0.121, T(eta, dev), n_f=n_f)
+        assert e.value.code == -1

@@ -28,10 +28,15 @@ struct BlkIdx {
     size_t key;   // (rhs, rank) slot of the per-block arrays
 };
 
+// Workgroups are numbered block-major, RHS-minor and dealt to the 8 XCDs so that each XCD
+// sweeps a contiguous range: the RHS of one block run on one XCD and share its links and
+// clover in that XCD's L2.
 __device__ __forceinline__ BlkIdx blk_idx(const Geom& g, int colour, int nrhs) {
     BlkIdx b;
-    b.rank = blockIdx.x / nrhs;
-    b.rhs = blockIdx.x - b.rank * nrhs;
+    const int n = (int)gridDim.x;
+    const int L = (n & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (n >> 3) + ((int)blockIdx.x >> 3);
+    b.rank = L / nrhs;
+    b.rhs = L - b.rank * nrhs;
     b.B = colour * g.NBc + b.rank;
     b.h0 = (unsigned)b.B * g.hvb;
     b.key = (size_t)b.rhs * g.NBc + b.rank;

@@ -16,6 +16,8 @@ Contents
   estimator.py  the two-flavour noise estimator of Eq. (3), W_gl of Eq. (8) and the
                 one-flavour estimator of Eq. (11)
                 with mass interpolation, log-domain combination, variances
+  derivative.py derivatives of the exponents and of log W_gl with respect to kappa2
+                and the links, by extrapolated central differences (exact solves)
   cref.py       ctypes wrapper of c/ddref.c, a matrix-free FP64 C version of
                 the operator, block solves and estimator for lattices too large
                 for the assembled matrix

@@ -24,6 +24,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 METRIC = "Dslash GB/s (% HBM peak); det-ratio estimates/s, mixed vs FP64 at 1e-8"
+WORKLOADS = {
+    3: "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205, "
+       "N_hit=12 as one multi-RHS batch, FP32 block/inner solves + FP64 defect correction",
+    4: "Schur det-ratio estimate, 64x32^3, 8^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205 in "
+       "N=4 mass-interpolation steps, 24 RHS as one multi-RHS batch, FP32 block/inner solves + FP64 defect "
+       "correction",
+}
 
 
 def log(*a):
@@ -33,6 +40,8 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("c3", "c4"), default="c3",
+                    help="c3: 48x24^3, 6^4 blocks, 12 RHS (default); c4: 64x32^3, 8^4 blocks, 4 steps, 24 RHS")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -64,13 +73,14 @@ def main():
     import paper_1211_1214_amd as dd
     from paper_1211_1214_amd import inputs
 
-    cfg = inputs.CONFIGS[3]
-    lat, blk, nhit = cfg["lat"], cfg["blk"], cfg["n_hit"]
+    cid = 3 if args.workload == "c3" else 4
+    cfg = inputs.CONFIGS[cid]
+    lat, blk, nhit, nint = cfg["lat"], cfg["blk"], cfg["n_hit"], cfg["n_interp"]
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     dev = torch.device("cuda:0")
     t = time.time()
-    U = inputs.make_links(lat, cfg["eps"], 3)
-    eta = inputs.make_noise_batch(lat, 3, 1, nhit)
+    U = inputs.make_links(lat, cfg["eps"], cid)
+    eta = inputs.make_noise_batch(lat, cid, nint, nhit)
     log(f"inputs generated in {time.time() - t:.1f}s")
     Ud = torch.from_numpy(U).to(dev)
     etad = torch.from_numpy(eta).to(dev)
@@ -96,11 +106,11 @@ def main():
              ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER))}
     ctx.profile_enable(False)
     elapsed = t1 - t0
-    value = nhit * args.steps / elapsed
-    x_mixed = r["x"][0]
+    value = nint * nhit * args.steps / elapsed
+    x_mixed = r["x"]
     log(f"timed {args.steps} steps in {elapsed:.3f}s: {value:.2f} estimates/s; profile {prof}")
 
-    # FP64 single-RHS path on the first noise vectors
+    # FP64 single-RHS path on the first noise vectors (all interpolation steps)
     fp64_t = 0.0
     x64 = []
     for j in range(args.fp64_samples):
@@ -110,22 +120,23 @@ def main():
                                      prec=dd.FP64)
         torch.cuda.synchronize()
         fp64_t += time.perf_counter() - ta
-        x64.append(r64["x"][0, 0])
-    fp64_rate = args.fp64_samples / fp64_t if args.fp64_samples else None
+        x64.append(r64["x"][:, 0])
+    fp64_rate = nint * args.fp64_samples / fp64_t if args.fp64_samples else None
 
     dslash = dslash_rates(ctx, dd, inputs, lat, dev, args.dslash_reps) if args.dslash_reps > 0 else None
 
-    # parity against the stored oracle exponents (written by tests/golden/make_c3_golden.py)
+    # parity against the stored oracle exponents (written by tests/golden/make_c{3,4}_golden.py)
     parity = {}
-    gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
+    gpath = os.path.join(ROOT, "tests", "golden", f"c{cid}_oracle.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     if golden:
-        for j, xo in golden["x_schur"].items():
-            j = int(j)
-            parity[f"x{j}_mixed_rel"] = abs(x_mixed[j] - xo) / max(abs(xo), 1.0)
+        for key, xo in golden["x_schur"].items():
+            i, j = (0, int(key)) if "," not in key else map(int, key.split(","))
+            parity[f"x{i}{j}_mixed_rel"] = abs(x_mixed[i, j] - xo) / max(abs(xo), 1.0)
             if j < len(x64):
-                parity[f"x{j}_fp64_rel"] = abs(x64[j] - xo) / max(abs(xo), 1.0)
-    d = max((abs(x_mixed[j] - x64[j]) / max(abs(x64[j]), 1.0) for j in range(len(x64))), default=None)
+                parity[f"x{i}{j}_fp64_rel"] = abs(x64[j][i] - xo) / max(abs(xo), 1.0)
+    d = max((abs(x_mixed[i, j] - x64[j][i]) / max(abs(x64[j][i]), 1.0) for j in range(len(x64))
+             for i in range(nint)), default=None)
     parity["x_mixed_vs_fp64_rel_max"] = d
 
     # roofline of the dominant kernel class (live HIP-event durations over the timed region)
@@ -142,7 +153,7 @@ def main():
                 "bytes_per_launch": per_launch_bytes}
 
     cpu = None
-    if not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
+    if cid == 3 and not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
         cpu = cpu_baseline(U, eta[0, 0], cfg, golden, args.cpu_cap)
 
     total_ms = sum(p["ms"] for p in prof.values())
@@ -150,10 +161,8 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
-        "config": {"workload": "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, "
-                               "kappa 0.1200->0.1205, N_hit=12 as one multi-RHS batch, FP32 block/inner "
-                               "solves + FP64 defect correction",
-                   "lattice": list(lat), "blocks": list(blk), "n_hit": nhit, "tol": args.tol},
+        "config": {"workload": WORKLOADS[cid], "lattice": list(lat), "blocks": list(blk), "n_interp": nint,
+                   "n_hit": nhit, "tol": args.tol},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "dslash": dslash,

@@ -136,6 +136,31 @@ int ddwc_det_ratio_estimate(ddwc_ctx *ctx, double kappa1, double kappa2, int n_i
                             double *step_var_host, ddwc_stats *stats, void *stream);
 
 /*
+ * Derivatives of the two-flavour exponents (Eq. 3 / Eq. 8 as in ddwc_det_ratio_estimate).
+ * Given the upstream gradient gx_host = dL/dx_ij [n_interp][n_hit] of any scalar L of the
+ * exponents (e.g. L = log W_gl: gx_ij = -softmax_j(-x_ij)), returns
+ *   *dkappa2_host = dL/dkappa2 (through m2 = 1/(2 kappa2) - 4 and the interpolation masses
+ *                   m_i, linear in m), if dkappa2_host is not null;
+ *   dU            = dL/dRe U + i dL/dIm U for every link matrix (device, canonical
+ *                   [4][V][3][3] complex128, overwritten; hop and clover terms), if not null.
+ * The solves of the forward pass are recomputed (nothing is stored between calls); the
+ * adjoint solves use D^+ = g5 D g5 and Dhat^+ = g5 Dhat g5.  Same eta, n_hit, tol, prec
+ * and geometry rules as ddwc_det_ratio_estimate; two flavours only.
+ */
+int ddwc_det_ratio_grad(ddwc_ctx *ctx, double kappa1, double kappa2, int n_interp, int op, const void *eta,
+                        int n_hit, double tol, int prec, const double *gx_host, double *dkappa2_host, void *dU,
+                        ddwc_stats *stats, void *stream);
+
+/*
+ * Link derivative of F = sum_r w_host[r] Re <a_r, D b_r> (the force term an adjoint pass
+ * or an HMC step needs): dU = dF/dRe U + i dF/dIm U, hop and clover terms, device canonical
+ * [4][V][3][3] complex128, overwritten.  a, b: device, canonical [nrhs][V][4][3] complex128.
+ * Independent of the mass.  Synchronises the stream.
+ */
+int ddwc_link_force(ddwc_ctx *ctx, const void *a, const void *b, int nrhs, const double *w_host, void *dU,
+                    void *stream);
+
+/*
  * Kernel timing for measurement.  When enabled, launches of the library's kernels
  * are bracketed with HIP events on their stream; ddwc_profile_read synchronises and
  * returns, for kernel class `kclass` (DDWC_K_*), the number of launches and their

@@ -43,6 +43,8 @@ SIGNATURES = {
     "ddwc_schur_apply": (_I, [_P, _D, _I, _P, _P, _I, _D, _I, _PS, _P]),
     "ddwc_solve": (_I, [_P, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),
     "ddwc_det_ratio_estimate": (_I, [_P, _D, _D, _I, _I, _I, _P, _I, _D, _I, _PD, _PD, _PD, _PS, _P]),
+    "ddwc_det_ratio_grad": (_I, [_P, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _P, _PS, _P]),
+    "ddwc_link_force": (_I, [_P, _P, _P, _I, _PD, _P, _P]),
     "ddwc_profile_enable": (_I, [_P, _I]),
     "ddwc_profile_read": (_I, [_P, _I, _PLL, _PD, _PD]),
     "ddwc_dslash_bytes": (_D, [_P, _I, _I]),
@@ -196,6 +198,39 @@ class Context:
         if n_f == 1:
             x = x[..., 0] + 1j * x[..., 1]
         return {"x": x, "log_w_gl": lw.value, "step_var": var, "stats": st.as_dict(), "status": code}
+
+    def det_ratio_grad(self, kappa1, kappa2, eta, gx, op=OP_SCHUR, tol=1e-12, prec=FP64, want_kappa2=True,
+                       want_links=True):
+        """dL/dkappa2 and dL/dU (torch convention dL/dRe U + i dL/dIm U, complex128 [4, V, 3, 3] on the
+        device) for L = sum_ij gx[i, j] x_ij, with x_ij the two-flavour exponents of det_ratio_estimate."""
+        import torch
+        sh = tuple(eta.shape)
+        if len(sh) != 5 or sh[2:] != (self.V, 4, 3):
+            raise ValueError(f"eta must have shape (n_interp, n_hit, {self.V}, 4, 3)")
+        n_interp, n_hit = sh[:2]
+        gx = np.ascontiguousarray(np.asarray(gx, dtype=np.float64))
+        if gx.shape != (n_interp, n_hit):
+            raise ValueError(f"gx must have shape ({n_interp}, {n_hit})")
+        dk = ctypes.c_double()
+        dU = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device=eta.device) if want_links else None
+        st = Stats()
+        _check(lib().ddwc_det_ratio_grad(
+            self._h, float(kappa1), float(kappa2), int(n_interp), int(op), _ptr(eta), int(n_hit), float(tol),
+            int(prec), gx.ctypes.data_as(_PD), ctypes.byref(dk) if want_kappa2 else None,
+            _ptr(dU, what="dU") if want_links else None, ctypes.byref(st), _stream()), "ddwc_det_ratio_grad")
+        return {"dkappa2": dk.value if want_kappa2 else None, "dU": dU, "stats": st.as_dict()}
+
+    def link_force(self, a, b, w=None):
+        """dF/dRe U + i dF/dIm U for F = sum_r w_r Re <a_r, D b_r> (complex128 [4, V, 3, 3], device)."""
+        import torch
+        n = _spinors(a, self.V, "a")
+        if _spinors(b, self.V, "b") != n or tuple(a.shape) != tuple(b.shape):
+            raise ValueError("a and b must have the same shape")
+        w = np.ascontiguousarray(np.ones(n) if w is None else np.asarray(w, dtype=np.float64).reshape(n))
+        dU = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device=a.device)
+        _check(lib().ddwc_link_force(self._h, _ptr(a, what="a"), _ptr(b, what="b"), int(n), w.ctypes.data_as(_PD),
+                                     _ptr(dU, what="dU"), _stream()), "ddwc_link_force")
+        return dU
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddwc.so")
-SOURCES = ["kernels.hip", "block_solver.hip", "eo.hip", "block_eo.hip", "api.hip"]
+SOURCES = ["kernels.hip", "block_solver.hip", "eo.hip", "block_eo.hip", "grad.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

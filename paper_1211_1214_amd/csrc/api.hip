@@ -1048,6 +1048,192 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
     return DDWC_OK;
 }
 
+// Re <x, y> per RHS, to the host.
+static int redots(ddwc_ctx* C, Exec& ex, const double2* x, const double2* y, int nrhs, std::vector<double>& out) {
+    const int nt = tiles_of(C->g.V);
+    double *part, *sums;
+    CK(ws_t(C, "gr_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(C, "gr_sums", (size_t)nrhs * NPART, &sums));
+    launch_dots(ex, C->g, x, y, part, nrhs);
+    launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+    std::vector<double> h((size_t)nrhs * NPART);
+    HC(hipMemcpyAsync(h.data(), sums, sizeof(double) * h.size(), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipStreamSynchronize(ex.stream));
+    out.resize(nrhs);
+    for (int j = 0; j < nrhs; ++j) out[j] = h[(size_t)j * NPART];
+    return DDWC_OK;
+}
+
+// Gradient of L = sum_ij gx_ij x_ij (x_ij the two-flavour exponents of ddwc_det_ratio_estimate)
+// with respect to kappa2 and the links.  With y = M eta and z = D_n^-+ y (full M; D^+ = g5 D g5)
+// or z = Dhat_n^-+ y (Schur):  dx = 2 Re <z, dD_p eta> - 2 Re <z, dD_n y>, and for the Schur
+// form, with a = D_bb^-+ P z, c = D_ww^-+ D_bw^+ a, w1 = D_ww^-1 D_wb v, w2 = D_bb^-1 D_bw w1,
+//     <z, dDhat v> = <a, dD (w2 - w1)> + <c, dD (w1 - v)>,
+// so dDhat/dm gives <a, w2> + <c, w1> and the links enter through Re <a, dD b> pairs.
+extern "C" int ddwc_det_ratio_grad(ddwc_ctx* C, double kappa1, double kappa2, int n_interp, int op, const void* eta,
+                                   int n_hit, double tol, int prec, const double* gx, double* dkappa2, void* dU,
+                                   ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa1, n_hit, prec));
+    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
+    if (!eta || !gx) return fail(DDWC_EINVAL, "null argument");
+    if (!dkappa2 && !dU) return fail(DDWC_EINVAL, "neither dkappa2 nor dU requested");
+    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
+    for (size_t k = 0; k < (size_t)n_interp * n_hit; ++k)
+        if (!isfinite(gx[k])) return fail(DDWC_EINVAL, "non-finite upstream gradient");
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    const Geom& g = C->g;
+    const int nrhs = n_hit;
+    const size_t nw = vec_words(C, nrhs, true);
+    const double m1 = mass_of(kappa1), m2 = mass_of(kappa2);
+    double2 *E, *A, *W1, *W12, *A1, *Gs, *Z, *Y, *W1n, *W2n, *Y5, *Zh, *Ap, *Cp, *An, *Cn, *B;
+    const char* nm[17] = {"gr_E", "gr_A", "gr_W1", "gr_W12", "gr_A1", "gr_G", "gr_Z", "gr_Y", "gr_W1n",
+                          "gr_W2n", "gr_Y5", "gr_Zh", "gr_Ap", "gr_Cp", "gr_An", "gr_Cn", "gr_B"};
+    double2** vp[17] = {&E, &A, &W1, &W12, &A1, &Gs, &Z, &Y, &W1n, &W2n, &Y5, &Zh, &Ap, &Cp, &An, &Cn, &B};
+    for (int k = 0; k < 17; ++k) CK(ws_t(C, nm[k], nw, vp[k]));
+    cx<double>* Gd = nullptr;
+    double* wd;
+    CK(ws_t(C, "gr_w", (size_t)nrhs, &wd));
+    if (dU) {
+        CK(ws_t(C, "gr_force", (size_t)36 * g.V, &Gd));
+        HC(hipMemsetAsync(Gd, 0, (size_t)36 * g.V * sizeof(cx<double>), ex.stream));
+    }
+    auto force = [&](const double2* a, const double2* b, const std::vector<double>& w) -> int {
+        HC(hipMemcpyAsync(wd, w.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, ex.stream));
+        launch_force_hop(ex, g, C->nbr, a, b, wd, nrhs, Gd);
+        if (C->csw != 0.0) launch_force_clover(ex, g, C->U64, C->csw, a, b, wd, nrhs, Gd);
+        HC(hipStreamSynchronize(ex.stream));
+        return DDWC_OK;
+    };
+    SolveInfo si;
+    BlockInfo bi;
+    const int MAXIT = 5000;
+    double dLdm2 = 0;
+    std::vector<double> d1, d2, wpos(nrhs), wneg(nrhs);
+    for (int i = 0; i < n_interp; ++i) {
+        const double mp = ((double)i / n_interp) * m2 + ((double)(n_interp - i) / n_interp) * m1;
+        const double mn = ((double)(i + 1) / n_interp) * m2 + ((double)(n_interp - i - 1) / n_interp) * m1;
+        const double dm = mp - mn, fp = (double)i / n_interp, fn = (double)(i + 1) / n_interp;  // dm_i/dm2
+        const char* eta_i = (const char*)eta + (size_t)i * nrhs * g.V * 12 * 16;
+        const double* gi = gx + (size_t)i * nrhs;
+        for (int j = 0; j < nrhs; ++j) {
+            wpos[j] = 2 * gi[j];
+            wneg[j] = -2 * gi[j];
+        }
+        std::vector<double> dp(nrhs), dn(nrhs);
+        if (op == DDWC_OP_FULL) {
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_ALL);
+            CK(solve_internal(C, ex, mn, E, Z, nrhs, tol, MAXIT, prec, &si));  // psi
+            launch_axpby(ex, g, 1.0, E, dm, Z, Y, nrhs, MASK_ALL);             // y = eta + dm psi
+            launch_axpby(ex, g, 1.0, Y, 0.0, nullptr, Y5, nrhs, MASK_ALL);
+            launch_gamma5(ex, g, Y5, nrhs);
+            CK(solve_internal(C, ex, mn, Y5, Zh, nrhs, tol, MAXIT, prec, &si));
+            launch_gamma5(ex, g, Zh, nrhs);  // z = D_n^-+ y
+            CK(redots(C, ex, Zh, E, nrhs, d1));
+            CK(redots(C, ex, Zh, Y, nrhs, d2));
+            for (int j = 0; j < nrhs; ++j) {
+                dp[j] = 2 * d1[j];
+                dn[j] = -2 * d2[j];
+            }
+            if (dU) {
+                launch_axpby(ex, g, 1.0, E, -1.0, Y, B, nrhs, MASK_ALL);  // eta - y
+                CK(force(Zh, B, wpos));
+            }
+        } else {
+            // forward quantities of the difference form (as in ddwc_det_ratio_estimate)
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_P);
+            launch_hop<double>(ex, g, C->U64, E, A, nrhs, 1);
+            CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, MAXIT, prec, &bi));
+            CK(block_internal(C, ex, 1, mn, W1, W12, nrhs, tol, MAXIT, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, W1, A, nrhs, 0);
+            CK(block_internal(C, ex, 0, mp, A, A1, nrhs, tol, MAXIT, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, W12, A, nrhs, 0);
+            launch_axpby(ex, g, 1.0, A1, 1.0, A, A, nrhs, MASK_BLACK);
+            CK(block_internal(C, ex, 0, mn, A, Gs, nrhs, tol, MAXIT, prec, &bi));
+            launch_axpby(ex, g, dm, Gs, 0.0, nullptr, Gs, nrhs, MASK_P);
+            CK(schur_hat_inverse(C, ex, mn, Gs, Z, nrhs, tol, prec, &si));
+            launch_axpby(ex, g, 1.0, E, 1.0, Z, Y, nrhs, MASK_P);  // y = Mhat e
+            // w1, w2 for v = y at m_n (for v = e at m_p they are W1 and A1)
+            launch_hop<double>(ex, g, C->U64, Y, A, nrhs, 1);
+            CK(block_internal(C, ex, 1, mn, A, W1n, nrhs, tol, MAXIT, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, W1n, A, nrhs, 0);
+            CK(block_internal(C, ex, 0, mn, A, W2n, nrhs, tol, MAXIT, prec, &bi));
+            // adjoint: Dhat_P is not gamma_5-hermitian (D_bb^-1 acts from the left), but
+            // Dhat_P^-+ v = v - g5 P D_bw [D^-1 (g5 v)]_w, so zh = g5 z = u - P D_bw [D_n^-1 u]_w
+            // with u = g5 y; then a = g5 D_bb^-1 zh and c = g5 D_ww^-1 D_wb (g5 a)
+            launch_axpby(ex, g, 1.0, Y, 0.0, nullptr, Y5, nrhs, MASK_P);
+            launch_gamma5(ex, g, Y5, nrhs);
+            CK(solve_internal(C, ex, mn, Y5, W12, nrhs, tol, MAXIT, prec, &si));
+            launch_hop<double>(ex, g, C->U64, W12, A, nrhs, 0);
+            launch_axpby(ex, g, 1.0, Y5, -1.0, A, Zh, nrhs, MASK_P);
+            CK(block_internal(C, ex, 0, mp, Zh, Ap, nrhs, tol, MAXIT, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, Ap, A, nrhs, 1);
+            CK(block_internal(C, ex, 1, mp, A, Cp, nrhs, tol, MAXIT, prec, &bi));
+            CK(block_internal(C, ex, 0, mn, Zh, An, nrhs, tol, MAXIT, prec, &bi));
+            launch_hop<double>(ex, g, C->U64, An, A, nrhs, 1);
+            CK(block_internal(C, ex, 1, mn, A, Cn, nrhs, tol, MAXIT, prec, &bi));
+            launch_gamma5(ex, g, Ap, nrhs);
+            launch_gamma5(ex, g, Cp, nrhs);
+            launch_gamma5(ex, g, An, nrhs);
+            launch_gamma5(ex, g, Cn, nrhs);
+            CK(redots(C, ex, Ap, A1, nrhs, d1));
+            CK(redots(C, ex, Cp, W1, nrhs, d2));
+            for (int j = 0; j < nrhs; ++j) dp[j] = 2 * (d1[j] + d2[j]);
+            CK(redots(C, ex, An, W2n, nrhs, d1));
+            CK(redots(C, ex, Cn, W1n, nrhs, d2));
+            for (int j = 0; j < nrhs; ++j) dn[j] = -2 * (d1[j] + d2[j]);
+            if (dU) {
+                launch_axpby(ex, g, 1.0, A1, -1.0, W1, B, nrhs, MASK_ALL);
+                CK(force(Ap, B, wpos));
+                launch_axpby(ex, g, 1.0, W1, -1.0, E, B, nrhs, MASK_ALL);
+                CK(force(Cp, B, wpos));
+                launch_axpby(ex, g, 1.0, W2n, -1.0, W1n, B, nrhs, MASK_ALL);
+                CK(force(An, B, wneg));
+                launch_axpby(ex, g, 1.0, W1n, -1.0, Y, B, nrhs, MASK_ALL);
+                CK(force(Cn, B, wneg));
+            }
+        }
+        for (int j = 0; j < nrhs; ++j) dLdm2 += gi[j] * (dp[j] * fp + dn[j] * fn);
+    }
+    if (dkappa2) *dkappa2 = dLdm2 * (-0.5 / (kappa2 * kappa2));
+    if (dU) launch_links_export(ex, g, Gd, dU);
+    HC(hipStreamSynchronize(ex.stream));
+    HC(hipGetLastError());
+    fill_stats(stats, si.outer, si.inner, si.relres, t0);
+    if (dkappa2 && !isfinite(*dkappa2)) return fail(DDWC_ENONFINITE, "non-finite derivative");
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_link_force(ddwc_ctx* C, const void* a, const void* b, int nrhs, const double* w_host, void* dU,
+                               void* stream) {
+    CK(check_ctx(C));
+    if (nrhs < 1 || nrhs > 4096) return fail(DDWC_EINVAL, "nrhs must be in [1, 4096]");
+    if (!a || !b || !w_host || !dU) return fail(DDWC_EINVAL, "null argument");
+    for (int r = 0; r < nrhs; ++r)
+        if (!isfinite(w_host[r])) return fail(DDWC_EINVAL, "non-finite weight");
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    const Geom& g = C->g;
+    double2 *ai, *bi;
+    double* wd;
+    cx<double>* Gd;
+    CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &ai));
+    CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &bi));
+    CK(ws_t(C, "gr_w", (size_t)nrhs, &wd));
+    CK(ws_t(C, "gr_force", (size_t)36 * g.V, &Gd));
+    launch_import<double>(ex, g, a, ai, nrhs, MASK_ALL);
+    launch_import<double>(ex, g, b, bi, nrhs, MASK_ALL);
+    HC(hipMemcpyAsync(wd, w_host, sizeof(double) * nrhs, hipMemcpyHostToDevice, ex.stream));
+    HC(hipMemsetAsync(Gd, 0, (size_t)36 * g.V * sizeof(cx<double>), ex.stream));
+    launch_force_hop(ex, g, C->nbr, ai, bi, wd, nrhs, Gd);
+    if (C->csw != 0.0) launch_force_clover(ex, g, C->U64, C->csw, ai, bi, wd, nrhs, Gd);
+    launch_links_export(ex, g, Gd, dU);
+    HC(hipStreamSynchronize(ex.stream));
+    HC(hipGetLastError());
+    return DDWC_OK;
+}
+
 extern "C" int ddwc_profile_enable(ddwc_ctx* C, int on) {
     CK(check_ctx(C));
     C->prof.harvest();

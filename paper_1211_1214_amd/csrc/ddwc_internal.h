@@ -138,6 +138,18 @@ void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, 
 // partials: (x, y) complex and (y, y) per RHS; x may equal y.
 void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs);
 
+// ------------------------------------------------------------------ derivatives (grad.hip)
+// v <- gamma_5 v (negates spins 2, 3), in place, FP64 internal fields.
+void launch_gamma5(Exec& e, const Geom& g, double2* v, int nrhs);
+// G += d/dU sum_r w_r Re <a_r, D b_r>: the hop part (force_hop) and the clover part
+// (force_clover, atomic adds).  G internal [4][9][V]; w device array [nrhs].
+void launch_force_hop(Exec& e, const Geom& g, const int* nbr, const double2* a, const double2* b, const double* w,
+                      int nrhs, cx<double>* G);
+void launch_force_clover(Exec& e, const Geom& g, const cx<double>* U, double csw, const double2* a, const double2* b,
+                         const double* w, int nrhs, cx<double>* G);
+// internal link-shaped field -> canonical [4][V][3][3] complex128
+void launch_links_export(Exec& e, const Geom& g, const cx<double>* G, void* canon);
+
 // ------------------------------------------------------------------ even-odd (eo.hip)
 // Half-field data of one precision: links, clover and neighbour table of each parity.
 template <class R>

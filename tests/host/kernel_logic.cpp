@@ -138,3 +138,53 @@ extern "C" int host_eo_apply(const int* lat, const int* blk, int tbc, double csw
     }
     return 0;
 }
+
+// Link gradient of Re <a, D(U) b> (one RHS, weight 1) with the library's force code: hop part
+// and clover part, in canonical layout [4][V][3][3] (re, im).
+#include "../../paper_1211_1214_amd/csrc/force.h"
+struct HostAdder {
+    std::vector<cx<double>>* G;
+    int V;
+    void operator()(int mu, int s, const M3& m) const {
+        for (int k = 0; k < 9; ++k) (*G)[((size_t)mu * 9 + k) * V + s] = (*G)[((size_t)mu * 9 + k) * V + s] + m.a[k];
+    }
+};
+extern "C" int host_force(const int* lat, const int* blk, int tbc, double csw, const double* links_canon,
+                          const double* a_canon, const double* b_canon, double* grad_canon) {
+    Geom g = make_geom(lat, blk, tbc);
+    const int V = g.V;
+    std::vector<cx<double>> U((size_t)36 * V), G((size_t)36 * V, mk(0.0, 0.0));
+    std::vector<int> can(V), nbr((size_t)8 * V);
+    std::vector<double2> a((size_t)12 * V), b((size_t)12 * V);
+    for (int s = 0; s < V; ++s) {
+        const Site S = decode(g, s);
+        can[s] = canonical_index(g, S);
+        for (int mu = 0; mu < 4; ++mu) {
+            for (int k = 0; k < 9; ++k) {
+                const double* src = links_canon + 2 * (((size_t)mu * V + can[s]) * 9 + k);
+                U[((size_t)mu * 9 + k) * V + s] = mk(src[0], src[1]);
+            }
+            nbr[(size_t)(2 * mu) * V + s] = table_entry<+1>(g, s, S, mu);
+            nbr[(size_t)(2 * mu + 1) * V + s] = table_entry<-1>(g, s, S, mu);
+        }
+        for (int c = 0; c < 12; ++c) {
+            a[(size_t)c * V + s] = make_double2(a_canon[2 * ((size_t)can[s] * 12 + c)], a_canon[2 * ((size_t)can[s] * 12 + c) + 1]);
+            b[(size_t)c * V + s] = make_double2(b_canon[2 * ((size_t)can[s] * 12 + c)], b_canon[2 * ((size_t)can[s] * 12 + c) + 1]);
+        }
+    }
+    const double w = 1.0;
+    for (int s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu) force_hop_site(g, nbr.data(), a.data(), b.data(), &w, 1, G.data(), s, mu);
+    if (csw != 0.0) {
+        HostAdder add{&G, V};
+        for (int y = 0; y < V; ++y) force_clover_site(g, U.data(), csw, a.data(), b.data(), &w, 1, y, add);
+    }
+    for (int s = 0; s < V; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int k = 0; k < 9; ++k) {
+                const cx<double> v = G[((size_t)mu * 9 + k) * V + s];
+                grad_canon[2 * (((size_t)mu * V + can[s]) * 9 + k)] = v.re;
+                grad_canon[2 * (((size_t)mu * V + can[s]) * 9 + k) + 1] = v.im;
+            }
+    return 0;
+}

@@ -24,7 +24,7 @@ def L():
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
     deps = [SRC] + [os.path.join(HERE, "..", "paper_1211_1214_amd", "csrc", f)
-                    for f in ("ddwc_device.h", "clover_build.h")]
+                    for f in ("ddwc_device.h", "clover_build.h", "eo.h", "force.h")]
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
         subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared", SRC,
                                "-o", LIB + ".tmp"], stderr=subprocess.DEVNULL)
@@ -33,6 +33,7 @@ def L():
     P = ctypes.c_void_p
     lib.host_apply.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_double, ctypes.c_int,
                                ctypes.c_int, P, P]
+    lib.host_force.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, P, P]
     return lib
 
 
@@ -103,3 +104,31 @@ def test_host_even_odd_operator(L, lat, blk, tbc):
     got = out.reshape(-1)
     assert np.abs(got[ev] - want).max() < 1e-12 * np.abs(want).max()
     assert np.all(got[od] == 0)
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.0])
+def test_host_force_matches_finite_differences(L, csw):
+    """The force code's gradient G of Re <a, D(U) b> (hop and clover terms) against extrapolated
+    central differences of the oracle's operator along a random link direction dU:
+    Re sum conj(G) dU = d/dh Re <a, D(U + h dU) b>."""
+    lat, blk = (4, 4, 2, 6), (2, 2, 1, 3)
+    V = int(np.prod(lat))
+    U = np.ascontiguousarray(inputs.make_links(lat, 0.3, 8))
+    rng = np.random.default_rng(3)
+    a = np.ascontiguousarray(rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3)))
+    b = np.ascontiguousarray(rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3)))
+    dU = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+    G = np.zeros_like(U)
+    L.host_force((ctypes.c_int * 4)(*lat), (ctypes.c_int * 4)(*blk), -1, csw, U.ctypes.data, a.ctypes.data,
+                 b.ctypes.data, G.ctypes.data)
+
+    def f(h):
+        D = dirac.dirac(U + h * dU, lat, 0.1, csw, -1)
+        return float(np.vdot(a.reshape(-1), D @ b.reshape(-1)).real)
+
+    def d(h):
+        return (f(h) - f(-h)) / (2 * h)
+
+    fd = (4 * d(5e-5) - d(1e-4)) / 3
+    got = float(np.sum(np.conj(G) * dU).real)
+    assert abs(got - fd) < 1e-8 * abs(fd), (got, fd)

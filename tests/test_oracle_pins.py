@@ -452,3 +452,42 @@ def test_one_flavour_log_domain_combination():
     assert abs(estimator.step_variance_one_flavour(x)[0] - w0.var(ddof=1) / w0.mean() ** 2) < 1e-13
     neg = np.array([[1.0 + np.pi * 1j, 1.5 + 0.9 * np.pi * 1j]])
     assert np.isnan(estimator.log_w_one_flavour(neg))
+
+
+# --------------------------------------------------------------------------- block determinants (Eq. 7)
+def test_block_logdets_compose_the_colour_blocks():
+    """D_bb and D_ww are the direct sums of the Dirichlet blocks: their log-determinants add up."""
+    lat, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    S = Schwarz(inputs.make_links(lat, 0.3, 2), lat, blk, 1.0)
+    m = dirac.mass(0.121)
+    Dbb, _, _, Dww = (a.toarray() for a in S.parts(m))
+    for c, Dc in ((0, Dbb), (1, Dww)):
+        ld = S.block_logdets(c, m)
+        assert len(ld) == 8
+        total = sum(l for _, l in ld) + np.log(np.prod([s for s, _ in ld]) + 0j)
+        assert _same_logdet(total, _slogdet(Dc), 1e-12)
+
+
+def test_block_logdets_single_site_blocks():
+    """1^4 blocks: D_k = (4 + m) + C(x), Hermitian positive definite; ln det = sum ln eigenvalues."""
+    lat, blk = (4, 4, 2, 2), (1, 1, 1, 1)
+    U = inputs.make_links(lat, 0.3, 3)
+    S = Schwarz(U, lat, blk, 1.0)
+    m = dirac.mass(0.121)
+    C = dirac.clover_term(U, lat, 1.0)
+    col = lt.colour(lat, blk)
+    for c in (0, 1):
+        ld = S.block_logdets(c, m)
+        want = [np.sum(np.log(np.linalg.eigvalsh((4 + m) * np.eye(12) + C[x]))) for x in np.nonzero(col == c)[0]]
+        assert all(s == 1.0 for s, _ in ld)
+        assert np.allclose([l for _, l in ld], want, rtol=0, atol=1e-12)
+
+
+def test_full_reweighting_factor_factorises():
+    """2 [ln|det D(m2)| - ln|det D(m1)|] = 2 [ln|det Dhat_P(m2)| - ln|det Dhat_P(m1)|] + block part."""
+    lat, blk = (4, 4, 4, 4), (2, 2, 2, 2)
+    S = Schwarz(inputs.make_links(lat, 0.3, 2), lat, blk, 1.0)
+    m1, m2 = dirac.mass(0.12), dirac.mass(0.121)
+    lhs = 2 * (_slogdet(S.D(m2).toarray()).real - _slogdet(S.D(m1).toarray()).real)
+    rhs = 2 * (_slogdet(S.hat_dense(m2)).real - _slogdet(S.hat_dense(m1)).real) + S.log_w_blocks(m1, m2)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)

@@ -161,6 +161,18 @@ int ddwc_link_force(ddwc_ctx *ctx, const void *a, const void *b, int nrhs, const
                     void *stream);
 
 /*
+ * Exact ln|det D_k(m)| and sign of every Dirichlet Schwarz block k of one colour (the block
+ * factor of Eq. 7: det D = det Dhat * det D_bb * det D_ww, D_bb and D_ww the direct sums of
+ * the D_k).  logabs_host [NBc], sign_host [NBc] (may be null), in the library's block order:
+ * blocks of the colour sorted by block coordinates (n_0, n_1, n_2, n_3) lexicographically.
+ * With every block extent even the odd sites are eliminated first (det D_k = prod det A_oo *
+ * det M_k), so the dense LU has dimension 6 Vb; otherwise 12 Vb.  EINVAL if one dense block
+ * exceeds 16 GiB; EUNDEF if a block is singular or its determinant is not real to 1e-6.
+ * Synchronises the stream.
+ */
+int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_host, int *sign_host, void *stream);
+
+/*
  * Kernel timing for measurement.  When enabled, launches of the library's kernels
  * are bracketed with HIP events on their stream; ddwc_profile_read synchronises and
  * returns, for kernel class `kclass` (DDWC_K_*), the number of launches and their

@@ -45,6 +45,7 @@ SIGNATURES = {
     "ddwc_det_ratio_estimate": (_I, [_P, _D, _D, _I, _I, _I, _P, _I, _D, _I, _PD, _PD, _PD, _PS, _P]),
     "ddwc_det_ratio_grad": (_I, [_P, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _P, _PS, _P]),
     "ddwc_link_force": (_I, [_P, _P, _P, _I, _PD, _P, _P]),
+    "ddwc_block_logdet": (_I, [_P, _D, _I, _PD, _PI, _P]),
     "ddwc_profile_enable": (_I, [_P, _I]),
     "ddwc_profile_read": (_I, [_P, _I, _PLL, _PD, _PD]),
     "ddwc_dslash_bytes": (_D, [_P, _I, _I]),
@@ -231,6 +232,22 @@ class Context:
         _check(lib().ddwc_link_force(self._h, _ptr(a, what="a"), _ptr(b, what="b"), int(n), w.ctypes.data_as(_PD),
                                      _ptr(dU, what="dU"), _stream()), "ddwc_link_force")
         return dU
+
+    def block_logdet(self, kappa, colour):
+        """(ln|det D_k|, sign) of every Dirichlet block of one colour, blocks sorted by coordinates."""
+        nbc = int(np.prod([l // b for l, b in zip(self.lat, self.blk)])) // 2
+        la = np.zeros(nbc)
+        sg = np.zeros(nbc, dtype=np.int32)
+        _check(lib().ddwc_block_logdet(self._h, float(kappa), int(colour), la.ctypes.data_as(_PD),
+                                       sg.ctypes.data_as(_PI), _stream()), "ddwc_block_logdet")
+        return la, sg
+
+    def log_w_blocks(self, kappa1, kappa2):
+        """Block factor of log W for two flavours (Eq. 7): 2 sum_k [ln|det D_k(m2)| - ln|det D_k(m1)|]."""
+        tot = 0.0
+        for c in (BLACK, WHITE):
+            tot += self.block_logdet(kappa2, c)[0].sum() - self.block_logdet(kappa1, c)[0].sum()
+        return 2 * tot
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <string>
@@ -117,6 +118,7 @@ struct ddwc_ctx {
     };
     std::map<std::string, Buf> ws;
     double* host = nullptr;  // pinned scratch for small device-to-host copies
+    void* blas = nullptr;    // dense linear-algebra handle (block determinants), created on first use
     size_t host_n = 0;
 };
 
@@ -241,6 +243,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
 }
 
 extern "C" int ddwc_destroy(ddwc_ctx* C) {
+    if (C && C->blas) blas_handle_destroy(C->blas);
     if (!C) return DDWC_OK;
     (void)hipDeviceSynchronize();
     C->prof.harvest();
@@ -1231,6 +1234,60 @@ extern "C" int ddwc_link_force(ddwc_ctx* C, const void* a, const void* b, int nr
     launch_links_export(ex, g, Gd, dU);
     HC(hipStreamSynchronize(ex.stream));
     HC(hipGetLastError());
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_block_logdet(ddwc_ctx* C, double kappa, int colour, double* logabs_host, int* sign_host,
+                                 void* stream) {
+    CK(check_common(C, kappa, 1, DDWC_FP64));
+    if (colour != DDWC_BLACK && colour != DDWC_WHITE) return fail(DDWC_EINVAL, "colour must be 0 or 1");
+    if (!logabs_host) return fail(DDWC_EINVAL, "null argument");
+    const Geom& g = C->g;
+    const size_t n = g.eo ? (size_t)12 * g.hvb : (size_t)12 * g.Vb;
+    const size_t mbytes = n * n * sizeof(cx<double>);
+    const size_t budget = (size_t)16 << 30;  // device memory for one batch of dense blocks
+    if (mbytes > budget) return fail(DDWC_EINVAL, "Schwarz block too large for dense block determinants");
+    const int NB = g.NBc;
+    const int batch = (int)std::min<size_t>((size_t)NB, std::max<size_t>(1, budget / mbytes));
+    if (!C->blas && !(C->blas = blas_handle_create())) return fail(DDWC_EHIP, "dense linear-algebra handle");
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    const double mass4 = 4.0 + mass_of(kappa);
+    cx<double>* Mat;
+    int *ipiv, *info;
+    double *odd, *lu;
+    CK(ws_t(C, "bd_mat", (size_t)batch * n * n, &Mat));
+    CK(ws_t(C, "bd_ipiv", (size_t)batch * n, &ipiv));
+    CK(ws_t(C, "bd_info", (size_t)batch, &info));
+    CK(ws_t(C, "bd_odd", (size_t)NB, &odd));
+    CK(ws_t(C, "bd_lu", (size_t)2 * NB, &lu));
+    HC(hipMemsetAsync(odd, 0, NB * sizeof(double), ex.stream));
+    if (g.eo) launch_bd_oddlogdet(ex, g, C->K64, mass4, colour, odd);
+    std::vector<int> hinfo(batch);
+    bool singular = false;
+    for (int r0 = 0; r0 < NB; r0 += batch) {
+        const int nb = std::min(batch, NB - r0);
+        const int st = block_logdet_run(ex, g, C->U64, C->K64, C->nbr, mass4, colour, r0, nb, C->blas, Mat, ipiv,
+                                        info, lu + 2 * r0);
+        if (st != 0) return fail(DDWC_EHIP, "batched LU of the block matrices failed (" + std::to_string(st) + ")");
+        HC(hipMemcpyAsync(hinfo.data(), info, nb * sizeof(int), hipMemcpyDeviceToHost, ex.stream));
+        HC(hipStreamSynchronize(ex.stream));
+        for (int b = 0; b < nb; ++b) singular |= hinfo[b] != 0;
+    }
+    std::vector<double> hodd(NB), hlu(2 * NB);
+    HC(hipMemcpyAsync(hodd.data(), odd, NB * sizeof(double), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipMemcpyAsync(hlu.data(), lu, 2 * NB * sizeof(double), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipStreamSynchronize(ex.stream));
+    HC(hipGetLastError());
+    bool undefined = singular;
+    for (int b = 0; b < NB; ++b) {
+        logabs_host[b] = hodd[b] + hlu[2 * b];
+        // det D_k is real: the phase is a multiple of pi up to rounding
+        const double ph = hlu[2 * b + 1];
+        const double c = cos(ph), sn = sin(ph);
+        if (!isfinite(logabs_host[b]) || fabs(sn) > 1e-6) undefined = true;
+        if (sign_host) sign_host[b] = c >= 0 ? 1 : -1;
+    }
+    if (undefined) return fail(DDWC_EUNDEF, "block determinant singular, not finite or not real");
     return DDWC_OK;
 }
 

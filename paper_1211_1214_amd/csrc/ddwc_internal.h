@@ -150,6 +150,17 @@ void launch_force_clover(Exec& e, const Geom& g, const cx<double>* U, double csw
 // internal link-shaped field -> canonical [4][V][3][3] complex128
 void launch_links_export(Exec& e, const Geom& g, const cx<double>* G, void* canon);
 
+// ------------------------------------------------------------------ block determinants (blockdet.hip)
+// Assembles the dense block matrices (M_k when g.eo, else D_k) of blocks r0 .. r0 + nb - 1 of
+// `colour` into Mat (column-major, nb x n x n), factors them (batched LU, handle rb) and
+// writes per block (sum ln|U_ii|, phase) to lu_out[2 nb].  Returns 0 or a negative code.
+int block_logdet_run(Exec& e, const Geom& g, const cx<double>* U, const double2* K, const int* nbr, double mass4,
+                     int colour, int r0, int nb, void* rb, cx<double>* Mat, int* ipiv, int* info, double* lu_out);
+// per block of `colour`: sum over its odd sites of ln det A(x)
+void launch_bd_oddlogdet(Exec& e, const Geom& g, const double2* K, double mass4, int colour, double* out);
+void* blas_handle_create();
+void blas_handle_destroy(void* h);
+
 // ------------------------------------------------------------------ even-odd (eo.hip)
 // Half-field data of one precision: links, clover and neighbour table of each parity.
 template <class R>

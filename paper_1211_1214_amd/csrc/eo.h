@@ -88,6 +88,54 @@ DDWC_HD void herm6_inverse(const double* d, const double* o, double shift, doubl
     }
 }
 
+// ln det of the Hermitian positive definite 6x6 block (shift + K) (packing of herm6_inverse),
+// from its Cholesky factor: 2 sum_j ln L_jj.  Returns NaN if the block is not positive definite.
+DDWC_HD double herm6_logdet(const double* d, const double* o, double shift) {
+    cx<double> A[6][6];
+    int k = 0;
+    for (int i = 0; i < 6; ++i) {
+        A[i][i] = mk(shift + d[i], 0.0);
+        for (int j = i + 1; j < 6; ++j) {
+            A[i][j] = mk(o[2 * k], o[2 * k + 1]);
+            A[j][i] = mk(o[2 * k], -o[2 * k + 1]);
+            ++k;
+        }
+    }
+    cx<double> L[6][6];
+    double ld = 0;
+    for (int j = 0; j < 6; ++j) {
+        double djj = A[j][j].re;
+        for (int q = 0; q < j; ++q) djj -= L[j][q].re * L[j][q].re + L[j][q].im * L[j][q].im;
+        if (!(djj > 0)) return NAN;
+        const double ljj = sqrt(djj);
+        ld += 2.0 * log(ljj);
+        L[j][j] = mk(ljj, 0.0);
+        for (int i = j + 1; i < 6; ++i) {
+            cx<double> t = A[i][j];
+            for (int q = 0; q < j; ++q) t = t - L[i][q] * mk(L[j][q].re, -L[j][q].im);
+            L[i][j] = mk(t.re / ljj, t.im / ljj);
+        }
+    }
+    return ld;
+}
+
+// out = (shift + A) v for the packed pair of Hermitian 6x6 blocks a[72] (layout of ddwc_device.h).
+DDWC_HD void packed_apply(const double a[72], double shift, const cx<double> v[12], cx<double> out[12]) {
+    for (int blk = 0; blk < 2; ++blk) {
+        const cx<double>* x = v + 6 * blk;
+        cx<double>* y = out + 6 * blk;
+        for (int i = 0; i < 6; ++i) y[i] = mk((shift + a[6 * blk + i]) * x[i].re, (shift + a[6 * blk + i]) * x[i].im);
+        int k = 0;
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j) {
+                const cx<double> aij = mk(a[12 + 30 * blk + 2 * k], a[12 + 30 * blk + 2 * k + 1]);
+                cmadd(y[i], aij, x[j]);
+                cjmadd(y[j], aij, x[i]);
+                ++k;
+            }
+    }
+}
+
 // Packed inverse of A = (4 + m) + C at one site: a = packed clover (72 reals), mass4 = 4 + m.
 DDWC_HD void clover_inverse_site(const double a[72], double mass4, double out[72]) {
     for (int blk = 0; blk < 2; ++blk) herm6_inverse(a + 6 * blk, a + 12 + 30 * blk, mass4, out + 6 * blk, out + 12 + 30 * blk);

@@ -147,8 +147,9 @@ def main():
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
     ds = prof["dslash32"]
     dslash_gbs = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9 if ds["ms"] > 0 else None
+    traffic = measured_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "launches": pd["launches"], "avg_launch_us": round(per_launch_ms * 1e3, 2),
                 "bytes_per_launch": per_launch_bytes}
 
@@ -176,6 +177,42 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def kernel_sources_digest():
+    """Digest of the library's kernel sources and build flags: a stored counter measurement is
+    used only while it matches the code that is running."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1211_1214_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1211_1214_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# kernel whose counters stand for each profiler class
+CLASS_KERNEL = {"block": "void ddwc::k_blk_inner<float>"}
+
+
+def measured_traffic(workload, kclass):
+    """HBM bytes per dispatch (FETCH_SIZE and WRITE_SIZE, calibrated) of the kernel of `kclass`,
+    from profiles/traffic_<workload>.json if it was measured on the current sources, else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    name = CLASS_KERNEL.get(kclass)
+    if not name or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("sources") != kernel_sources_digest():
+        return None
+    for k, v in rec["kernels"].items():
+        if k.startswith(name):
+            return v["read_bytes"] + v["write_bytes"]
+    return None
 
 
 def dslash_rates(ctx, dd, inputs, lat, dev, reps):

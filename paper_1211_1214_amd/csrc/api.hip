@@ -713,12 +713,11 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
         info->block_iters += isum;
     }
     if (C->prof.on) {
-        // algorithmic bytes per even site and inner iteration: 25 half-spinor passes and two
-        // applications of M_k, each reading both parities' links twice (16 links per
-        // even-odd pair), the even clover and the odd inverse.
+        // algorithmic bytes of the persistent inner kernel per even site and iteration: 25
+        // half-spinor passes and two applications of M_k, each reading both parities' links
+        // twice (16 links per even-odd pair), the even clover and the odd inverse.
         const double S = 24.0 * (fp64 ? 8 : 4), Gk = (16 * 18.0 + 144.0) * (fp64 ? 8 : 4);
-        C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * (25 * S + 2 * Gk) +
-                                       (double)nout * nb * g.hvb * (6 * 192.0 + 16 * 18 * 8.0 + 144 * 8.0);
+        C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * (25 * S + 2 * Gk);
     }
     if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
     if (!converged) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");

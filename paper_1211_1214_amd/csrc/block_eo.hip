@@ -359,18 +359,18 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
 
 void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                      double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs) {
-    Timed t(e, 2, 0);
+    Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
     k_blk_prep<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, bpe, re, xe, to, bb, rr, colour, nrhs);
 }
 void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,
                       const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs) {
-    Timed t(e, 2, 0);
+    Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
     k_blk_resid<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, bpe, xe, re, to, rr, mass4, colour,
                                                                     nrhs);
 }
 void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                       const double2* xe, double2* x, int colour, int nrhs) {
-    Timed t(e, 2, 0);
+    Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
     k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
 }
 template <class R>

@@ -40,8 +40,8 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("c3", "c4"), default="c3",
-                    help="c3: 48x24^3, 6^4 blocks, 12 RHS (default); c4: 64x32^3, 8^4 blocks, 4 steps, 24 RHS")
+    ap.add_argument("--workload", choices=("48x24", "64x32"), default="48x24",
+                    help="48x24: 48x24^3, 6^4 blocks, 12 RHS (default); 64x32: 64x32^3, 8^4 blocks, 4 steps, 24 RHS")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -73,7 +73,7 @@ def main():
     import paper_1211_1214_amd as dd
     from paper_1211_1214_amd import inputs
 
-    cid = 3 if args.workload == "c3" else 4
+    cid = 3 if args.workload == "48x24" else 4
     cfg = inputs.CONFIGS[cid]
     lat, blk, nhit, nint = cfg["lat"], cfg["blk"], cfg["n_hit"], cfg["n_interp"]
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
@@ -125,9 +125,9 @@ def main():
 
     dslash = dslash_rates(ctx, dd, inputs, lat, dev, args.dslash_reps) if args.dslash_reps > 0 else None
 
-    # parity against the stored oracle exponents (written by tests/golden/make_c{3,4}_golden.py)
+    # parity against the stored oracle exponents (written by tests/golden/make_golden_{48x24,64x32}.py)
     parity = {}
-    gpath = os.path.join(ROOT, "tests", "golden", f"c{cid}_oracle.json")
+    gpath = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     if golden:
         for key, xo in golden["x_schur"].items():
@@ -263,7 +263,7 @@ def cpu_baseline(U, eta0, cfg, golden, cap):
     return {"value": round(1.0 / est, 5), "unit": "estimates/s", "cores": cref.CRef.threads(), "kind": "oracle",
             "sample": f"one Schur exponent on the same 48x24^3 workload with each of its {len(iters)} BiCGStab "
                       f"solves capped at {cap} iterations ({wall:.1f}s), scaled per solve by the oracle's own "
-                      f"iteration counts {full} for a full estimate (tests/golden/c3_oracle.json)"}
+                      f"iteration counts {full} for a full estimate (tests/golden/oracle_48x24.json)"}
 
 
 if __name__ == "__main__":

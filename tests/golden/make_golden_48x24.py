@@ -1,4 +1,4 @@
-"""Write tests/golden/c3_oracle.json: oracle exponents on the 48x24^3 workload.
+"""Write tests/golden/oracle_48x24.json: oracle exponents on the 48x24^3 workload.
 
 Calls only the oracle (the matrix-free C version).  The workload: 48x24^3 lattice,
 6^4 Schwarz blocks, synthetic links exp(i 0.3 H) with seed [1211, 3], c_sw = 1,
@@ -8,7 +8,7 @@ solves to 1e-13) for the first noise vectors, the full-operator exponent for j =
 and the iteration counts of the oracle's own solves for one Schur exponent (used to
 scale the benchmark's bounded CPU sample to one estimate).
 
-Run: python tests/golden/make_c3_golden.py [n_schur]
+Run: python tests/golden/make_golden_48x24.py [n_schur]
 """
 import json
 import os
@@ -46,7 +46,7 @@ def main(n_schur=2):
     out["x_full"]["0"] = x
     out["full_solve_iterations"] = iters
     print("full", x, iters, flush=True)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_oracle.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_48x24.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

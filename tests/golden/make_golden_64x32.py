@@ -1,4 +1,4 @@
-"""Write tests/golden/c4_oracle.json: oracle exponents on the 64x32^3 workload.
+"""Write tests/golden/oracle_64x32.json: oracle exponents on the 64x32^3 workload.
 
 Calls only the oracle (the matrix-free C version).  The workload: 64x32^3 lattice,
 8^4 Schwarz blocks, synthetic links exp(i 0.3 H) with seed [1211, 4], c_sw = 1,
@@ -7,7 +7,7 @@ complex Gaussian noise with seed [1214, 4, i, j].  Stored: the Schur-complement 
 x_ij (difference form, all solves to 1e-13) of the first interpolation step i = 0 for the
 first noise vectors j, and the last step i = 3 for j = 0.
 
-Run: python tests/golden/make_c4_golden.py [n_first_step]
+Run: python tests/golden/make_golden_64x32.py [n_first_step]
 """
 import json
 import os
@@ -38,7 +38,7 @@ def main(n_first=1):
         out["x_schur"][f"{i},{j}"] = x
         out["seconds"][f"{i},{j}"] = time.time() - t0
         print("schur", i, j, x, time.time() - t0, flush=True)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_oracle.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_64x32.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

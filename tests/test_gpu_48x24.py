@@ -5,7 +5,7 @@ The oracle cannot redo the whole batch in seconds, so the checks are
   * the operator on every site against the C oracle (FP64 one RHS; FP32 on sampled RHS),
   * solve and block-solve residuals measured with the oracle's operator (a property that
     holds at any size),
-  * sampled exponents x_0j against the oracle values stored by tests/golden/make_c3_golden.py.
+  * sampled exponents x_0j against the oracle values stored by tests/golden/make_golden_48x24.py.
 """
 import json
 import os
@@ -21,7 +21,7 @@ from oracle import cref, dirac  # noqa: E402
 from paper_1211_1214_amd import inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_48x24.json")
 TOL = 1e-10  # the benchmark's solver tolerance
 
 
@@ -31,15 +31,15 @@ def say(*a):
 
 
 @pytest.fixture(scope="module")
-def c3():
+def lat48():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     cfg = inputs.CONFIGS[3]
-    say("c3: generating inputs")
+    say("48x24: generating inputs")
     U = inputs.make_links(cfg["lat"], cfg["eps"], 3)
     dev = torch.device("cuda:0")
     ctx = dd.Context(torch.from_numpy(U).to(dev), cfg["lat"], cfg["blk"], -1, cfg["csw"])
-    say("c3: building the C oracle field")
+    say("48x24: building the C oracle field")
     R = cref.CRef(U, cfg["lat"], cfg["blk"], cfg["csw"], -1)
     yield cfg, U, dev, ctx, R
     ctx.close()
@@ -50,33 +50,33 @@ def rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def test_c3_dslash(c3):
-    cfg, U, dev, ctx, R = c3
+def test_48x24_dslash(lat48):
+    cfg, U, dev, ctx, R = lat48
     lat = cfg["lat"]
-    say("c3 dslash fp64")
+    say("48x24 dslash fp64")
     psi = inputs.make_spinor(lat, 101)
     m = dirac.mass(cfg["kappa2"])
     got = ctx.dslash_apply(cfg["kappa2"], torch.from_numpy(psi).to(dev)).cpu().numpy()
     assert rel(got, R.dslash(m, psi)) < 1e-12
-    say("c3 dslash fp32, 12 RHS")
+    say("48x24 dslash fp32, 12 RHS")
     psi = inputs.make_spinor(lat, 102, nrhs=cfg["n_hit"])
     got = ctx.dslash_apply(cfg["kappa2"], torch.from_numpy(psi).to(dev), prec=dd.MIXED32).cpu().numpy()
     for j in (0, 5, 11):
         assert rel(got[j], R.dslash(m, psi[j])) < 2e-6
 
 
-def test_c3_solve_residuals(c3):
-    cfg, U, dev, ctx, R = c3
+def test_48x24_solve_residuals(lat48):
+    cfg, U, dev, ctx, R = lat48
     lat = cfg["lat"]
     m = dirac.mass(cfg["kappa2"])
     b = inputs.make_noise_batch(lat, 3, 1, 2)[0]
-    say("c3 global solve, mixed")
+    say("48x24 global solve, mixed")
     x, st = ctx.solve(cfg["kappa2"], torch.from_numpy(b).to(dev), tol=TOL, prec=dd.MIXED32)
     x = x.cpu().numpy()
     for j in range(2):
         r = b[j] - R.dslash(m, x[j])
         assert np.linalg.norm(r) <= 1.05 * TOL * np.linalg.norm(b[j])
-    say("c3 block solves, mixed, both colours")
+    say("48x24 block solves, mixed, both colours")
     for colour in (0, 1):
         xb, st = ctx.block_solve(colour, cfg["kappa1"], torch.from_numpy(b).to(dev), tol=TOL, prec=dd.MIXED32)
         xb = xb.cpu().numpy()
@@ -91,22 +91,22 @@ def test_c3_solve_residuals(c3):
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden exponents not generated")
-def test_c3_exponents_against_oracle(c3):
-    cfg, U, dev, ctx, R = c3
+def test_48x24_exponents_against_oracle(lat48):
+    cfg, U, dev, ctx, R = lat48
     gold = json.load(open(GOLDEN))
     lat, nhit = cfg["lat"], cfg["n_hit"]
     eta = inputs.make_noise_batch(lat, 3, 1, nhit)
     etad = torch.from_numpy(eta).to(dev)
-    say("c3 estimate, mixed, 12 RHS")
+    say("48x24 estimate, mixed, 12 RHS")
     res = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad, op=dd.OP_SCHUR, tol=TOL, prec=dd.MIXED32)
     for j, xo in gold["x_schur"].items():
         assert abs(res["x"][0, int(j)] - xo) <= 1e-8 * max(abs(xo), 1), (j, res["x"][0, int(j)], xo)
-    say("c3 estimate, FP64 single RHS")
+    say("48x24 estimate, FP64 single RHS")
     r64 = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad[:, :1].contiguous(), op=dd.OP_SCHUR, tol=TOL,
                                  prec=dd.FP64)
     xo = gold["x_schur"]["0"]
     assert abs(r64["x"][0, 0] - xo) <= 1e-8 * max(abs(xo), 1)
-    say("c3 estimate, full operator, mixed")
+    say("48x24 estimate, full operator, mixed")
     rf = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad[:, :2].contiguous(), op=dd.OP_FULL, tol=TOL,
                                 prec=dd.MIXED32)
     xo = gold["x_full"]["0"]

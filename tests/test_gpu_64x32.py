@@ -2,7 +2,7 @@
 block), N = 4 mass-interpolation steps and 24 RHS in one multi-RHS batch, mixed precision.
 
 The oracle cannot redo the batch in seconds, so the checks are
-  * sampled exponents x_ij against the oracle values stored by tests/golden/make_c4_golden.py,
+  * sampled exponents x_ij against the oracle values stored by tests/golden/make_golden_64x32.py,
   * the FP64 single-RHS path on noise vector 0 (all four steps) against the mixed batch,
   * the final residuals of the solver statistics.
 """
@@ -19,7 +19,7 @@ import paper_1211_1214_amd as dd  # noqa: E402
 from paper_1211_1214_amd import inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_oracle.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_64x32.json")
 
 
 def say(*a):
@@ -27,19 +27,19 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_c4_estimate():
+def test_64x32_estimate():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     cfg = inputs.CONFIGS[4]
     lat, blk = cfg["lat"], cfg["blk"]
-    say("c4: generating inputs")
+    say("64x32: generating inputs")
     U = inputs.make_links(lat, cfg["eps"], 4)
     eta = inputs.make_noise_batch(lat, 4, cfg["n_interp"], cfg["n_hit"])
     dev = torch.device("cuda:0")
     ctx = dd.Context(torch.from_numpy(U).to(dev), lat, blk, -1, cfg["csw"])
     etad = torch.from_numpy(eta).to(dev)
     del eta
-    say("c4: mixed estimate, 4 steps x 24 RHS")
+    say("64x32: mixed estimate, 4 steps x 24 RHS")
     res = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad, op=dd.OP_SCHUR, tol=1e-10, prec=dd.MIXED32)
     x = res["x"]
     assert x.shape == (4, 24) and np.all(np.isfinite(x))
@@ -48,9 +48,9 @@ def test_c4_estimate():
     gold = json.load(open(GOLDEN))
     for key, xo in gold["x_schur"].items():
         i, j = map(int, key.split(","))
-        say(f"c4: x[{i},{j}] = {x[i, j]!r}, oracle {xo!r}")
+        say(f"64x32: x[{i},{j}] = {x[i, j]!r}, oracle {xo!r}")
         assert abs(x[i, j] - xo) <= 1e-8 * max(abs(xo), 1.0)
-    say("c4: FP64 single-RHS path on noise vector 0")
+    say("64x32: FP64 single-RHS path on noise vector 0")
     r64 = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad[:, :1].contiguous(), op=dd.OP_SCHUR, tol=1e-10,
                                  prec=dd.FP64)
     assert np.all(np.abs(r64["x"][:, 0] - x[:, 0]) <= 1e-8 * np.maximum(np.abs(x[:, 0]), 1.0))

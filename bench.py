@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--inner", choices=("fp32", "fp16"), default=None,
+                    help="storage of the global inner solver (default: fp32 at 48x24, fp16 at 64x32)")
     ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -87,8 +89,11 @@ def main():
     ctx = dd.Context(Ud, lat, blk, -1, cfg["csw"])
     torch.cuda.synchronize()
 
+    inner = args.inner or ("fp32" if cid == 3 else "fp16")
+    prec = dd.MIXED16 if inner == "fp16" else dd.MIXED32
+
     def step():
-        return ctx.det_ratio_estimate(k1, k2, etad, op=dd.OP_SCHUR, tol=args.tol, prec=dd.MIXED32)
+        return ctx.det_ratio_estimate(k1, k2, etad, op=dd.OP_SCHUR, tol=args.tol, prec=prec)
 
     for w in range(args.warmup):
         r = step()
@@ -161,9 +166,13 @@ def main():
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
-        "config": {"workload": WORKLOADS[cid], "lattice": list(lat), "blocks": list(blk), "n_interp": nint,
-                   "n_hit": nhit, "tol": args.tol},
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 inner / f64 outer" if inner == "fp32" else "f16 storage, f32 arithmetic inner / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[cid] + ("" if inner == "fp32" else
+                                                 "; global inner solver in FP16 storage (per-site scales, FP16 links)"),
+                   "lattice": list(lat), "blocks": list(blk), "n_interp": nint, "n_hit": nhit, "tol": args.tol,
+                   "inner": inner},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "dslash": dslash,

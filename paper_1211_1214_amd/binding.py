@@ -15,7 +15,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libddwc.so")
 
 OK, EINVAL, ENOCONV, EHIP, ENONFINITE, EUNDEF = 0, -1, -2, -3, -4, -5
-FP64, MIXED32 = 0, 1
+FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER = range(5)

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ddwc.h"
@@ -101,6 +102,7 @@ struct ddwc_ctx {
     cx<double>* Uh64 = nullptr;
     cx<float>* Uh32 = nullptr;
     double2* Kh64 = nullptr;
+    cx<f16>* Uh16 = nullptr;  // FP16 half-order links (storage of the FP16 inner solver)
     float4* Kh32 = nullptr;
     int* nbr_eo = nullptr;
     struct Ainv {
@@ -165,7 +167,7 @@ static int check_common(const ddwc_ctx* C, double kappa, int nrhs, int prec) {
     CK(check_ctx(C));
     if (!(kappa > 0) || !isfinite(kappa)) return fail(DDWC_EINVAL, "kappa must be positive and finite");
     if (nrhs < 1 || nrhs > 65535) return fail(DDWC_EINVAL, "nrhs must be in [1, 65535]");
-    if (prec != DDWC_FP64 && prec != DDWC_MIXED32) return fail(DDWC_EINVAL, "unknown precision");
+    if (prec != DDWC_FP64 && prec != DDWC_MIXED32 && prec != DDWC_MIXED16) return fail(DDWC_EINVAL, "unknown precision");
     size_t words = (size_t)nrhs * 12 * C->g.V;
     if (words > (size_t)1 << 40) return fail(DDWC_EINVAL, "problem too large");
     return DDWC_OK;
@@ -226,11 +228,13 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
             hipMalloc(&C->Uh32, (size_t)2 * 36 * n2 * sizeof(cx<float>)) != hipSuccess ||
             hipMalloc(&C->Kh64, (size_t)2 * 36 * n2 * sizeof(double2)) != hipSuccess ||
             hipMalloc(&C->Kh32, (size_t)2 * 18 * n2 * sizeof(float4)) != hipSuccess ||
-            hipMalloc(&C->nbr_eo, (size_t)2 * 8 * n2 * sizeof(int)) != hipSuccess) {
+            hipMalloc(&C->nbr_eo, (size_t)2 * 8 * n2 * sizeof(int)) != hipSuccess ||
+            hipMalloc(&C->Uh16, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess) {
             ddwc_destroy(C);
             return fail(DDWC_EHIP, "device allocation of the even-odd fields failed");
         }
         launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Kh64, C->Kh32, C->nbr_eo);
+        launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32, C->Uh16);
     }
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
@@ -252,7 +256,7 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     if (C->K64) (void)hipFree(C->K64);
     if (C->K32) (void)hipFree(C->K32);
     if (C->nbr) (void)hipFree(C->nbr);
-    for (void* q : {(void*)C->Uh64, (void*)C->Uh32, (void*)C->Kh64, (void*)C->Kh32, (void*)C->nbr_eo})
+    for (void* q : {(void*)C->Uh64, (void*)C->Uh32, (void*)C->Kh64, (void*)C->Kh32, (void*)C->nbr_eo, (void*)C->Uh16})
         if (q) (void)hipFree(q);
     for (auto& a : C->ainv) {
         (void)hipFree(a.a64);
@@ -421,6 +425,18 @@ EoFields<float> eo_fields<float>(const ddwc_ctx* C) {
     return F;
 }
 
+template <>
+EoFields<H16> eo_fields<H16>(const ddwc_ctx* C) {
+    EoFields<H16> F;
+    F.n2 = C->g.V / 2;
+    for (int p = 0; p < 2; ++p) {
+        F.U[p] = C->Uh16 + (size_t)p * 36 * F.n2;
+        F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
+        F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
+    }
+    return F;
+}
+
 // Odd-site inverses of 4 + m + C for mass4 = 4 + m (kept for the last few masses).
 static int get_ainv(ddwc_ctx* C, Exec& ex, double mass4, const double2** a64, const float4** a32) {
     const size_t n2 = C->g.V / 2;
@@ -456,35 +472,46 @@ static int get_ainv(ddwc_ctx* C, Exec& ex, double mass4, const double2** a64, co
 // Mee = A_ee - 1/4 H_eo A_oo^-1 H_oe inside FP64 defect correction, then
 // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e).  The FP64 residual of the even system equals the
 // residual of the full system, so the stopping rule is ||b'_e - Mee x_e|| <= tol ||b||.
-template <class R>
+template <class S>
 static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
                     int maxit, SolveInfo* info) {
-    typedef typename Traits<R>::word W;
+    typedef typename Traits<S>::word W;
+    typedef typename Traits<S>::real R;
+    typedef typename Traits<S>::xs XS;
+    typedef typename Traits<XS>::word XW;
+    typedef typename Traits<S>::kword KW;
     const Geom& g = C->g;
-    const bool fp64 = sizeof(R) == 8;
+    const bool fp64 = std::is_same<S, double>::value, h16 = std::is_same<S, H16>::value;
     const EoFields<double> F64 = eo_fields<double>(C);
-    const EoFields<R> FR = eo_fields<R>(C);
+    const EoFields<S> FR = eo_fields<S>(C);
     const unsigned n2 = F64.n2;
     Geom gh = g;  // geometry of the half fields for the vector kernels (only V is used)
     gh.V = (int)n2;
     const int nt = tiles_of(n2);
     const int ntf = tiles_of(g.V);
-    // precision-R fields RHS-innermost: the RHS of a site share its links, clover and table
-    const bool ri = nrhs > 1 && nrhs <= WG;
+    // low-precision fields RHS-innermost: the RHS of a site share its links, clover and table
+    // (FP16 fields, whose scale plane follows the word planes, always are)
+    if (h16 && nrhs > WG) return fail(DDWC_EINVAL, "the FP16 inner solver takes at most 256 RHS");
+    const bool ri = h16 || (nrhs > 1 && nrhs <= WG);
     const int ntR = vector_tiles(n2, nrhs, ri);
     const double mass4 = 4.0 + mass;
     const double2* A64;
     const float4* A32;
     CK(get_ainv(C, ex, mass4, &A64, &A32));
-    const W* AR = fp64 ? (const W*)A64 : (const W*)A32;
-    const size_t hw64 = (size_t)nrhs * 12 * n2, hwR = (size_t)nrhs * (fp64 ? 12 : 6) * n2;
+    const KW* AR = fp64 ? (const KW*)A64 : (const KW*)A32;
+    const size_t hw64 = (size_t)nrhs * 12 * n2, stride = (size_t)nrhs * n2;
+    // bytes of one precision-S field (FP16: three word planes and a plane of float scales)
+    const size_t bytesR = h16 ? ((3 * 16 + 4) * stride + 15) / 16 * 16 : (size_t)Traits<S>::NCW * 16 * stride;
+    const size_t bytesX = (size_t)Traits<XS>::NCW * 16 * stride;
     const int kcl = fp64 ? DDWC_K_DSLASH64 : DDWC_K_DSLASH32;
     // algorithmic bytes of one half operator (hop kernel): half input with neighbours, half
     // output, the links of all sites, the site matrix of one parity
-    const double rs = 24.0 * sizeof(R);
-    const double hbytes = (double)n2 * (nrhs * 2 * rs + 8 * 18.0 * sizeof(R) + 72.0 * sizeof(R));
+    const double rs = h16 ? 52.0 : 24.0 * sizeof(R);
+    const double hbytes =
+        (double)n2 * (nrhs * 2 * rs + 8 * 18.0 * sizeof(typename Traits<S>::link) + 72.0 * sizeof(R));
     double2 *be, *bo, *bpe, *xe, *xo, *re, *to;
-    W *r, *rh, *p, *v, *s, *t, *xR, *tmp;
+    W *r, *rh, *p, *v, *s, *t, *tmp;
+    XW* xR;
     double *part, *sums, *scale, *thr;
     BiState* st;
     CK(ws_t(C, "eo_be", hw64, &be));
@@ -494,15 +521,18 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     CK(ws_t(C, "eo_xo", hw64, &xo));
     CK(ws_t(C, "eo_re", hw64, &re));
     CK(ws_t(C, "eo_to", hw64, &to));
-    const std::string pre = fp64 ? "eo64_" : "eo32_";
-    CK(ws_t(C, pre + "r", hwR, &r));
-    CK(ws_t(C, pre + "rh", hwR, &rh));
-    CK(ws_t(C, pre + "p", hwR, &p));
-    CK(ws_t(C, pre + "v", hwR, &v));
-    CK(ws_t(C, pre + "s", hwR, &s));
-    CK(ws_t(C, pre + "t", hwR, &t));
-    CK(ws_t(C, pre + "x", hwR, &xR));
-    CK(ws_t(C, pre + "tmp", hwR, &tmp));
+    const std::string pre = fp64 ? "eo64_" : h16 ? "eo16_" : "eo32_";
+    {
+        void* q;
+        W** vecs[7] = {&r, &rh, &p, &v, &s, &t, &tmp};
+        const char* nm[7] = {"r", "rh", "p", "v", "s", "t", "tmp"};
+        for (int k = 0; k < 7; ++k) {
+            CK(ws_get(C, pre + nm[k], bytesR, &q));
+            *vecs[k] = (W*)q;
+        }
+        CK(ws_get(C, pre + "x", bytesX, &q));
+        xR = (XW*)q;
+    }
     CK(ws_t(C, "g_part", (size_t)(ntf > ntR ? ntf : ntR) * nrhs * NPART, &part));
     CK(ws_t(C, "g_sums", (size_t)nrhs * NPART, &sums));
     CK(ws_t(C, "g_scale", (size_t)nrhs, &scale));
@@ -538,13 +568,14 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
     HC(hipStreamSynchronize(sm));
     for (int k = 0; k < nrhs; ++k) rr[k] = h_sums[k * NPART + 2];
-    const double floor_eps = fp64 ? 0.0 : 2e-6;
+    // the inner solve stops at this relative residual at the least (the storage's reach)
+    const double floor_eps = fp64 ? 0.0 : h16 ? 1e-3 : 2e-6;
     const int poll = 2;
     int total = 0, nout = 0;
     bool converged = false;
     auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
-        launch_eo_hopinv<R>(ex, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
-        launch_eo_diaghop<R>(ex, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
+        launch_eo_hopinv<S>(ex, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
+        launch_eo_diaghop<S>(ex, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
                              hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
     };
     while (true) {
@@ -566,18 +597,18 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         }
         HC(hipMemcpyAsync(scale, h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
         HC(hipMemcpyAsync(thr, h_thr, sizeof(double) * nrhs, hipMemcpyHostToDevice, sm));
-        launch_bicg_init<R>(ex, n2, ri, re, scale, r, rh, p, xR, part, nrhs);
+        launch_bicg_init<S>(ex, n2, ri, re, scale, r, rh, p, xR, part, nrhs);
         launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_INIT, thr);
         while (total < maxit) {
             for (int k = 0; k < poll && total < maxit; ++k, ++total) {
                 apply_M(p, v, 1, rh);
                 launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_ALPHA, nullptr);
-                launch_bicg_s<R>(ex, n2, ri, st, r, v, s, nrhs);
+                launch_bicg_s<S>(ex, n2, ri, st, r, v, s, nrhs);
                 apply_M(s, t, 2, nullptr);
                 launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_OMEGA, nullptr);
-                launch_bicg_xr<R>(ex, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
+                launch_bicg_xr<S>(ex, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
                 launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
-                launch_bicg_p<R>(ex, n2, ri, st, r, v, p, nrhs);
+                launch_bicg_p<S>(ex, n2, ri, st, r, v, p, nrhs);
             }
             HC(hipGetLastError());
             HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
@@ -586,7 +617,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
             for (int k = 0; k < nrhs; ++k) any = any || h_st[k].active;
             if (!any) break;
         }
-        launch_accumulate<R>(ex, n2, ri, xR, scale, xe, nrhs);
+        launch_accumulate<S>(ex, n2, ri, xR, scale, xe, nrhs);
         // r_e = b'_e - Mee x_e in FP64
         launch_eo_hopinv<double>(ex, F64, 1, false, xe, nullptr, 1.0, A64, to, nrhs, DDWC_K_DSLASH64, 0);
         launch_eo_diaghop<double>(ex, F64, 0, false, 3, true, xe, to, -0.25, mass4, bpe, re, part, nrhs, DDWC_K_DSLASH64, 0);
@@ -618,6 +649,7 @@ static int solve_internal(ddwc_ctx* C, Exec& ex, double mass, const double2* b64
                           double tol, int maxit, int prec, SolveInfo* info) {
     if (C->g.eo) {
         if (prec == DDWC_FP64) return eo_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
+        if (prec == DDWC_MIXED16) return eo_solve<H16>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
         return eo_solve<float>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
     }
     if (prec == DDWC_FP64) return global_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);

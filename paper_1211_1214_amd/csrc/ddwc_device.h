@@ -219,16 +219,46 @@ DDWC_HD int canonical_index(const Geom& g, const Site& S) {
 template <class R>
 struct Traits;
 
+// Storage of one precision: `word` the 16-byte spinor word, `real` the arithmetic type,
+// `link` the storage of a link entry, `kword` the clover word, `xs` the precision that
+// accumulates a solver's solution.
 template <>
 struct Traits<double> {
     typedef double2 word;
+    typedef double real;
+    typedef double link;
+    typedef double2 kword;
+    typedef double xs;
     static constexpr int NCW = 12;  // spinor words per site
     static constexpr int NKW = 36;  // clover words per site
 };
 template <>
 struct Traits<float> {
     typedef float4 word;
+    typedef float real;
+    typedef float link;
+    typedef float4 kword;
+    typedef float xs;
     static constexpr int NCW = 6;
+    static constexpr int NKW = 18;
+};
+
+// FP16 storage with FP32 arithmetic: a spinor is three words of eight halves (four complex)
+// scaled by one FP32 factor per site (its largest component modulus), kept in a plane of
+// floats after the word planes; links are plain halves (|U_ij| <= 1); the clover stays FP32.
+struct H16 {};
+typedef _Float16 f16;
+struct __attribute__((aligned(16))) hw16 {
+    f16 h[8];
+};
+template <>
+struct Traits<H16> {
+    typedef hw16 word;
+    typedef float real;
+    typedef f16 link;
+    typedef float4 kword;
+    typedef float xs;
+    static constexpr int NCW = 3;
     static constexpr int NKW = 18;
 };
 
@@ -268,10 +298,44 @@ DDWC_HD void store_spinor(float4* __restrict__ f, unsigned V, unsigned s, const 
         at(f + (size_t)k * V, s) = make_float4(p[2 * k].re, p[2 * k].im, p[2 * k + 1].re, p[2 * k + 1].im);
 }
 
-template <class R>
-DDWC_HD void load_link(const cx<R>* __restrict__ U, unsigned V, int mu, unsigned s, cx<R> u[9]) {
+template <class R, class L>
+DDWC_HD void load_link(const cx<L>* __restrict__ U, unsigned V, int mu, unsigned s, cx<R> u[9]) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = at(U + (size_t)(mu * 9 + k) * V, s);
+    for (int k = 0; k < 9; ++k) {
+        const cx<L> w = at(U + (size_t)(mu * 9 + k) * V, s);
+        u[k] = mk((R)w.re, (R)w.im);
+    }
+}
+
+// FP16 spinors: words k = 0..2 hold complex 4k .. 4k + 3; the scale plane follows the three
+// word planes of the field (f is the field base, `stride` its plane length).
+DDWC_HD float* scale_plane(hw16* f, unsigned stride) { return (float*)(f + 3 * (size_t)stride); }
+DDWC_HD const float* scale_plane(const hw16* f, unsigned stride) { return (const float*)(f + 3 * (size_t)stride); }
+DDWC_HD void load_spinor(const hw16* __restrict__ f, unsigned stride, unsigned s, cx<float> p[12]) {
+    const float sc = at(scale_plane(f, stride), s);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const hw16 w = at(f + (size_t)k * stride, s);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) p[4 * k + q] = mk(sc * (float)w.h[2 * q], sc * (float)w.h[2 * q + 1]);
+    }
+}
+DDWC_HD void store_spinor(hw16* __restrict__ f, unsigned stride, unsigned s, const cx<float> p[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(p[c].re), fabsf(p[c].im)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    at(scale_plane(f, stride), s) = m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        hw16 w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w.h[2 * q] = (f16)(inv * p[4 * k + q].re);
+            w.h[2 * q + 1] = (f16)(inv * p[4 * k + q].im);
+        }
+        at(f + (size_t)k * stride, s) = w;
+    }
 }
 
 // The 36 reals of chiral block `blk` of the clover term at site s:
@@ -453,10 +517,10 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 //
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).
-template <class R, int HOPS, bool PIPE>
-DDWC_HD void hop_sum(unsigned n, unsigned s, const typename Traits<R>::word* __restrict__ in,
-                     const cx<R>* __restrict__ Uf, const cx<R>* __restrict__ Ub, const int* __restrict__ nbr,
-                     cx<R> acc[12], int ndir, unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
+template <class R, int HOPS, bool PIPE, class W, class L>
+DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
+                     const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
+                     unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
     if (sstride == 0) sstride = n;
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));

@@ -103,29 +103,30 @@ template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
                 typename Traits<R>::word* out, int nrhs, int to_colour);
 
-// BiCGStab vector kernels on fields of n sites, nrhs RHS, per-RHS scalars in st.  ri selects
-// the RHS-innermost layout [NCW][n][nrhs] for the precision-R fields (else [nrhs][NCW][n]);
-// FP64 fields (r64, x64) are always RHS-major.  Partial sums use vector_tiles() tiles per RHS.
+// BiCGStab vector kernels on fields of n sites, nrhs RHS, per-RHS scalars in st, storage S
+// (double, float or H16; H16 fields must be RHS-innermost).  ri selects the RHS-innermost
+// layout [NCW][n][nrhs] (else [nrhs][NCW][n]); FP64 fields (r64, x64) are always RHS-major.
+// Partial sums use vector_tiles() tiles per RHS.
 int vector_tiles(unsigned n, int nrhs, bool ri);
-template <class R>
+template <class S>
 void launch_bicg_init(Exec& e, unsigned n, bool ri, const double2* r64, const double* scale,
-                      typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
-                      typename Traits<R>::word* x, double* part, int nrhs);
-template <class R>
-void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
-                   const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs);
-template <class R>
-void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<R>::word* x,
-                    const typename Traits<R>::word* p, const typename Traits<R>::word* s,
-                    const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
-                    typename Traits<R>::word* r, double* part, int nrhs);
-template <class R>
-void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
-                   const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs);
-// x64 += (1/scale) * x_R per RHS (RHS with scale 0 untouched).
-template <class R>
-void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<R>::word* x, const double* scale,
-                       double2* x64, int nrhs);
+                      typename Traits<S>::word* r, typename Traits<S>::word* rh, typename Traits<S>::word* p,
+                      typename Traits<typename Traits<S>::xs>::word* x, double* part, int nrhs);
+template <class S>
+void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
+                   const typename Traits<S>::word* v, typename Traits<S>::word* s, int nrhs);
+template <class S>
+void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
+                    const typename Traits<S>::word* p, const typename Traits<S>::word* s,
+                    const typename Traits<S>::word* t, const typename Traits<S>::word* rh,
+                    typename Traits<S>::word* r, double* part, int nrhs);
+template <class S>
+void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
+                   const typename Traits<S>::word* v, typename Traits<S>::word* p, int nrhs);
+// x64 += (1/scale) * x per RHS (RHS with scale 0 untouched); x in Traits<S>::xs.
+template <class S>
+void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typename Traits<S>::xs>::word* x,
+                       const double* scale, double2* x64, int nrhs);
 
 // Sums partials per RHS in a fixed order and applies the BiCGStab stage update.
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
@@ -165,12 +166,14 @@ void blas_handle_destroy(void* h);
 // Half-field data of one precision: links, clover and neighbour table of each parity.
 template <class R>
 struct EoFields {
-    unsigned n2;                            // V / 2
-    const cx<R>* U[2];                      // [4][9][n2] links of the sites of parity p
-    const typename Traits<R>::word* K[2];   // clover of the sites of parity p
-    const int* nbr[2];                      // [8][n2] neighbour half indices (other parity)
+    unsigned n2;                                        // V / 2
+    const cx<typename Traits<R>::link>* U[2];           // [4][9][n2] links of the sites of parity p
+    const typename Traits<R>::kword* K[2];              // clover of the sites of parity p
+    const int* nbr[2];                                  // [8][n2] neighbour half indices (other parity)
 };
 
+// FP16 copy of n FP32 complex link entries.
+void launch_links_to_half(Exec& e, size_t n, const cx<float>* src, cx<f16>* dst);
 void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
                      cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo);
 void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
@@ -178,17 +181,17 @@ void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, d
 void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);
 // y_p = Ainv (c + alpha H_{p,1-p} x); c may be null, alpha = 0 skips the hops.  ri: the fields
 // are RHS-innermost (as for the vector kernels).
-template <class R>
-void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, bool ri, const typename Traits<R>::word* x,
-                      const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
-                      typename Traits<R>::word* y, int nrhs, int kclass, double bytes);
+template <class S>
+void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typename Traits<S>::word* x,
+                      const typename Traits<S>::word* c, double alpha, const typename Traits<S>::kword* Ainv,
+                      typename Traits<S>::word* y, int nrhs, int kclass, double bytes);
 // y_p = [A_pp] c + beta H_{p,1-p} t with epilogue epi (0 none, 1 dot(aux, y), 2 dots (y, c), (y, y),
 // 3 residual y = aux - y with ||y||^2).
-template <class R>
-void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, bool ri, int epi, bool use_a, const typename Traits<R>::word* c,
-                       const typename Traits<R>::word* tv, double beta, double mass4,
-                       const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part, int nrhs,
-                       int kclass, double bytes);
+template <class S>
+void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, bool use_a,
+                       const typename Traits<S>::word* c, const typename Traits<S>::word* tv, double beta,
+                       double mass4, const typename Traits<S>::word* aux, typename Traits<S>::word* y, double* part,
+                       int nrhs, int kclass, double bytes);
 
 // ------------------------------------------------------------------ even-odd block solver (block_eo.hip)
 int block_eo_threads(const Geom& g);

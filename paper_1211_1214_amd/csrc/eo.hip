@@ -40,6 +40,19 @@ void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double
     k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Kh64, Kh32, nbr_eo);
 }
 
+// FP16 copy of the FP32 half-order links (setup).
+__global__ void k_links_to_half(size_t n, const cx<float>* __restrict__ src, cx<f16>* __restrict__ dst) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cx<float> v = src[i];
+    dst[i] = mk((f16)v.re, (f16)v.im);
+}
+
+void launch_links_to_half(Exec& e, size_t n, const cx<float>* src, cx<f16>* dst) {
+    Timed t(e, 4, 0);
+    k_links_to_half<<<(unsigned)((n + 255) / 256), 256, 0, e.stream>>>(n, src, dst);
+}
+
 // A_pp^-1 for the sites of parity p of half clover Kp (once per mass).
 __global__ void k_eo_inverse(unsigned V2, const double2* __restrict__ Kp, double mass4, double2* __restrict__ A64,
                              float4* __restrict__ A32) {
@@ -94,17 +107,20 @@ void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* h
 // RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
 // y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
-// alpha = 0 skips the hops.
-template <class R, bool RI>
-__global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<R>::word* __restrict__ x,
-                                                  const typename Traits<R>::word* __restrict__ c, R alpha,
-                                                  const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
+// alpha = 0 skips the hops.  S is the storage (double, float or H16), arithmetic in its real.
+template <class S, bool RI>
+__global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<S>::word* __restrict__ x,
+                                                  const typename Traits<S>::word* __restrict__ c,
+                                                  typename Traits<S>::real alpha,
+                                                  const cx<typename Traits<S>::link>* __restrict__ Up,
+                                                  const cx<typename Traits<S>::link>* __restrict__ Uq,
                                                   const int* __restrict__ nbrp,
-                                                  const typename Traits<R>::word* __restrict__ Ainv,
-                                                  typename Traits<R>::word* __restrict__ y, int nrhs, int ntiles) {
+                                                  const typename Traits<S>::kword* __restrict__ Ainv,
+                                                  typename Traits<S>::word* __restrict__ y, int nrhs, int ntiles) {
+    typedef typename Traits<S>::real R;
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
     if (!it.ok) return;
-    const VView<RI, R> w(n2, nrhs, it.i, it.r);
+    const VView<RI, S> w(n2, nrhs, it.i, it.r);
     cx<R> acc[12], out[12];
     if (alpha != R(0))
         hop_sum<R, HOPS_ALL, true>(n2, it.i, x + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
@@ -131,19 +147,23 @@ enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
 // y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
 // Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
 // RESID: y = aux - y and partial ||y||^2.
-template <class R, int EPI, bool USE_A, bool RI>
-__global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<R>::word* __restrict__ c,
-                                                   const typename Traits<R>::word* __restrict__ t, R beta,
-                                                   const cx<R>* __restrict__ Up, const cx<R>* __restrict__ Uq,
+template <class S, int EPI, bool USE_A, bool RI>
+__global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<S>::word* __restrict__ c,
+                                                   const typename Traits<S>::word* __restrict__ t,
+                                                   typename Traits<S>::real beta,
+                                                   const cx<typename Traits<S>::link>* __restrict__ Up,
+                                                   const cx<typename Traits<S>::link>* __restrict__ Uq,
                                                    const int* __restrict__ nbrp,
-                                                   const typename Traits<R>::word* __restrict__ Kp, R mass4,
-                                                   const typename Traits<R>::word* __restrict__ aux,
-                                                   typename Traits<R>::word* __restrict__ y, double* part, int nrhs,
+                                                   const typename Traits<S>::kword* __restrict__ Kp,
+                                                   typename Traits<S>::real mass4,
+                                                   const typename Traits<S>::word* __restrict__ aux,
+                                                   typename Traits<S>::word* __restrict__ y, double* part, int nrhs,
                                                    int ntiles) {
+    typedef typename Traits<S>::real R;
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
     double v[3] = {0, 0, 0};
     if (it.ok) {
-        const VView<RI, R> w(n2, nrhs, it.i, it.r);
+        const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
         hop_sum<R, HOPS_ALL, true>(n2, it.i, t + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
         load_spinor(c + w.base, w.stride, w.idx, cc);
@@ -176,30 +196,32 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
     if (EPI == EOE_RESID) vpartials<1, RI>(v, part, ntiles, it, nrhs);
 }
 
-template <class R>
-void launch_eo_hopinv(Exec& e, const EoFields<R>& F, int p, bool ri, const typename Traits<R>::word* x,
-                      const typename Traits<R>::word* c, double alpha, const typename Traits<R>::word* Ainv,
-                      typename Traits<R>::word* y, int nrhs, int kclass, double bytes) {
+template <class S>
+void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typename Traits<S>::word* x,
+                      const typename Traits<S>::word* c, double alpha, const typename Traits<S>::kword* Ainv,
+                      typename Traits<S>::word* y, int nrhs, int kclass, double bytes) {
+    typedef typename Traits<S>::real R;
     Timed t(e, kclass, bytes);
     const int nt = vector_tiles(F.n2, nrhs, ri);
     if (ri)
-        k_eo_hopinv<R, true><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y,
+        k_eo_hopinv<S, true><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y,
                                                       nrhs, nt);
     else
-        k_eo_hopinv<R, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
+        k_eo_hopinv<S, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
                                                               Ainv, y, nrhs, nt);
 }
 
-template <class R>
-void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, bool ri, int epi, bool use_a,
-                       const typename Traits<R>::word* c, const typename Traits<R>::word* tv, double beta,
-                       double mass4, const typename Traits<R>::word* aux, typename Traits<R>::word* y, double* part,
+template <class S>
+void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, bool use_a,
+                       const typename Traits<S>::word* c, const typename Traits<S>::word* tv, double beta,
+                       double mass4, const typename Traits<S>::word* aux, typename Traits<S>::word* y, double* part,
                        int nrhs, int kclass, double bytes) {
+    typedef typename Traits<S>::real R;
     Timed tm(e, kclass, bytes);
     const int nt = vector_tiles(F.n2, nrhs, ri);
     const int ng = ri ? nt : nt * nrhs;
 #define EOL(EP, UA, RIV)                                                                                            \
-    k_eo_diaghop<R, EP, UA, RIV><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p],       \
+    k_eo_diaghop<S, EP, UA, RIV><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p],       \
                                                           F.K[p], (R)mass4, aux, y, part, nrhs, nt)
 #define EOSW(RIV)                                            \
     if (use_a) {                                             \
@@ -221,14 +243,15 @@ void launch_eo_diaghop(Exec& e, const EoFields<R>& F, int p, bool ri, int epi, b
 #undef EOL
 }
 
-#define EO_INST(R)                                                                                                 \
-    template void launch_eo_hopinv<R>(Exec&, const EoFields<R>&, int, bool, const Traits<R>::word*,                \
-                                      const Traits<R>::word*, double, const Traits<R>::word*, Traits<R>::word*, int, \
-                                      int, double);                                                                \
-    template void launch_eo_diaghop<R>(Exec&, const EoFields<R>&, int, bool, int, bool, const Traits<R>::word*,    \
-                                       const Traits<R>::word*, double, double, const Traits<R>::word*,             \
-                                       Traits<R>::word*, double*, int, int, double);
+#define EO_INST(S)                                                                                                 \
+    template void launch_eo_hopinv<S>(Exec&, const EoFields<S>&, int, bool, const Traits<S>::word*,                \
+                                      const Traits<S>::word*, double, const Traits<S>::kword*, Traits<S>::word*,   \
+                                      int, int, double);                                                           \
+    template void launch_eo_diaghop<S>(Exec&, const EoFields<S>&, int, bool, int, bool, const Traits<S>::word*,    \
+                                       const Traits<S>::word*, double, double, const Traits<S>::word*,             \
+                                       Traits<S>::word*, double*, int, int, double);
 EO_INST(double)
 EO_INST(float)
+EO_INST(H16)
 
 }  // namespace ddwc

@@ -6,6 +6,8 @@
 // that each of the 8 XCDs sweeps one contiguous range: the RHS of a tile share its
 // links and clover in that XCD's L2, and face neighbours of consecutive Schwarz
 // blocks stay in the same L2.
+#include <type_traits>
+
 #include "ddwc_internal.h"
 #include "clover_build.h"
 #include "vec_items.h"
@@ -230,41 +232,55 @@ __device__ __forceinline__ cx<R> cxs(const double* a) {
     return mk((R)a[0], (R)a[1]);
 }
 
-template <class R, bool RI>
+// Storage S (double, float or H16) with arithmetic in Traits<S>::real; the solution
+// correction x is kept in Traits<S>::xs.
+#define VTYPES(S)                                       \
+    typedef typename Traits<S>::real R;                 \
+    typedef typename Traits<S>::xs XS;                  \
+    (void)sizeof(R);                                    \
+    (void)sizeof(XS)
+
+template <class S, bool RI>
 __global__ __launch_bounds__(WG) void k_bicg_init(unsigned n, const double2* __restrict__ r64,
-                                                  const double* __restrict__ scale, typename Traits<R>::word* r,
-                                                  typename Traits<R>::word* rh, typename Traits<R>::word* p,
-                                                  typename Traits<R>::word* x, double* part, int nrhs, int ntiles) {
+                                                  const double* __restrict__ scale, typename Traits<S>::word* r,
+                                                  typename Traits<S>::word* rh, typename Traits<S>::word* p,
+                                                  typename Traits<typename Traits<S>::xs>::word* x, double* part,
+                                                  int nrhs, int ntiles) {
+    VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
     double v[1] = {0};
     if (it.ok) {
-        const VView<RI, R> w(n, nrhs, it.i, it.r);
+        const VView<RI, S> w(n, nrhs, it.i, it.r);
+        const VView<RI, XS> wx(n, nrhs, it.i, it.r);
         cx<double> a[12];
         load_spinor(r64 + (size_t)it.r * 12 * n, n, it.i, a);
         const double sc = scale[it.r];
-        cx<R> q[12], z[12];
+        cx<R> q[12];
+        cx<XS> z[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             q[k] = mk((R)(sc * a[k].re), (R)(sc * a[k].im));
-            z[k] = mk(R(0), R(0));
+            z[k] = mk(XS(0), XS(0));
         }
         store_spinor(r + w.base, w.stride, w.idx, q);
         store_spinor(rh + w.base, w.stride, w.idx, q);
         store_spinor(p + w.base, w.stride, w.idx, q);
-        store_spinor(x + w.base, w.stride, w.idx, z);
+        store_spinor(x + wx.base, wx.stride, wx.idx, z);
+        if (std::is_same<S, H16>::value) load_spinor(r + w.base, w.stride, w.idx, q);  // r as stored
         v[0] = acc_nrm(q);
     }
     vpartials<1, RI>(v, part, ntiles, it, nrhs);
 }
 
-template <class R, bool RI>
+template <class S, bool RI>
 __global__ __launch_bounds__(WG) void k_bicg_s(unsigned n, const BiState* __restrict__ st,
-                                               const typename Traits<R>::word* __restrict__ r,
-                                               const typename Traits<R>::word* __restrict__ v,
-                                               typename Traits<R>::word* __restrict__ s_out, int nrhs, int ntiles) {
+                                               const typename Traits<S>::word* __restrict__ r,
+                                               const typename Traits<S>::word* __restrict__ v,
+                                               typename Traits<S>::word* __restrict__ s_out, int nrhs, int ntiles) {
+    VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
     if (!it.ok) return;
-    const VView<RI, R> w(n, nrhs, it.i, it.r);
+    const VView<RI, S> w(n, nrhs, it.i, it.r);
     const cx<R> al = cxs<R>(st[it.r].alpha);
     cx<R> a[12], b[12];
     load_spinor(r + w.base, w.stride, w.idx, a);
@@ -274,32 +290,37 @@ __global__ __launch_bounds__(WG) void k_bicg_s(unsigned n, const BiState* __rest
     store_spinor(s_out + w.base, w.stride, w.idx, a);
 }
 
-template <class R, bool RI>
+template <class S, bool RI>
 __global__ __launch_bounds__(WG) void k_bicg_xr(unsigned n, const BiState* __restrict__ st,
-                                                typename Traits<R>::word* __restrict__ x,
-                                                const typename Traits<R>::word* __restrict__ p,
-                                                const typename Traits<R>::word* __restrict__ sv,
-                                                const typename Traits<R>::word* __restrict__ t,
-                                                const typename Traits<R>::word* __restrict__ rh,
-                                                typename Traits<R>::word* __restrict__ r, double* part, int nrhs,
+                                                typename Traits<typename Traits<S>::xs>::word* __restrict__ x,
+                                                const typename Traits<S>::word* __restrict__ p,
+                                                const typename Traits<S>::word* __restrict__ sv,
+                                                const typename Traits<S>::word* __restrict__ t,
+                                                const typename Traits<S>::word* __restrict__ rh,
+                                                typename Traits<S>::word* __restrict__ r, double* part, int nrhs,
                                                 int ntiles) {
+    VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
     double v[3] = {0, 0, 0};
     if (it.ok) {
-        const VView<RI, R> w(n, nrhs, it.i, it.r);
+        const VView<RI, S> w(n, nrhs, it.i, it.r);
+        const VView<RI, XS> wx(n, nrhs, it.i, it.r);
         const cx<R> al = cxs<R>(st[it.r].alpha), om = cxs<R>(st[it.r].omega);
-        cx<R> xx[12], pp[12], ss[12], tt[12];
-        load_spinor(x + w.base, w.stride, w.idx, xx);
+        cx<XS> xx[12];
+        cx<R> pp[12], ss[12], tt[12];
+        load_spinor(x + wx.base, wx.stride, wx.idx, xx);
         load_spinor(p + w.base, w.stride, w.idx, pp);
         load_spinor(sv + w.base, w.stride, w.idx, ss);
         load_spinor(t + w.base, w.stride, w.idx, tt);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            xx[k] = xx[k] + al * pp[k] + om * ss[k];
+            const cx<R> d = al * pp[k] + om * ss[k];
+            xx[k] = xx[k] + mk((XS)d.re, (XS)d.im);
             ss[k] = ss[k] - om * tt[k];
         }
-        store_spinor(x + w.base, w.stride, w.idx, xx);
+        store_spinor(x + wx.base, wx.stride, wx.idx, xx);
         store_spinor(r + w.base, w.stride, w.idx, ss);
+        if (std::is_same<S, H16>::value) load_spinor(r + w.base, w.stride, w.idx, ss);  // r as stored
         load_spinor(rh + w.base, w.stride, w.idx, pp);
         acc_dot(pp, ss, v[0], v[1]);
         v[2] = acc_nrm(ss);
@@ -307,14 +328,15 @@ __global__ __launch_bounds__(WG) void k_bicg_xr(unsigned n, const BiState* __res
     vpartials<3, RI>(v, part, ntiles, it, nrhs);
 }
 
-template <class R, bool RI>
+template <class S, bool RI>
 __global__ __launch_bounds__(WG) void k_bicg_p(unsigned n, const BiState* __restrict__ st,
-                                               const typename Traits<R>::word* __restrict__ r,
-                                               const typename Traits<R>::word* __restrict__ v,
-                                               typename Traits<R>::word* __restrict__ p, int nrhs, int ntiles) {
+                                               const typename Traits<S>::word* __restrict__ r,
+                                               const typename Traits<S>::word* __restrict__ v,
+                                               typename Traits<S>::word* __restrict__ p, int nrhs, int ntiles) {
+    VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
     if (!it.ok) return;
-    const VView<RI, R> w(n, nrhs, it.i, it.r);
+    const VView<RI, S> w(n, nrhs, it.i, it.r);
     const cx<R> be = cxs<R>(st[it.r].beta), om = cxs<R>(st[it.r].omega);
     cx<R> rr[12], pp[12], vv[12];
     load_spinor(r + w.base, w.stride, w.idx, rr);
@@ -325,70 +347,73 @@ __global__ __launch_bounds__(WG) void k_bicg_p(unsigned n, const BiState* __rest
     store_spinor(p + w.base, w.stride, w.idx, pp);
 }
 
-template <class R, bool RI>
-__global__ __launch_bounds__(WG) void k_accumulate(unsigned n, const typename Traits<R>::word* __restrict__ x,
+template <class S, bool RI>
+__global__ __launch_bounds__(WG) void k_accumulate(unsigned n,
+                                                   const typename Traits<typename Traits<S>::xs>::word* __restrict__ x,
                                                    const double* __restrict__ scale, double2* __restrict__ x64,
                                                    int nrhs, int ntiles) {
+    VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
     if (!it.ok) return;
     const double sc = scale[it.r];
     if (sc == 0.0) return;
     const double inv = 1.0 / sc;
-    const VView<RI, R> w(n, nrhs, it.i, it.r);
-    cx<R> a[12];
+    const VView<RI, XS> wx(n, nrhs, it.i, it.r);
+    cx<XS> a[12];
     cx<double> b[12];
-    load_spinor(x + w.base, w.stride, w.idx, a);
+    load_spinor(x + wx.base, wx.stride, wx.idx, a);
     double2* dst = x64 + (size_t)it.r * 12 * n;
     load_spinor(dst, n, it.i, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) b[k] = b[k] + mk(inv * (double)a[k].re, inv * (double)a[k].im);
     store_spinor(dst, n, it.i, b);
 }
+#undef VTYPES
 
 int vector_tiles(unsigned n, int nrhs, bool ri) { return ri ? tiles_of((int)(n * (unsigned)nrhs)) : tiles_of((int)n); }
 static int vector_grid(unsigned n, int nrhs, bool ri) { return ri ? vector_tiles(n, nrhs, ri) : tiles_of((int)n) * nrhs; }
 
-#define VDISPATCH(KERNEL, R, ...)                                                                          \
+#define VDISPATCH(KERNEL, S, ...)                                                                          \
     do {                                                                                                   \
         const int nt = vector_tiles(n, nrhs, ri), ng = vector_grid(n, nrhs, ri);                           \
         if (ri)                                                                                            \
-            KERNEL<R, true><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                             \
+            KERNEL<S, true><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                             \
         else                                                                                               \
-            KERNEL<R, false><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                            \
+            KERNEL<S, false><<<ng, WG, 0, e.stream>>>(n, __VA_ARGS__, nrhs, nt);                            \
     } while (0)
 
-template <class R>
+template <class S>
 void launch_bicg_init(Exec& e, unsigned n, bool ri, const double2* r64, const double* scale,
-                      typename Traits<R>::word* r, typename Traits<R>::word* rh, typename Traits<R>::word* p,
-                      typename Traits<R>::word* x, double* part, int nrhs) {
+                      typename Traits<S>::word* r, typename Traits<S>::word* rh, typename Traits<S>::word* p,
+                      typename Traits<typename Traits<S>::xs>::word* x, double* part, int nrhs) {
     Timed t(e, 3, 0);
-    VDISPATCH(k_bicg_init, R, r64, scale, r, rh, p, x, part);
+    VDISPATCH(k_bicg_init, S, r64, scale, r, rh, p, x, part);
 }
-template <class R>
-void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
-                   const typename Traits<R>::word* v, typename Traits<R>::word* s, int nrhs) {
+template <class S>
+void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
+                   const typename Traits<S>::word* v, typename Traits<S>::word* s, int nrhs) {
     Timed t(e, 3, 0);
-    VDISPATCH(k_bicg_s, R, st, r, v, s);
+    VDISPATCH(k_bicg_s, S, st, r, v, s);
 }
-template <class R>
-void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<R>::word* x,
-                    const typename Traits<R>::word* p, const typename Traits<R>::word* s,
-                    const typename Traits<R>::word* t, const typename Traits<R>::word* rh,
-                    typename Traits<R>::word* r, double* part, int nrhs) {
+template <class S>
+void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
+                    const typename Traits<S>::word* p, const typename Traits<S>::word* s,
+                    const typename Traits<S>::word* t, const typename Traits<S>::word* rh,
+                    typename Traits<S>::word* r, double* part, int nrhs) {
     Timed tm(e, 3, 0);
-    VDISPATCH(k_bicg_xr, R, st, x, p, s, t, rh, r, part);
+    VDISPATCH(k_bicg_xr, S, st, x, p, s, t, rh, r, part);
 }
-template <class R>
-void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<R>::word* r,
-                   const typename Traits<R>::word* v, typename Traits<R>::word* p, int nrhs) {
+template <class S>
+void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
+                   const typename Traits<S>::word* v, typename Traits<S>::word* p, int nrhs) {
     Timed t(e, 3, 0);
-    VDISPATCH(k_bicg_p, R, st, r, v, p);
+    VDISPATCH(k_bicg_p, S, st, r, v, p);
 }
-template <class R>
-void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<R>::word* x, const double* scale,
-                       double2* x64, int nrhs) {
+template <class S>
+void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typename Traits<S>::xs>::word* x,
+                       const double* scale, double2* x64, int nrhs) {
     Timed t(e, 3, 0);
-    VDISPATCH(k_accumulate, R, x, scale, x64);
+    VDISPATCH(k_accumulate, S, x, scale, x64);
 }
 #undef VDISPATCH
 
@@ -554,5 +579,13 @@ void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, dou
 
 INST(double)
 INST(float)
+
+template void launch_bicg_init<H16>(Exec&, unsigned, bool, const double2*, const double*, hw16*, hw16*, hw16*, float4*,
+                                    double*, int);
+template void launch_bicg_s<H16>(Exec&, unsigned, bool, const BiState*, const hw16*, const hw16*, hw16*, int);
+template void launch_bicg_xr<H16>(Exec&, unsigned, bool, const BiState*, float4*, const hw16*, const hw16*,
+                                  const hw16*, const hw16*, hw16*, double*, int);
+template void launch_bicg_p<H16>(Exec&, unsigned, bool, const BiState*, const hw16*, const hw16*, hw16*, int);
+template void launch_accumulate<H16>(Exec&, unsigned, bool, const float4*, const double*, double2*, int);
 
 }  // namespace ddwc

@@ -188,3 +188,21 @@ extern "C" int host_force(const int* lat, const int* blk, int tbc, double csw, c
             }
     return 0;
 }
+
+// FP16 spinor storage: store then load one spinor (24 reals) through the library's code.
+extern "C" int host_h16_roundtrip(const double* in, double* out, float* scale_out) {
+    struct alignas(16) Buf {
+        hw16 w[3];
+        float scale[4];
+    } buf;
+    cx<float> p[12], q[12];
+    for (int c = 0; c < 12; ++c) p[c] = mk((float)in[2 * c], (float)in[2 * c + 1]);
+    store_spinor(buf.w, 1, 0, p);
+    load_spinor((const hw16*)buf.w, 1, 0, q);
+    for (int c = 0; c < 12; ++c) {
+        out[2 * c] = q[c].re;
+        out[2 * c + 1] = q[c].im;
+    }
+    *scale_out = buf.scale[0];
+    return 0;
+}

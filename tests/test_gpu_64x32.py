@@ -4,6 +4,7 @@ block), N = 4 mass-interpolation steps and 24 RHS in one multi-RHS batch, mixed 
 The oracle cannot redo the batch in seconds, so the checks are
   * sampled exponents x_ij against the oracle values stored by tests/golden/make_golden_64x32.py,
   * the FP64 single-RHS path on noise vector 0 (all four steps) against the mixed batch,
+  * the FP16-storage inner solver (DDWC_MIXED16) against the oracle values and the FP32 batch,
   * the final residuals of the solver statistics.
 """
 import json
@@ -50,6 +51,13 @@ def test_64x32_estimate():
         i, j = map(int, key.split(","))
         say(f"64x32: x[{i},{j}] = {x[i, j]!r}, oracle {xo!r}")
         assert abs(x[i, j] - xo) <= 1e-8 * max(abs(xo), 1.0)
+    say("64x32: FP16 inner solves, 4 steps x 24 RHS")
+    r16 = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad, op=dd.OP_SCHUR, tol=1e-10, prec=dd.MIXED16)
+    assert r16["stats"]["rel_residual"] <= 1e-10
+    for key, xo in gold["x_schur"].items():
+        i, j = map(int, key.split(","))
+        assert abs(r16["x"][i, j] - xo) <= 1e-8 * max(abs(xo), 1.0)
+    assert np.all(np.abs(r16["x"] - x) <= 1e-8 * np.maximum(np.abs(x), 1.0))
     say("64x32: FP64 single-RHS path on noise vector 0")
     r64 = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad[:, :1].contiguous(), op=dd.OP_SCHUR, tol=1e-10,
                                  prec=dd.FP64)

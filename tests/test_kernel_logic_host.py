@@ -34,6 +34,7 @@ def L():
     lib.host_apply.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_double, ctypes.c_int,
                                ctypes.c_int, P, P]
     lib.host_force.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, P, P]
+    lib.host_h16_roundtrip.argtypes = [P, P, P]
     return lib
 
 
@@ -132,3 +133,22 @@ def test_host_force_matches_finite_differences(L, csw):
     fd = (4 * d(5e-5) - d(1e-4)) / 3
     got = float(np.sum(np.conj(G) * dU).real)
     assert abs(got - fd) < 1e-8 * abs(fd), (got, fd)
+
+
+def test_host_fp16_spinor_storage(L):
+    """FP16 storage with a per-site scale: the scale is the largest component modulus and every
+    component comes back within half a unit in the last place of FP16 relative to it (2^-11)."""
+    rng = np.random.default_rng(5)
+    for mag in (1e-30, 1e-3, 1.0, 7e4, 3e30):
+        v = np.ascontiguousarray(rng.standard_normal(24) * mag)
+        out = np.zeros(24)
+        sc = np.zeros(1, dtype=np.float32)
+        L.host_h16_roundtrip(v.ctypes.data, out.ctypes.data, sc.ctypes.data)
+        m = np.abs(v.astype(np.float32)).max()
+        assert abs(sc[0] - m) <= 1e-7 * m
+        assert np.abs(out - v).max() <= (2.0 ** -11 + 2e-7) * m
+    z = np.zeros(24)
+    out = np.ones(24)
+    sc = np.ones(1, dtype=np.float32)
+    L.host_h16_roundtrip(z.ctypes.data, out.ctypes.data, sc.ctypes.data)
+    assert sc[0] == 0 and np.all(out == 0)

@@ -55,11 +55,11 @@ typedef enum {
     DDWC_EUNDEF = -5      /* estimate undefined: non-finite step mean or variance */
 } ddwc_status;
 
-/* DDWC_MIXED16: as DDWC_MIXED32, except that the even-odd global solver's inner BiCGStab keeps
- * its vectors in FP16 with one FP32 scale per site and RHS, and its links in FP16 (clover,
- * arithmetic and the solution correction in FP32; FP64 defect correction restores the
- * tolerance).  Operators, block solves and lattices with an odd block extent run as
- * DDWC_MIXED32.  At most 256 RHS per call in the FP16 solver. */
+/* DDWC_MIXED16: as DDWC_MIXED32, except that the inner BiCGStab of the even-odd global solver
+ * and of the even-odd Schwarz block solver keeps its vectors in FP16 with one FP32 scale per
+ * site and RHS, and its links in FP16 (clover, arithmetic and the solution correction in
+ * FP32; FP64 defect correction restores the tolerance).  ddwc_dslash_apply and lattices with
+ * an odd block extent run as DDWC_MIXED32.  At most 256 RHS per call in the global solver. */
 typedef enum { DDWC_FP64 = 0, DDWC_MIXED32 = 1, DDWC_MIXED16 = 2 } ddwc_precision;
 typedef enum { DDWC_BLACK = 0, DDWC_WHITE = 1 } ddwc_colour;
 typedef enum { DDWC_OP_FULL = 0, DDWC_OP_SCHUR = 1 } ddwc_operator;

@@ -676,7 +676,10 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     CK(get_ainv(C, ex, mass4, &A64, &A32));
     const EoFields<double> F64 = eo_fields<double>(C);
     const unsigned n2 = F64.n2;
-    const size_t hw64 = (size_t)nrhs * 12 * n2, hwR = (size_t)nrhs * (fp64 ? 12 : 6) * n2;
+    const bool h16 = prec == DDWC_MIXED16;
+    const size_t hw64 = (size_t)nrhs * 12 * n2;
+    // the correction vector (slot 5) is kept in FP32 when the others are FP16
+    const size_t slabS = blk_slab_bytes(prec, n2), slabX = blk_slab_bytes(h16 ? DDWC_MIXED32 : prec, n2);
     double2 *bpe, *re, *xe, *to;
     CK(ws_t(C, "be_bpe", hw64, &bpe));
     CK(ws_t(C, "be_re", hw64, &re));
@@ -684,7 +687,9 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     CK(ws_t(C, "be_to", hw64, &to));
     void* w[7];
     const char* names[7] = {"be_r", "be_rh", "be_p", "be_v", "be_t", "be_e", "be_tmp"};
-    for (int k = 0; k < 7; ++k) CK(ws_get(C, std::string(names[k]) + (fp64 ? "64" : "32"), hwR * 16, &w[k]));
+    for (int k = 0; k < 7; ++k)
+        CK(ws_get(C, std::string(names[k]) + (fp64 ? "64" : h16 ? "16" : "32"), (k == 5 ? slabX : slabS) * nrhs,
+                  &w[k]));
     const size_t nb = (size_t)nrhs * g.NBc;
     double *bb, *rr;
     int* iters;
@@ -727,6 +732,9 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
         if (fp64) {
             const EoFields<double> F = F64;
             launch_blk_inner<double>(ex, g, F, A64, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
+        } else if (h16) {
+            const EoFields<H16> F = eo_fields<H16>(C);
+            launch_blk_inner<H16>(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
         } else {
             const EoFields<float> F = eo_fields<float>(C);
             launch_blk_inner<float>(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
@@ -748,7 +756,8 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
         // algorithmic bytes of the persistent inner kernel per even site and iteration: 25
         // half-spinor passes and two applications of M_k, each reading both parities' links
         // twice (16 links per even-odd pair), the even clover and the odd inverse.
-        const double S = 24.0 * (fp64 ? 8 : 4), Gk = (16 * 18.0 + 144.0) * (fp64 ? 8 : 4);
+        const double S = h16 ? 52.0 : 24.0 * (fp64 ? 8 : 4);
+        const double Gk = 16 * 18.0 * (fp64 ? 8 : h16 ? 2 : 4) + 144.0 * (fp64 ? 8 : 4);
         C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * (25 * S + 2 * Gk);
     }
     if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");

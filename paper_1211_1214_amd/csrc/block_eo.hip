@@ -10,8 +10,11 @@
 //                 correction to x_e in FP64 (blocks already converged return at once)
 //   k_blk_resid   FP64: r_e = b'_e - M_k x_e and ||r_e||^2 (defect correction)
 //   k_blk_recon   FP64: x_o, and (x_e, x_o) written to the full solution
+#include <type_traits>
+
 #include "ddwc_internal.h"
 #include "eo.h"
+#include "../../include/ddwc.h"
 
 namespace ddwc {
 
@@ -44,10 +47,19 @@ __device__ __forceinline__ BlkIdx blk_idx(const Geom& g, int colour, int nrhs) {
 }
 
 // Ainv (c + alpha H^k x) at odd half site j (x even), into y (odd).
-template <class R>
-__device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename Traits<R>::word* x,
-                                         const typename Traits<R>::word* c, R alpha, const EoFields<R>& F,
-                                         const typename Traits<R>::word* Ainv, cx<R> w[12]) {
+// Storage S (double, float or H16; arithmetic in Traits<S>::real).  A vector of one RHS is a
+// slab of slab_words<S>(n2) words: the word planes and, for H16, the plane of site scales.
+template <class S>
+__host__ __device__ __forceinline__ size_t slab_words(unsigned n2) {
+    return (size_t)Traits<S>::NCW * n2 + (std::is_same<S, H16>::value ? n2 / 4 : 0);
+}
+
+template <class S>
+__device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename Traits<S>::word* x,
+                                         const typename Traits<S>::word* c, typename Traits<S>::real alpha,
+                                         const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
+                                         cx<typename Traits<S>::real> w[12]) {
+    typedef typename Traits<S>::real R;
     cx<R> acc[12];
     hop_sum<R, HOPS_INSIDE, false>(n2, j, x, F.U[1], F.U[0], F.nbr[1], acc, 8);
     if (c) {
@@ -65,10 +77,12 @@ __device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename
 }
 
 // [A_ee] c + beta H^k t at even half site i (t odd).
-template <class R, bool USE_A>
-__device__ __forceinline__ void even_pass(unsigned n2, unsigned i, const typename Traits<R>::word* c,
-                                          const typename Traits<R>::word* t, R beta, const EoFields<R>& F, R mass4,
-                                          cx<R> y[12]) {
+template <class S, bool USE_A>
+__device__ __forceinline__ void even_pass(unsigned n2, unsigned i, const typename Traits<S>::word* c,
+                                          const typename Traits<S>::word* t, typename Traits<S>::real beta,
+                                          const EoFields<S>& F, typename Traits<S>::real mass4,
+                                          cx<typename Traits<S>::real> y[12]) {
+    typedef typename Traits<S>::real R;
     cx<R> cc[12];
     hop_sum<R, HOPS_INSIDE, false>(n2, i, t, F.U[0], F.U[1], F.nbr[0], y, 8);
     load_spinor(c, n2, i, cc);
@@ -187,10 +201,12 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, EoFields<d
     }
 }
 
-template <class R>
+template <class S>
 struct BlkInner {
-    typedef typename Traits<R>::word W;
-    W *r, *rh, *p, *v, *t, *e, *tmp;
+    typedef typename Traits<S>::word W;
+    typedef typename Traits<typename Traits<S>::xs>::word XW;
+    W *r, *rh, *p, *v, *t, *tmp;
+    XW* e;  // the correction, in Traits<S>::xs
 };
 
 template <class R>
@@ -201,16 +217,18 @@ __device__ __forceinline__ cx<R> cdiv_r(cx<double> a, cx<double> b) {
 
 // v = M_k p on the block (two passes separated by a workgroup barrier), with the dot
 // products requested: (rh, v) when DOT1, (v, p) and (v, v) when DOT2.
-template <class R, int DOT>
-__device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
-                                         unsigned h0, size_t oR, const typename Traits<R>::word* in,
-                                         typename Traits<R>::word* tmp, typename Traits<R>::word* out,
-                                         const typename Traits<R>::word* rh, R mass4, double red[3]) {
+template <class S, int DOT>
+__device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
+                                         unsigned h0, size_t oR, const typename Traits<S>::word* in,
+                                         typename Traits<S>::word* tmp, typename Traits<S>::word* out,
+                                         const typename Traits<S>::word* rh, typename Traits<S>::real mass4,
+                                         double red[3]) {
+    typedef typename Traits<S>::real R;
     const unsigned n2 = F.n2;
 #pragma unroll 1
     for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
         cx<R> w[12];
-        odd_pass<R>(n2, h0 + l, in + oR, nullptr, R(1), F, Ainv, w);
+        odd_pass<S>(n2, h0 + l, in + oR, nullptr, R(1), F, Ainv, w);
         store_spinor(tmp + oR, n2, h0 + l, w);
     }
     __syncthreads();
@@ -218,7 +236,7 @@ __device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<R>& F, co
     for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
         const unsigned i = h0 + l;
         cx<R> y[12];
-        even_pass<R, true>(n2, i, in + oR, tmp + oR, R(-0.25), F, mass4, y);
+        even_pass<S, true>(n2, i, in + oR, tmp + oR, R(-0.25), F, mass4, y);
         store_spinor(out + oR, n2, i, y);
         if (DOT == 1) {
             cx<R> h[12];
@@ -233,11 +251,11 @@ __device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<R>& F, co
     }
 }
 
-template <class R>
-__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R> F,
-                                                             const typename Traits<R>::word* __restrict__ Ainv,
+template <class S>
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<S> F,
+                                                             const typename Traits<S>::kword* __restrict__ Ainv,
                                                              const double2* __restrict__ re, double2* __restrict__ xe,
-                                                             BlkInner<R> w, const double* __restrict__ bb,
+                                                             BlkInner<S> w, const double* __restrict__ bb,
                                                              const double* __restrict__ rr, double mass4, double tol,
                                                              double inner_floor, int maxit, int* iters, int colour,
                                                              int nrhs) {
@@ -246,7 +264,10 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
     const double b2 = bb[k.key], r2 = rr[k.key];
     if (!(b2 > 0) || !(r2 > tol * tol * b2) || !isfinite(r2)) return;  // uniform over the workgroup
     const unsigned n2 = F.n2;
-    const size_t oh = (size_t)k.rhs * 12 * n2, oR = (size_t)k.rhs * Traits<R>::NCW * n2;
+    typedef typename Traits<S>::real R;
+    typedef typename Traits<S>::xs XS;
+    const size_t oh = (size_t)k.rhs * 12 * n2, oR = (size_t)k.rhs * slab_words<S>(n2),
+                 oX = (size_t)k.rhs * Traits<XS>::NCW * n2;
     const R m4 = (R)mass4;
     const double rn = sqrt(r2), sc = 1.0 / rn;
     double eps = 0.5 * tol * sqrt(b2) / rn;
@@ -256,17 +277,18 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
     for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
         const unsigned i = k.h0 + l;
         cx<double> a[12];
-        cx<R> q[12], z[12];
+        cx<R> q[12];
+        cx<XS> z[12];
         load_spinor(re + oh, n2, i, a);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             q[c] = mk((R)(sc * a[c].re), (R)(sc * a[c].im));
-            z[c] = mk(R(0), R(0));
+            z[c] = mk(XS(0), XS(0));
         }
         store_spinor(w.r + oR, n2, i, q);
         store_spinor(w.rh + oR, n2, i, q);
         store_spinor(w.p + oR, n2, i, q);
-        store_spinor(w.e + oR, n2, i, z);
+        store_spinor(w.e + oX, n2, i, z);
         red[0] += acc_nrm(q);
     }
     block_sum<1>(red, lds);
@@ -275,7 +297,7 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
     int it = 0;
     while (it < maxit) {
         red[0] = red[1] = red[2] = 0;
-        apply_Mk<R, 1>(g, F, Ainv, k.h0, oR, w.p, w.tmp, w.v, w.rh, m4, red);
+        apply_Mk<S, 1>(g, F, Ainv, k.h0, oR, w.p, w.tmp, w.v, w.rh, m4, red);
         block_sum<2>(red, lds);
         if (!(red[0] * red[0] + red[1] * red[1] > 0)) break;
         const cx<R> alpha = cdiv_r<R>(rho, mk(red[0], red[1]));
@@ -292,7 +314,7 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
         }
         __syncthreads();
         red[0] = red[1] = red[2] = 0;
-        apply_Mk<R, 2>(g, F, Ainv, k.h0, oR, w.r, w.tmp, w.t, nullptr, m4, red);
+        apply_Mk<S, 2>(g, F, Ainv, k.h0, oR, w.r, w.tmp, w.t, nullptr, m4, red);
         block_sum<3>(red, lds);
         cx<R> omega = mk(R(0), R(0));
         if (red[2] > 0) omega = mk((R)(red[0] / red[2]), (R)(red[1] / red[2]));
@@ -301,17 +323,19 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
 #pragma unroll 1
         for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
             const unsigned i = k.h0 + l;
-            cx<R> ee[12], pp[12], ss[12], tt[12];
-            load_spinor(w.e + oR, n2, i, ee);
+            cx<XS> ee[12];
+            cx<R> pp[12], ss[12], tt[12];
+            load_spinor(w.e + oX, n2, i, ee);
             load_spinor(w.p + oR, n2, i, pp);
             load_spinor(w.r + oR, n2, i, ss);
             load_spinor(w.t + oR, n2, i, tt);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                ee[c] = ee[c] + alpha * pp[c] + omega * ss[c];
+                const cx<R> d = alpha * pp[c] + omega * ss[c];
+                ee[c] = ee[c] + mk((XS)d.re, (XS)d.im);
                 ss[c] = ss[c] - omega * tt[c];
             }
-            store_spinor(w.e + oR, n2, i, ee);
+            store_spinor(w.e + oX, n2, i, ee);
             store_spinor(w.r + oR, n2, i, ss);
             load_spinor(w.rh + oR, n2, i, pp);
             acc_dot(pp, ss, red[0], red[1]);
@@ -346,9 +370,9 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<R
 #pragma unroll 1
     for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
         const unsigned i = k.h0 + l;
-        cx<R> e[12];
+        cx<XS> e[12];
         cx<double> x[12];
-        load_spinor(w.e + oR, n2, i, e);
+        load_spinor(w.e + oX, n2, i, e);
         load_spinor(xe + oh, n2, i, x);
 #pragma unroll
         for (int c = 0; c < 12; ++c) x[c] = x[c] + mk(rn * (double)e[c].re, rn * (double)e[c].im);
@@ -373,22 +397,29 @@ void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const d
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
     k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
 }
-template <class R>
-void launch_blk_inner(Exec& e, const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
+template <class S>
+void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
                       const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,
                       double mass4, double tol, int maxit, int* iters, int colour, int nrhs) {
     Timed t(e, 2, 0);
-    BlkInner<R> bw;
-    typedef typename Traits<R>::word W;
+    BlkInner<S> bw;
+    typedef typename Traits<S>::word W;
     bw.r = (W*)w[0];
     bw.rh = (W*)w[1];
     bw.p = (W*)w[2];
     bw.v = (W*)w[3];
     bw.t = (W*)w[4];
-    bw.e = (W*)w[5];
+    bw.e = (typename BlkInner<S>::XW*)w[5];
     bw.tmp = (W*)w[6];
-    k_blk_inner<R><<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(
-        g, F, Ainv, re, xe, bw, bb, rr, mass4, tol, sizeof(R) == 8 ? 0.0 : 2e-6, maxit, iters, colour, nrhs);
+    // the inner solve stops at this relative residual at the least (the storage's reach)
+    const double floor_eps = std::is_same<S, double>::value ? 0.0 : std::is_same<S, H16>::value ? 1e-3 : 2e-6;
+    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
+                                                                       floor_eps, maxit, iters, colour, nrhs);
+}
+size_t blk_slab_bytes(int prec, unsigned n2) {
+    if (prec == DDWC_FP64) return slab_words<double>(n2) * 16;
+    if (prec == DDWC_MIXED16) return slab_words<H16>(n2) * 16;
+    return slab_words<float>(n2) * 16;
 }
 template void launch_blk_inner<double>(Exec&, const Geom&, const EoFields<double>&, const double2*, const double2*,
                                        double2*, void* const[7], const double*, const double*, double, double, int,
@@ -396,5 +427,8 @@ template void launch_blk_inner<double>(Exec&, const Geom&, const EoFields<double
 template void launch_blk_inner<float>(Exec&, const Geom&, const EoFields<float>&, const float4*, const double2*,
                                       double2*, void* const[7], const double*, const double*, double, double, int,
                                       int*, int, int);
+template void launch_blk_inner<H16>(Exec&, const Geom&, const EoFields<H16>&, const float4*, const double2*,
+                                    double2*, void* const[7], const double*, const double*, double, double, int,
+                                    int*, int, int);
 
 }  // namespace ddwc

@@ -201,10 +201,12 @@ void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const d
                       const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs);
 void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                       const double2* xe, double2* x, int colour, int nrhs);
-template <class R>
-void launch_blk_inner(Exec& e, const Geom& g, const EoFields<R>& F, const typename Traits<R>::word* Ainv,
+template <class S>
+void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
                       const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,
                       double mass4, double tol, int maxit, int* iters, int colour, int nrhs);
+// bytes of one RHS of a block-solver vector in the storage of precision `prec` (n2 = V/2)
+size_t blk_slab_bytes(int prec, unsigned n2);
 
 // ------------------------------------------------------------------ block solver (block_solver.hip)
 struct BlockSolveArgs {

@@ -94,7 +94,7 @@ def test_dslash_periodic_and_wilson(dev):
         ctx.close()
 
 
-@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32])
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
 @pytest.mark.parametrize("colour", [0, 1])
 @pytest.mark.parametrize("name", list(GEOMS))
 def test_block_solve(dev, name, colour, prec):
@@ -116,7 +116,7 @@ def lt_colour_mask(lat, blk, c):
     return lt.colour(lat, blk) == c
 
 
-@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32])
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
 @pytest.mark.parametrize("name", list(GEOMS))
 def test_schur_apply_and_inverse(dev, name, prec):
     lat, blk, U, ctx, S = setup(name, dev)

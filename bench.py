@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule options")
     ap.add_argument("--dslash-reps", type=int, default=20, help="launches per standalone Dslash measurement")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (calibrates HBM counters) and exit")
@@ -91,6 +92,8 @@ def main():
 
     inner = args.inner or ("fp32" if cid == 3 else "fp16")
     prec = dd.MIXED16 if inner == "fp16" else dd.MIXED32
+    tuned = ctx.autotune(k2, nhit, prec) if not args.no_autotune else None
+    log(f"autotune: {tuned}")
 
     def step():
         return ctx.det_ratio_estimate(k1, k2, etad, op=dd.OP_SCHUR, tol=args.tol, prec=prec)
@@ -174,6 +177,7 @@ def main():
                    "lattice": list(lat), "blocks": list(blk), "n_interp": nint, "n_hit": nhit, "tol": args.tol,
                    "inner": inner},
         "roofline": roofline,
+        "schedule": tuned,
         "cpu_baseline": cpu,
         "dslash": dslash,
         "dslash32_in_solver_gbs": None if dslash_gbs is None else round(dslash_gbs, 1),

@@ -178,6 +178,29 @@ int ddwc_link_force(ddwc_ctx *ctx, const void *a, const void *b, int nrhs, const
 int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_host, int *sign_host, void *stream);
 
 /*
+ * Schedule options of a context.
+ *   DDWC_OPT_GRAPHS        1: the global solver replays each chunk of BiCGStab iterations from
+ *                          a captured HIP graph (cached per buffer set and mass; not while
+ *                          profiling); 0: launches them one by one.  Default 1.
+ *   DDWC_OPT_POLL          iterations between the host's convergence checks, [1, 64]; default 2.
+ *   DDWC_OPT_BLOCK_THREADS workgroup size of the Schwarz block kernels: 0 (enough waves for one
+ *                          block parity, at most 256) or a multiple of 64 in [64, 256].
+ * Results do not depend on the graph option; the other two can change iteration counts and
+ * rounding, never the tolerance reached.  EINVAL for unknown options or values.
+ */
+typedef enum { DDWC_OPT_GRAPHS = 0, DDWC_OPT_POLL = 1, DDWC_OPT_BLOCK_THREADS = 2 } ddwc_option;
+int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
+int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
+
+/*
+ * Autotuner: times the schedule options on this lattice with nrhs reproducible right-hand
+ * sides at the given kappa and precision (a block sweep of one colour for each workgroup
+ * size; a global solve for each poll interval with and without graphs, tolerance 1e-8) and
+ * sets the fastest.  *seconds_host (may be null) receives the tuning time.  Synchronises.
+ */
+int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *seconds_host, void *stream);
+
+/*
  * Kernel timing for measurement.  When enabled, launches of the library's kernels
  * are bracketed with HIP events on their stream; ddwc_profile_read synchronises and
  * returns, for kernel class `kclass` (DDWC_K_*), the number of launches and their

@@ -19,6 +19,7 @@ FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER = range(5)
+OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS = range(3)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.
@@ -46,6 +47,9 @@ SIGNATURES = {
     "ddwc_det_ratio_grad": (_I, [_P, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _P, _PS, _P]),
     "ddwc_link_force": (_I, [_P, _P, _P, _I, _PD, _P, _P]),
     "ddwc_block_logdet": (_I, [_P, _D, _I, _PD, _PI, _P]),
+    "ddwc_set_option": (_I, [_P, _I, _I]),
+    "ddwc_get_option": (_I, [_P, _I, _PI]),
+    "ddwc_autotune": (_I, [_P, _D, _I, _I, _PD, _P]),
     "ddwc_profile_enable": (_I, [_P, _I]),
     "ddwc_profile_read": (_I, [_P, _I, _PLL, _PD, _PD]),
     "ddwc_dslash_bytes": (_D, [_P, _I, _I]),
@@ -248,6 +252,22 @@ class Context:
         for c in (BLACK, WHITE):
             tot += self.block_logdet(kappa2, c)[0].sum() - self.block_logdet(kappa1, c)[0].sum()
         return 2 * tot
+
+    def set_option(self, option, value):
+        _check(lib().ddwc_set_option(self._h, int(option), int(value)), "ddwc_set_option")
+
+    def get_option(self, option):
+        v = ctypes.c_int()
+        _check(lib().ddwc_get_option(self._h, int(option), ctypes.byref(v)), "ddwc_get_option")
+        return v.value
+
+    def autotune(self, kappa, nrhs, prec=MIXED32):
+        """Times the schedule options and keeps the fastest; returns the options and the tuning time."""
+        t = ctypes.c_double()
+        _check(lib().ddwc_autotune(self._h, float(kappa), int(nrhs), int(prec), ctypes.byref(t), _stream()),
+               "ddwc_autotune")
+        return {"graphs": self.get_option(OPT_GRAPHS), "poll": self.get_option(OPT_POLL),
+                "block_threads": self.get_option(OPT_BLOCK_THREADS), "seconds": t.value}
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

@@ -121,6 +121,18 @@ struct ddwc_ctx {
     std::map<std::string, Buf> ws;
     double* host = nullptr;  // pinned scratch for small device-to-host copies
     void* blas = nullptr;    // dense linear-algebra handle (block determinants), created on first use
+    // schedule options (ddwc_set_option, ddwc_autotune)
+    int opt_graphs = 1;       // replay the global solver's iteration chunks from captured graphs
+    int opt_poll = 2;         // BiCGStab iterations between host convergence checks
+    int opt_blk_threads = 0;  // block-solver workgroup size (0: default rule)
+    hipStream_t cap = nullptr;  // private stream the graphs are captured on
+    struct Graph {
+        std::vector<uintptr_t> key;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        long long used = 0;
+    };
+    std::vector<Graph> graphs;
     size_t host_n = 0;
 };
 
@@ -157,6 +169,12 @@ static int host_buf(ddwc_ctx* C, size_t n, double** out) {
 }
 
 static double mass_of(double kappa) { return 1.0 / (2.0 * kappa) - 4.0; }
+
+static Exec make_exec(ddwc_ctx* C, void* stream) {
+    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    ex.blk_threads = C->opt_blk_threads;
+    return ex;
+}
 
 static int check_ctx(const ddwc_ctx* C) {
     if (!C) return fail(DDWC_EINVAL, "null context");
@@ -218,7 +236,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
         ddwc_destroy(C);
         return fail(DDWC_EHIP, "device allocation of links/clover failed");
     }
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     launch_nbr_build(ex, g, C->nbr);
     launch_links_import(ex, g, links_dev, C->U64, C->U32);
     launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
@@ -248,6 +266,13 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
 
 extern "C" int ddwc_destroy(ddwc_ctx* C) {
     if (C && C->blas) blas_handle_destroy(C->blas);
+    if (C) {
+        for (auto& gr : C->graphs) {
+            if (gr.x) (void)hipGraphExecDestroy(gr.x);
+            if (gr.g) (void)hipGraphDestroy(gr.g);
+        }
+        if (C->cap) (void)hipStreamDestroy(C->cap);
+    }
     if (!C) return DDWC_OK;
     (void)hipDeviceSynchronize();
     C->prof.harvest();
@@ -472,6 +497,52 @@ static int get_ainv(ddwc_ctx* C, Exec& ex, double mass4, const double2** a64, co
 // Mee = A_ee - 1/4 H_eo A_oo^-1 H_oe inside FP64 defect correction, then
 // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e).  The FP64 residual of the even system equals the
 // residual of the full system, so the stopping rule is ||b'_e - Mee x_e|| <= tol ||b||.
+// The instantiated graph of the launches `body` issues, cached under `key` (at most 8 kept);
+// captured on the context's private stream.  nullptr if capture is not possible.
+template <class F>
+static hipGraphExec_t graph_for(ddwc_ctx* C, const std::vector<uintptr_t>& key, F&& body) {
+    static long long clock = 0;
+    for (auto& gr : C->graphs)
+        if (gr.key == key) {
+            gr.used = ++clock;
+            return gr.x;
+        }
+    if (!C->cap && hipStreamCreateWithFlags(&C->cap, hipStreamNonBlocking) != hipSuccess) {
+        C->cap = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    Exec ec = make_exec(C, C->cap);
+    ec.prof = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    if (hipStreamBeginCapture(C->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    body(ec);
+    if (hipStreamEndCapture(C->cap, &g) != hipSuccess || !g ||
+        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return nullptr;
+    }
+    if (C->graphs.size() >= 8) {
+        auto old = std::min_element(C->graphs.begin(), C->graphs.end(),
+                                    [](const ddwc_ctx::Graph& a, const ddwc_ctx::Graph& b) { return a.used < b.used; });
+        (void)hipGraphExecDestroy(old->x);
+        (void)hipGraphDestroy(old->g);
+        C->graphs.erase(old);
+    }
+    ddwc_ctx::Graph gr;
+    gr.key = key;
+    gr.g = g;
+    gr.x = x;
+    gr.used = ++clock;
+    C->graphs.push_back(gr);
+    return x;
+}
+
 template <class S>
 static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
                     int maxit, SolveInfo* info) {
@@ -570,14 +641,41 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     for (int k = 0; k < nrhs; ++k) rr[k] = h_sums[k * NPART + 2];
     // the inner solve stops at this relative residual at the least (the storage's reach)
     const double floor_eps = fp64 ? 0.0 : h16 ? 1e-3 : 2e-6;
-    const int poll = 2;
+    const int poll = C->opt_poll;
     int total = 0, nout = 0;
     bool converged = false;
-    auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
-        launch_eo_hopinv<S>(ex, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
-        launch_eo_diaghop<S>(ex, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
-                             hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
+    // `iters` BiCGStab iterations on stream ee (the caller's, or the capture stream)
+    auto chunk = [&](Exec& ee, int iters) {
+        auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
+            launch_eo_hopinv<S>(ee, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
+            launch_eo_diaghop<S>(ee, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
+                                 hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
+        };
+        for (int k = 0; k < iters; ++k) {
+            apply_M(p, v, 1, rh);
+            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_ALPHA, nullptr);
+            launch_bicg_s<S>(ee, n2, ri, st, r, v, s, nrhs);
+            apply_M(s, t, 2, nullptr);
+            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_OMEGA, nullptr);
+            launch_bicg_xr<S>(ee, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
+            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
+            launch_bicg_p<S>(ee, n2, ri, st, r, v, p, nrhs);
+        }
     };
+    // a chunk of `poll` iterations replayed from a graph (every argument of its launches is in
+    // the key, so one graph serves every chunk of every solve with the same buffers and mass)
+    hipGraphExec_t gx = nullptr;
+    if (C->opt_graphs && !C->prof.on) {
+        double m4 = mass4;
+        uint64_t mb;
+        memcpy(&mb, &m4, 8);
+        std::vector<uintptr_t> key = {(uintptr_t)(fp64 ? 1 : h16 ? 3 : 2), (uintptr_t)nrhs, (uintptr_t)ri,
+                                      (uintptr_t)n2, (uintptr_t)poll, (uintptr_t)mb, (uintptr_t)r, (uintptr_t)rh,
+                                      (uintptr_t)p, (uintptr_t)v, (uintptr_t)s, (uintptr_t)t, (uintptr_t)tmp,
+                                      (uintptr_t)xR, (uintptr_t)part, (uintptr_t)st, (uintptr_t)AR,
+                                      (uintptr_t)FR.U[0], (uintptr_t)FR.K[0]};
+        gx = graph_for(C, key, [&](Exec& ee) { chunk(ee, poll); });
+    }
     while (true) {
         bool all = true;
         for (int k = 0; k < nrhs; ++k)
@@ -600,16 +698,12 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         launch_bicg_init<S>(ex, n2, ri, re, scale, r, rh, p, xR, part, nrhs);
         launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_INIT, thr);
         while (total < maxit) {
-            for (int k = 0; k < poll && total < maxit; ++k, ++total) {
-                apply_M(p, v, 1, rh);
-                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_ALPHA, nullptr);
-                launch_bicg_s<S>(ex, n2, ri, st, r, v, s, nrhs);
-                apply_M(s, t, 2, nullptr);
-                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_OMEGA, nullptr);
-                launch_bicg_xr<S>(ex, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
-                launch_finalize(ex, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
-                launch_bicg_p<S>(ex, n2, ri, st, r, v, p, nrhs);
-            }
+            const int it = std::min(poll, maxit - total);
+            if (gx && it == poll)
+                HC(hipGraphLaunch(gx, sm));
+            else
+                chunk(ex, it);
+            total += it;
             HC(hipGetLastError());
             HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
             HC(hipStreamSynchronize(sm));
@@ -851,7 +945,7 @@ extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void
                                  void* stream) {
     CK(check_common(C, kappa, nrhs, prec));
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     const Geom& g = C->g;
     const double mass4 = 4.0 + mass_of(kappa);
     if (prec == DDWC_FP64) {
@@ -882,7 +976,7 @@ extern "C" int ddwc_block_solve(ddwc_ctx* C, int colour, double kappa, const voi
     if (!rhs || !sol) return fail(DDWC_EINVAL, "null vector");
     if (colour != DDWC_BLACK && colour != DDWC_WHITE) return fail(DDWC_EINVAL, "colour must be 0 or 1");
     if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     double2 *b, *x;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &b));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &x));
@@ -903,7 +997,7 @@ extern "C" int ddwc_solve(ddwc_ctx* C, double kappa, const void* b, void* x, int
     CK(check_common(C, kappa, nrhs, prec));
     if (!b || !x) return fail(DDWC_EINVAL, "null vector");
     if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     double2 *bi, *xi;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &bi));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &xi));
@@ -953,7 +1047,7 @@ extern "C" int ddwc_schur_apply(ddwc_ctx* C, double kappa, int inverse, const vo
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
     if (inverse != 0 && inverse != 1) return fail(DDWC_EINVAL, "inverse must be 0 or 1");
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     double2 *e, *o;
     CK(ws_t(C, "api_a", vec_words(C, nrhs, true), &e));
     CK(ws_t(C, "api_b", vec_words(C, nrhs, true), &o));
@@ -989,7 +1083,7 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
     if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
     if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     const Geom& g = C->g;
     const int nrhs = n_hit;
     const size_t nw = vec_words(C, nrhs, true);
@@ -1126,7 +1220,7 @@ extern "C" int ddwc_det_ratio_grad(ddwc_ctx* C, double kappa1, double kappa2, in
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
     for (size_t k = 0; k < (size_t)n_interp * n_hit; ++k)
         if (!isfinite(gx[k])) return fail(DDWC_EINVAL, "non-finite upstream gradient");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     const Geom& g = C->g;
     const int nrhs = n_hit;
     const size_t nw = vec_words(C, nrhs, true);
@@ -1256,7 +1350,7 @@ extern "C" int ddwc_link_force(ddwc_ctx* C, const void* a, const void* b, int nr
     if (!a || !b || !w_host || !dU) return fail(DDWC_EINVAL, "null argument");
     for (int r = 0; r < nrhs; ++r)
         if (!isfinite(w_host[r])) return fail(DDWC_EINVAL, "non-finite weight");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     const Geom& g = C->g;
     double2 *ai, *bi;
     double* wd;
@@ -1290,7 +1384,7 @@ extern "C" int ddwc_block_logdet(ddwc_ctx* C, double kappa, int colour, double* 
     const int NB = g.NBc;
     const int batch = (int)std::min<size_t>((size_t)NB, std::max<size_t>(1, budget / mbytes));
     if (!C->blas && !(C->blas = blas_handle_create())) return fail(DDWC_EHIP, "dense linear-algebra handle");
-    Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
+    Exec ex = make_exec(C, stream);
     const double mass4 = 4.0 + mass_of(kappa);
     cx<double>* Mat;
     int *ipiv, *info;
@@ -1328,6 +1422,109 @@ extern "C" int ddwc_block_logdet(ddwc_ctx* C, double kappa, int colour, double* 
         if (sign_host) sign_host[b] = c >= 0 ? 1 : -1;
     }
     if (undefined) return fail(DDWC_EUNDEF, "block determinant singular, not finite or not real");
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
+    CK(check_ctx(C));
+    switch (option) {
+        case DDWC_OPT_GRAPHS:
+            if (value != 0 && value != 1) return fail(DDWC_EINVAL, "graphs option must be 0 or 1");
+            C->opt_graphs = value;
+            break;
+        case DDWC_OPT_POLL:
+            if (value < 1 || value > 64) return fail(DDWC_EINVAL, "poll interval must be in [1, 64]");
+            C->opt_poll = value;
+            break;
+        case DDWC_OPT_BLOCK_THREADS:
+            if (value != 0 && (value < 64 || value > 256 || value % 64 != 0))
+                return fail(DDWC_EINVAL, "block threads must be 0 or a multiple of 64 in [64, 256]");
+            C->opt_blk_threads = value;
+            break;
+        default:
+            return fail(DDWC_EINVAL, "unknown option");
+    }
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
+    CK(check_ctx(C));
+    if (!value) return fail(DDWC_EINVAL, "null argument");
+    switch (option) {
+        case DDWC_OPT_GRAPHS: *value = C->opt_graphs; break;
+        case DDWC_OPT_POLL: *value = C->opt_poll; break;
+        case DDWC_OPT_BLOCK_THREADS: *value = C->opt_blk_threads; break;
+        default: return fail(DDWC_EINVAL, "unknown option");
+    }
+    return DDWC_OK;
+}
+
+// Times the schedule choices on this context's lattice with nrhs reproducible right-hand
+// sides and keeps the fastest: the block-solver workgroup size (one colour's block sweep),
+// then the poll interval and graph replay of the global solve.  Each candidate runs once to
+// warm up and once timed.
+extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, double* seconds_host, void* stream) {
+    CK(check_common(C, kappa, nrhs, prec));
+    auto t0 = std::chrono::steady_clock::now();
+    const double mass = mass_of(kappa);
+    double2 *b, *x;
+    CK(ws_t(C, "tune_b", vec_words(C, nrhs, true), &b));
+    CK(ws_t(C, "tune_x", vec_words(C, nrhs, true), &x));
+    {
+        Exec ex = make_exec(C, stream);
+        launch_fill_hash(ex, b, vec_words(C, nrhs, true), 0x1211ULL);
+    }
+    auto timed = [&](auto&& run) -> double {
+        double best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            HC(hipStreamSynchronize((hipStream_t)stream));
+            auto a = std::chrono::steady_clock::now();
+            const int st = run();
+            if (st != DDWC_OK) return -1.0;
+            HC(hipStreamSynchronize((hipStream_t)stream));
+            if (rep == 1) best = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+        }
+        return best;
+    };
+    const int saved_threads = C->opt_blk_threads;
+    double best = 1e300;
+    int pick = saved_threads;
+    for (int T : {0, 128, 192, 256}) {
+        C->opt_blk_threads = T;
+        const double t = timed([&]() {
+            Exec ex = make_exec(C, stream);
+            BlockInfo bi;
+            return block_internal(C, ex, 0, mass, b, x, nrhs, 1e-8, 5000, prec, &bi);
+        });
+        if (t < 0) {
+            C->opt_blk_threads = saved_threads;
+            return fail(DDWC_ENOCONV, "autotune: block solve failed");
+        }
+        if (t < best) best = t, pick = T;
+    }
+    C->opt_blk_threads = pick;
+    const int saved_poll = C->opt_poll, saved_graphs = C->opt_graphs;
+    best = 1e300;
+    int pp = saved_poll, pg = saved_graphs;
+    for (int poll : {2, 4, 8})
+        for (int graphs : {0, 1}) {
+            C->opt_poll = poll;
+            C->opt_graphs = graphs;
+            const double t = timed([&]() {
+                Exec ex = make_exec(C, stream);
+                SolveInfo si;
+                return solve_internal(C, ex, mass, b, x, nrhs, 1e-8, 5000, prec, &si);
+            });
+            if (t < 0) {
+                C->opt_poll = saved_poll;
+                C->opt_graphs = saved_graphs;
+                return fail(DDWC_ENOCONV, "autotune: global solve failed");
+            }
+            if (t < best) best = t, pp = poll, pg = graphs;
+        }
+    C->opt_poll = pp;
+    C->opt_graphs = pg;
+    if (seconds_host) *seconds_host = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return DDWC_OK;
 }
 

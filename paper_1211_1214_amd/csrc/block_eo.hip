@@ -20,7 +20,10 @@ namespace ddwc {
 
 constexpr int BE_MAX_THREADS = 256;
 
-int block_eo_threads(const Geom& g) {
+// Workgroup size of the block kernels: `req` (a multiple of 64 up to BE_MAX_THREADS, set by the
+// autotuner) or, by default, enough waves for one block parity up to BE_MAX_THREADS.
+int block_eo_threads(const Geom& g, int req) {
+    if (req > 0) return req > BE_MAX_THREADS ? BE_MAX_THREADS : ((req + 63) / 64) * 64;
     int t = ((g.hvb + 63) / 64) * 64;
     return t < BE_MAX_THREADS ? t : BE_MAX_THREADS;
 }
@@ -384,18 +387,18 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<S
 void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                      double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs) {
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
-    k_blk_prep<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, bpe, re, xe, to, bb, rr, colour, nrhs);
+    k_blk_prep<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, b, bpe, re, xe, to, bb, rr, colour, nrhs);
 }
 void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,
                       const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs) {
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
-    k_blk_resid<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, bpe, xe, re, to, rr, mass4, colour,
+    k_blk_resid<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, bpe, xe, re, to, rr, mass4, colour,
                                                                     nrhs);
 }
 void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                       const double2* xe, double2* x, int colour, int nrhs) {
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
-    k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
+    k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
 }
 template <class S>
 void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
@@ -413,7 +416,7 @@ void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typena
     bw.tmp = (W*)w[6];
     // the inner solve stops at this relative residual at the least (the storage's reach)
     const double floor_eps = std::is_same<S, double>::value ? 0.0 : std::is_same<S, H16>::value ? 1e-3 : 2e-6;
-    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g), 0, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
+    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
                                                                        floor_eps, maxit, iters, colour, nrhs);
 }
 size_t blk_slab_bytes(int prec, unsigned n2) {

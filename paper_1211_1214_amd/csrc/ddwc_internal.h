@@ -46,7 +46,8 @@ struct Profiler {
 struct Exec {
     hipStream_t stream;
     Profiler* prof;
-    const int* nbr;  // neighbour table [8][V] of the context
+    const int* nbr;        // neighbour table [8][V] of the context
+    int blk_threads = 0;   // workgroup size of the block-solver kernels (0: the default rule)
 };
 
 // RAII-free scoped timing helper used by the launchers.
@@ -131,6 +132,9 @@ void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typen
 // Sums partials per RHS in a fixed order and applies the BiCGStab stage update.
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
                      const double* thr_rel2);
+
+// n double2 words of reproducible values in [-1/2, 1/2) (autotuner inputs).
+void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed);
 
 // FP64 helpers on internal vectors.
 // z = a*x + b*y on sites selected by mask (others of z set to zero); x or y may be null (= 0).

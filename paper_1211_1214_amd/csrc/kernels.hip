@@ -417,6 +417,26 @@ void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typen
 }
 #undef VDISPATCH
 
+// ------------------------------------------------------------------ reproducible test data
+// v[i] = (u(2i), u(2i + 1)) - 1/2 with u a 64-bit integer hash mapped to [0, 1) (the
+// SplitMix64 finaliser); used by the autotuner for its right-hand sides.
+__device__ __forceinline__ double hash_unit(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+__global__ void k_fill_hash(double2* __restrict__ v, size_t n, uint64_t seed) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v[i] = make_double2(hash_unit(seed + 2 * i) - 0.5, hash_unit(seed + 2 * i + 1) - 0.5);
+}
+void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed) {
+    Timed t(e, 4, 0);
+    k_fill_hash<<<(unsigned)((n + 255) / 256), 256, 0, e.stream>>>(v, n, seed);
+}
+
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
                                                   double* __restrict__ sums, BiState* __restrict__ st, int stage,

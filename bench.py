@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule options")
+    ap.add_argument("--solver", choices=("bicgstab", "sap-gcr"), default="bicgstab",
+                    help="global solver: even-odd BiCGStab or GCR preconditioned by Schwarz sweeps")
     ap.add_argument("--dslash-reps", type=int, default=20, help="launches per standalone Dslash measurement")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (calibrates HBM counters) and exit")
@@ -92,6 +94,8 @@ def main():
 
     inner = args.inner or ("fp32" if cid == 3 else "fp16")
     prec = dd.MIXED16 if inner == "fp16" else dd.MIXED32
+    if args.solver == "sap-gcr":
+        ctx.set_option(dd.binding.OPT_SOLVER, 1)
     tuned = ctx.autotune(k2, nhit, prec) if not args.no_autotune else None
     log(f"autotune: {tuned}")
 
@@ -175,7 +179,7 @@ def main():
         "config": {"workload": WORKLOADS[cid] + ("" if inner == "fp32" else
                                                  "; global inner solver in FP16 storage (per-site scales, FP16 links)"),
                    "lattice": list(lat), "blocks": list(blk), "n_interp": nint, "n_hit": nhit, "tol": args.tol,
-                   "inner": inner},
+                   "inner": inner, "solver": args.solver},
         "roofline": roofline,
         "schedule": tuned,
         "cpu_baseline": cpu,

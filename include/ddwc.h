@@ -185,10 +185,15 @@ int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_ho
  *   DDWC_OPT_POLL          iterations between the host's convergence checks, [1, 64]; default 2.
  *   DDWC_OPT_BLOCK_THREADS workgroup size of the Schwarz block kernels: 0 (enough waves for one
  *                          block parity, at most 256) or a multiple of 64 in [64, 256].
- * Results do not depend on the graph option; the other two can change iteration counts and
+ *   DDWC_OPT_SOLVER        global solver: 0 even-odd BiCGStab (default; lexicographic BiCGStab when
+ *                          a block extent is odd), 1 GCR (8 directions per cycle, restarted with
+ *                          the exact FP64 residual) preconditioned by the Schwarz alternating
+ *                          procedure: 3 multiplicative cycles over the black then the white
+ *                          blocks, each block solve by the persistent block solver to 1e-1.
+ * Results do not depend on the graph option; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
-typedef enum { DDWC_OPT_GRAPHS = 0, DDWC_OPT_POLL = 1, DDWC_OPT_BLOCK_THREADS = 2 } ddwc_option;
+typedef enum { DDWC_OPT_GRAPHS = 0, DDWC_OPT_POLL = 1, DDWC_OPT_BLOCK_THREADS = 2, DDWC_OPT_SOLVER = 3 } ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
 

@@ -19,7 +19,7 @@ FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER = range(5)
-OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS = range(3)
+OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER = range(4)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.

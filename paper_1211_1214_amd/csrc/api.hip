@@ -125,6 +125,7 @@ struct ddwc_ctx {
     int opt_graphs = 1;       // replay the global solver's iteration chunks from captured graphs
     int opt_poll = 2;         // BiCGStab iterations between host convergence checks
     int opt_blk_threads = 0;  // block-solver workgroup size (0: default rule)
+    int opt_solver = 0;       // global solver: 0 even-odd BiCGStab, 1 SAP-preconditioned GCR
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
     struct Graph {
         std::vector<uintptr_t> key;
@@ -739,8 +740,12 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     return DDWC_OK;
 }
 
+static int sap_gcr(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
+                   int maxit, int prec, SolveInfo* info);
+
 static int solve_internal(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs,
                           double tol, int maxit, int prec, SolveInfo* info) {
+    if (C->opt_solver == 1) return sap_gcr(C, ex, mass, b64, x64, nrhs, tol, maxit, prec, info);
     if (C->g.eo) {
         if (prec == DDWC_FP64) return eo_solve<double>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
         if (prec == DDWC_MIXED16) return eo_solve<H16>(C, ex, mass, b64, x64, nrhs, tol, maxit, info);
@@ -1010,6 +1015,169 @@ extern "C" int ddwc_solve(ddwc_ctx* C, double kappa, const void* b, void* x, int
     }
     fill_stats(stats, si.outer, si.inner, si.relres, t0);
     return st;
+}
+
+// ------------------------------------------------------------------ SAP-preconditioned GCR
+// The global solve preconditioned by the Schwarz blocks themselves (the Schwarz alternating
+// procedure the paper's DD references use): M_sap eta runs NCY multiplicative cycles, each
+// an approximate solve on all black blocks, a residual update, an approximate solve on all
+// white blocks and a residual update, the block solves by the persistent block solver to a
+// loose relative tolerance.  Flexible GCR with NKV directions per cycle, modified
+// Gram-Schmidt, all in FP64 with per-RHS coefficients; the residual is recomputed exactly
+// at every restart.
+static int cdots(ddwc_ctx* C, Exec& ex, const double2* x, const double2* y, int nrhs, std::vector<cx<double>>& xy,
+                 std::vector<double>& yy) {
+    const int nt = tiles_of(C->g.V);
+    double *part, *sums;
+    CK(ws_t(C, "sg_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(C, "sg_sums", (size_t)nrhs * NPART, &sums));
+    launch_dots(ex, C->g, x, y, part, nrhs);
+    launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+    std::vector<double> h((size_t)nrhs * NPART);
+    HC(hipMemcpyAsync(h.data(), sums, sizeof(double) * h.size(), hipMemcpyDeviceToHost, ex.stream));
+    HC(hipStreamSynchronize(ex.stream));
+    xy.resize(nrhs);
+    yy.resize(nrhs);
+    for (int j = 0; j < nrhs; ++j) {
+        xy[j] = mk(h[(size_t)j * NPART], h[(size_t)j * NPART + 1]);
+        yy[j] = h[(size_t)j * NPART + 2];
+    }
+    return DDWC_OK;
+}
+
+static int sap_gcr(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, double2* x64, int nrhs, double tol,
+                   int maxit, int prec, SolveInfo* info) {
+    const int NKV = 8, NCY = 3;
+    const double btol = 0.1;  // relative residual of the approximate block solves
+    const Geom& g = C->g;
+    const size_t nw = vec_words(C, nrhs, true);
+    const double mass4 = 4.0 + mass;
+    const double dbytes = ddwc_dslash_bytes(C, nrhs, DDWC_FP64);
+    double2 *r, *rho, *dl, *cd;
+    double* part;
+    CK(ws_t(C, "sg_r", nw, &r));
+    CK(ws_t(C, "sg_rho", nw, &rho));
+    CK(ws_t(C, "sg_dl", nw, &dl));
+    CK(ws_t(C, "sg_c", (size_t)nrhs, &cd));
+    CK(ws_t(C, "sg_rpart", (size_t)tiles_of(g.V) * nrhs * NPART, &part));
+    std::vector<double2*> Z(NKV), W(NKV);
+    for (int k = 0; k < NKV; ++k) {
+        CK(ws_t(C, "sg_z" + std::to_string(k), nw, &Z[k]));
+        CK(ws_t(C, "sg_w" + std::to_string(k), nw, &W[k]));
+    }
+    std::vector<double2> hc(nrhs);
+    auto caxpy = [&](const std::vector<cx<double>>& c, const double2* xv, double2* yv) -> int {
+        for (int j = 0; j < nrhs; ++j) hc[j] = make_double2(c[j].re, c[j].im);
+        HC(hipMemcpyAsync(cd, hc.data(), sizeof(double2) * nrhs, hipMemcpyHostToDevice, ex.stream));
+        launch_caxpy(ex, g, cd, xv, yv, nrhs);
+        HC(hipStreamSynchronize(ex.stream));  // hc is reused by the next call
+        return DDWC_OK;
+    };
+    BlockInfo bi;
+    int sweeps = 0;
+    // out = M_sap eta
+    auto sap = [&](const double2* eta, double2* out) -> int {
+        HC(hipMemsetAsync(out, 0, sizeof(double2) * nw, ex.stream));
+        launch_axpby(ex, g, 1.0, eta, 0.0, nullptr, rho, nrhs, MASK_ALL);
+        for (int cy = 0; cy < NCY; ++cy)
+            for (int colour = 0; colour < 2; ++colour) {
+                const int st = block_internal(C, ex, colour, mass, rho, dl, nrhs, btol, 1000, prec, &bi);
+                if (st != DDWC_OK && st != DDWC_ENOCONV) return st;
+                ++sweeps;
+                launch_axpby(ex, g, 1.0, out, 1.0, dl, out, nrhs, MASK_ALL);
+                launch_residual<double>(ex, g, C->U64, C->K64, mass4, out, eta, rho, part, nrhs, DDWC_K_DSLASH64,
+                                        dbytes);
+            }
+        return DDWC_OK;
+    };
+    std::vector<cx<double>> xy;
+    std::vector<double> bb, rr, yy;
+    CK(cdots(C, ex, b64, b64, nrhs, xy, bb));
+    for (int j = 0; j < nrhs; ++j)
+        if (!isfinite(bb[j])) return fail(DDWC_ENONFINITE, "non-finite right-hand side");
+    HC(hipMemsetAsync(x64, 0, sizeof(double2) * nw, ex.stream));
+    HC(hipMemcpyAsync(r, b64, sizeof(double2) * nw, hipMemcpyDeviceToDevice, ex.stream));
+    rr = bb;
+    int total = 0, nout = 0;
+    bool converged = false;
+    auto done = [&](int j, double rj) { return !(bb[j] > 0 && rj > tol * tol * bb[j]); };
+    // a[i][k*nrhs + j]: component of w_i (normalised) in D z_k; nk, ck per (k, RHS)
+    std::vector<std::vector<cx<double>>> a(NKV, std::vector<cx<double>>((size_t)NKV * nrhs));
+    std::vector<double> nk((size_t)NKV * nrhs);
+    std::vector<cx<double>> ck((size_t)NKV * nrhs), coef(nrhs);
+    while (true) {
+        bool all = true;
+        for (int j = 0; j < nrhs; ++j) all = all && done(j, rr[j]);
+        if (all) {
+            converged = true;
+            break;
+        }
+        if (total >= maxit || nout >= 200) break;
+        ++nout;
+        std::vector<double> rest = rr;
+        int kused = 0;
+        for (int k = 0; k < NKV && total < maxit; ++k) {
+            CK(sap(r, Z[k]));
+            launch_dslash<double>(ex, g, C->U64, C->K64, mass4, Z[k], W[k], nrhs, DDWC_K_DSLASH64, dbytes);
+            for (int i = 0; i < k; ++i) {  // modified Gram-Schmidt
+                CK(cdots(C, ex, W[i], W[k], nrhs, xy, yy));
+                for (int j = 0; j < nrhs; ++j) {
+                    a[i][(size_t)k * nrhs + j] = xy[j];
+                    coef[j] = mk(-xy[j].re, -xy[j].im);
+                }
+                CK(caxpy(coef, W[i], W[k]));
+            }
+            CK(cdots(C, ex, W[k], W[k], nrhs, xy, yy));
+            for (int j = 0; j < nrhs; ++j) {
+                const double n = yy[j] > 0 ? sqrt(yy[j]) : 0.0;
+                nk[(size_t)k * nrhs + j] = n;
+                coef[j] = mk(n > 0 ? 1.0 / n - 1.0 : -1.0, 0.0);  // w_k <- w_k / n_k
+            }
+            CK(caxpy(coef, W[k], W[k]));
+            CK(cdots(C, ex, W[k], r, nrhs, xy, yy));
+            for (int j = 0; j < nrhs; ++j) {
+                const bool use = nk[(size_t)k * nrhs + j] > 0;
+                ck[(size_t)k * nrhs + j] = use ? xy[j] : mk(0.0, 0.0);
+                coef[j] = use ? mk(-xy[j].re, -xy[j].im) : mk(0.0, 0.0);
+                if (use) rest[j] = fmax(rest[j] - (xy[j].re * xy[j].re + xy[j].im * xy[j].im), 0.0);
+            }
+            CK(caxpy(coef, W[k], r));
+            ++total;
+            kused = k + 1;
+            bool est = true;
+            for (int j = 0; j < nrhs; ++j) est = est && done(j, 4.0 * rest[j]);
+            if (est) break;
+        }
+        // x += sum_k beta_k z_k with beta from the triangular system n_k beta_k + sum_{i>k} a_ki beta_i = c_k
+        std::vector<cx<double>> beta((size_t)kused * nrhs);
+        for (int j = 0; j < nrhs; ++j)
+            for (int k = kused - 1; k >= 0; --k) {
+                const double n = nk[(size_t)k * nrhs + j];
+                cx<double> t = ck[(size_t)k * nrhs + j];
+                for (int i = k + 1; i < kused; ++i) t = t - a[k][(size_t)i * nrhs + j] * beta[(size_t)i * nrhs + j];
+                beta[(size_t)k * nrhs + j] = n > 0 ? mk(t.re / n, t.im / n) : mk(0.0, 0.0);
+            }
+        for (int k = 0; k < kused; ++k) {
+            for (int j = 0; j < nrhs; ++j) coef[j] = beta[(size_t)k * nrhs + j];
+            CK(caxpy(coef, Z[k], x64));
+        }
+        // exact residual
+        launch_residual<double>(ex, g, C->U64, C->K64, mass4, x64, b64, r, part, nrhs, DDWC_K_DSLASH64, dbytes);
+        CK(cdots(C, ex, r, r, nrhs, xy, rr));
+        for (int j = 0; j < nrhs; ++j)
+            if (!isfinite(rr[j])) return fail(DDWC_ENONFINITE, "non-finite residual in the global solve");
+    }
+    double worst = 0;
+    for (int j = 0; j < nrhs; ++j)
+        if (bb[j] > 0) worst = fmax(worst, sqrt(rr[j] / bb[j]));
+    if (info) {
+        info->outer += nout;
+        info->inner += total;
+        info->relres = fmax(info->relres, worst);
+    }
+    (void)sweeps;
+    if (!converged) return fail(DDWC_ENOCONV, "global solve did not reach its tolerance within maxit");
+    return DDWC_OK;
 }
 
 // Dhat_P(m) e for e already projected (internal FP64): out = e - P D_bb^-1 D_bw D_ww^-1 D_wb e.
@@ -1441,6 +1609,10 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
                 return fail(DDWC_EINVAL, "block threads must be 0 or a multiple of 64 in [64, 256]");
             C->opt_blk_threads = value;
             break;
+        case DDWC_OPT_SOLVER:
+            if (value != 0 && value != 1) return fail(DDWC_EINVAL, "solver must be 0 or 1");
+            C->opt_solver = value;
+            break;
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1454,6 +1626,7 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_GRAPHS: *value = C->opt_graphs; break;
         case DDWC_OPT_POLL: *value = C->opt_poll; break;
         case DDWC_OPT_BLOCK_THREADS: *value = C->opt_blk_threads; break;
+        case DDWC_OPT_SOLVER: *value = C->opt_solver; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;

@@ -140,6 +140,8 @@ void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed);
 // z = a*x + b*y on sites selected by mask (others of z set to zero); x or y may be null (= 0).
 void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, const double2* y, double2* z,
                   int nrhs, int mask);
+// y += c_r x per RHS (c device, nrhs complex).
+void launch_caxpy(Exec& e, const Geom& g, const double2* c, const double2* x, double2* y, int nrhs);
 // partials: (x, y) complex and (y, y) per RHS; x may equal y.
 void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs);
 

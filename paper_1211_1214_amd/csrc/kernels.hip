@@ -548,6 +548,29 @@ void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, 
     k_axpby<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, a, x, b, y, z, nrhs, mask);
 }
 
+// y = y + c_r x for every RHS r, c device [nrhs] complex (GCR updates); no site mask.
+__global__ __launch_bounds__(WG) void k_caxpy(unsigned V, const double2* __restrict__ c, const double2* __restrict__ x,
+                                              double2* __restrict__ y) {
+    const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (s >= V) return;
+    const double2 cw = c[rhs];
+    if (cw.x == 0.0 && cw.y == 0.0) return;
+    const cx<double> cc = mk(cw.x, cw.y);
+    const size_t off = (size_t)rhs * 12 * V;
+    cx<double> u[12], w[12];
+    load_spinor(x + off, V, s, u);
+    load_spinor(y + off, V, s, w);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = w[k] + cc * u[k];
+    store_spinor(y + off, V, s, w);
+}
+
+void launch_caxpy(Exec& e, const Geom& g, const double2* c, const double2* x, double2* y, int nrhs) {
+    Timed t(e, 3, 0);
+    k_caxpy<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>((unsigned)g.V, c, x, y);
+}
+
 __global__ __launch_bounds__(WG) void k_dots(Geom g, const double2* __restrict__ x, const double2* __restrict__ y,
                                              double* part, int nrhs, int ntiles) {
     TileRhs tr = tile_rhs(ntiles, nrhs);

@@ -1,7 +1,7 @@
 """Schedule options through the C ABI: HIP-graph replay of the global solver's iteration
 chunks (bit-identical to eager launches, replayed many times with other work in between),
-block-solver workgroup sizes and poll intervals (each against the oracle), option
-validation and the autotuner."""
+block-solver workgroup sizes and poll intervals (each against the oracle), the SAP-preconditioned
+GCR global solver (against the oracle's solve and exponents), option validation and the autotuner."""
 import sys
 
 import numpy as np
@@ -91,7 +91,8 @@ def test_poll_option(env, poll):
 def test_option_validation(env):
     dev, U, ctx, S = env
     for opt, bad in ((binding.OPT_GRAPHS, 2), (binding.OPT_POLL, 0), (binding.OPT_POLL, 65),
-                     (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 512), (7, 1)):
+                     (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 512), (binding.OPT_SOLVER, 2),
+                     (7, 1)):
         with pytest.raises(dd.DDWCError) as e:
             ctx.set_option(opt, bad)
         assert e.value.code == -1
@@ -111,3 +112,49 @@ def test_autotune(env):
     m = dirac.mass(0.121)
     want = np.stack([S.inv_full(m)(bb.reshape(-1)).reshape(bb.shape) for bb in b])
     assert np.abs(x.cpu().numpy() - want).max() <= 1e-9 * np.abs(want).max()
+
+
+LEX_LAT, LEX_BLK = (4, 4, 2, 2), (2, 2, 1, 1)  # odd block extents: the lexicographic block solver
+
+
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
+@pytest.mark.parametrize("geom", ["eo", "lex"])
+def test_sap_gcr_solve(env, geom, prec):
+    """OPT_SOLVER = 1 (GCR preconditioned by the Schwarz alternating procedure) against the oracle's
+    dense solve, several RHS, both block-solver kinds."""
+    dev, U, ctx, S = env
+    say("sap-gcr solve", geom, prec)
+    if geom == "lex":
+        if prec == dd.MIXED16:
+            pytest.skip("FP16 storage needs even block extents")
+        Ul = inputs.make_links(LEX_LAT, 0.3, 11)
+        c = dd.Context(T(Ul, dev), LEX_LAT, LEX_BLK, -1, 1.0)
+        Sx, lat = Schwarz(Ul, LEX_LAT, LEX_BLK, 1.0), LEX_LAT
+    else:
+        c, Sx, lat = ctx, S, LAT
+    c.set_option(binding.OPT_SOLVER, 1)
+    assert c.get_option(binding.OPT_SOLVER) == 1
+    b = inputs.make_spinor(lat, 86, nrhs=3)
+    x, st = c.solve(0.121, T(b, dev), tol=1e-12, prec=prec)
+    c.set_option(binding.OPT_SOLVER, 0)
+    m = dirac.mass(0.121)
+    want = np.stack([Sx.inv_full(m)(bb.reshape(-1)).reshape(bb.shape) for bb in b])
+    assert np.abs(x.cpu().numpy() - want).max() <= 1e-9 * np.abs(want).max()
+    assert st["rel_residual"] <= 1e-12 and st["outer_iters"] >= 1
+    if c is not ctx:
+        c.close()
+
+
+def test_sap_gcr_estimate(env):
+    """The Schur estimator with the SAP-GCR global solver against the oracle's exponents."""
+    from oracle import estimator
+    dev, U, ctx, S = env
+    say("sap-gcr estimate")
+    eta = inputs.make_noise_batch(LAT, 12, 2, 3)
+    ctx.set_option(binding.OPT_SOLVER, 1)
+    r = ctx.det_ratio_estimate(0.1200, 0.1210, T(eta, dev), op=dd.OP_SCHUR, tol=1e-12, prec=dd.MIXED32)
+    ctx.set_option(binding.OPT_SOLVER, 0)
+    want = estimator.exponents(S, dirac.mass(0.1200), dirac.mass(0.1210), eta, "schur", "diff")
+    assert np.abs(r["x"] - want).max() <= 1e-8 * max(np.abs(want).max(), 1.0)
+    lw = estimator.log_w_gl(want)
+    assert abs(r["log_w_gl"] - lw) <= 1e-8 * max(abs(lw), 1.0)

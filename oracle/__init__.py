@@ -13,6 +13,9 @@ Contents
                 sparse Wilson-clover operator D(m) in the mass normalisation
   schwarz.py    D_bb, D_ww, D_bw, D_wb, the Schur complement and its
                 P-restricted form and inverse (Sec. 1, Eq. 1)
+  nested.py     nested domain decomposition (Sec. 2.2): the Schur complement of the
+                Dirichlet operator of one colour's outer blocks with respect to inner
+                blocks, and the total log W with exact inner block determinants
   estimator.py  the two-flavour noise estimator of Eq. (3), W_gl of Eq. (8) and the
                 one-flavour estimator of Eq. (11)
                 with mass interpolation, log-domain combination, variances

@@ -141,6 +141,29 @@ int ddwc_det_ratio_estimate(ddwc_ctx *ctx, double kappa1, double kappa2, int n_i
                             double *step_var_host, ddwc_stats *stats, void *stream);
 
 /*
+ * Nested domain decomposition (Sec. 2.2: the 8^4 blocks of the larger lattice are split again
+ * into an 8^4 Schur complement with Dirichlet boundaries and 4^4 blocks).
+ *   outer: the context whose Schwarz blocks B are split; inner: a context of the same lattice,
+ *   links, c_sw and time boundary with blocks b, b_mu dividing B_mu (EINVAL otherwise; the links
+ *   are compared through a fingerprint taken at ddwc_create).
+ * For the outer blocks of one colour, A = D_cc (the direct sum of their Dirichlet operators,
+ * Sec. 1) splits by the inner blocks (inner colouring) as det A = det Ahat * prod_s det D_s,
+ *   Ahat = 1 - A_bb^-1 A_bw A_ww^-1 A_wb on range(P_c),
+ * P_c = the face sites of black inner blocks inside the colour's outer blocks.  This call
+ * estimates log |det Ahat(m2) / det Ahat(m1)|^2 (n_f = 2; n_f = 1: the one-flavour form) exactly
+ * as ddwc_det_ratio_estimate(op = SCHUR) estimates W_gl (Eq. 8, mass interpolation, log domain):
+ * x_ij from e = P_c eta_ij, with Ahat^-1 applied by one block solve of the outer context.
+ * Arguments after colour as in ddwc_det_ratio_estimate (eta canonical, n_hit RHS per step,
+ * x_host [n_interp][n_hit], pairs for n_f = 1).  stats: the outer block solves.  The full
+ * log W of the larger lattice is log W_gl (outer context) + the two colours of this call
+ * + 2 sum over all inner blocks of [ln|det D_s(m2)| - ln|det D_s(m1)|] (ddwc_block_logdet
+ * on the inner context).  Uses both contexts' workspace; synchronises the stream.
+ */
+int ddwc_det_ratio_nested(ddwc_ctx *outer, ddwc_ctx *inner, int colour, double kappa1, double kappa2,
+                          int n_interp, int n_f, const void *eta, int n_hit, double tol, int prec, double *x_host,
+                          double *log_w, double *step_var_host, ddwc_stats *stats, void *stream);
+
+/*
  * Derivatives of the two-flavour exponents (Eq. 3 / Eq. 8 as in ddwc_det_ratio_estimate).
  * Given the upstream gradient gx_host = dL/dx_ij [n_interp][n_hit] of any scalar L of the
  * exponents (e.g. L = log W_gl: gx_ij = -softmax_j(-x_ij)), returns

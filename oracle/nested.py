@@ -107,3 +107,50 @@ def log_w_total(U, lat, outer, inner, csw, m1, m2, eta_gl, eta_nested, time_bc=-
         lw += estimator.log_w_gl(estimator.exponents(Nc, m1, m2, eta_nested[c], "schur", "diff"))
         lw += 2 * (sum(la for _, la in Nc.inner_block_logdets(m2)) - sum(la for _, la in Nc.inner_block_logdets(m1)))
     return lw
+
+
+class NestedMatrixFree:
+    """The same interface for lattices too large for assembled matrices: the matrix-free C
+    version of the oracle with the inner blocks (inner block solves and hops) and with the
+    outer blocks (the inversion of A_c is a block solve of colour c); every hop cut to the
+    colour-c outer blocks."""
+
+    def __init__(self, U, lat, outer, inner, csw: float, colour: int, time_bc: int = -1, tol: float = 1e-13):
+        from .cref import CRef
+        for B, b in zip(outer, inner):
+            if B % b != 0:
+                raise ValueError(f"inner block extent {b} does not divide outer extent {B}")
+        self.lat, self.colour, self.tol = tuple(lat), colour, tol
+        self.V = lt.volume(lat)
+        self.inner = CRef(U, lat, inner, csw, time_bc)
+        self.outer = CRef(U, lat, outer, csw, time_bc)
+        self.region = (lt.colour(lat, outer) == colour)[:, None, None]
+        self.pmask = (lt.face_black(lat, inner) & (lt.colour(lat, outer) == colour))[:, None, None]
+
+    def close(self):
+        self.inner.close()
+        self.outer.close()
+
+    def flat(self, psi):
+        return np.asarray(psi).reshape(-1)
+
+    def _spinor(self, psi):
+        return np.asarray(psi).reshape(self.V, 4, 3)
+
+    def restrict_P(self, psi):
+        return self._spinor(psi) * self.pmask
+
+    def hop_wb(self, m, psi):
+        return self.inner.hop(1, self._spinor(psi)) * self.region
+
+    def hop_bw(self, m, psi):
+        return self.inner.hop(0, self._spinor(psi)) * self.region
+
+    def block_inverse(self, colour: int, m: float, psi):
+        return self.inner.block_solve(colour, m, self._spinor(psi), self.tol)
+
+    def hat_inverse(self, m: float, phi):
+        """Ahat_c^-1 phi = phi - P_c [A_c^-1 (0_b, A_wb phi)]_b."""
+        f = self.restrict_P(phi)
+        chi = self.outer.block_solve(self.colour, m, self.hop_wb(m, f), self.tol)
+        return self.restrict_P(f - self.restrict_P(chi))

@@ -44,6 +44,7 @@ SIGNATURES = {
     "ddwc_schur_apply": (_I, [_P, _D, _I, _P, _P, _I, _D, _I, _PS, _P]),
     "ddwc_solve": (_I, [_P, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),
     "ddwc_det_ratio_estimate": (_I, [_P, _D, _D, _I, _I, _I, _P, _I, _D, _I, _PD, _PD, _PD, _PS, _P]),
+    "ddwc_det_ratio_nested": (_I, [_P, _P, _I, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _PD, _PS, _P]),
     "ddwc_det_ratio_grad": (_I, [_P, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _P, _PS, _P]),
     "ddwc_link_force": (_I, [_P, _P, _P, _I, _PD, _P, _P]),
     "ddwc_block_logdet": (_I, [_P, _D, _I, _PD, _PI, _P]),
@@ -203,6 +204,37 @@ class Context:
         if n_f == 1:
             x = x[..., 0] + 1j * x[..., 1]
         return {"x": x, "log_w_gl": lw.value, "step_var": var, "stats": st.as_dict(), "status": code}
+
+    def det_ratio_nested(self, inner, colour, kappa1, kappa2, eta, tol=1e-12, prec=FP64, n_f=2, allow=()):
+        """Nested-DD factor of the outer blocks of one colour (this context: outer blocks; inner: a
+        Context of the same links with smaller blocks): x and log |det Ahat(m2)/det Ahat(m1)|^2."""
+        sh = tuple(eta.shape)
+        if len(sh) != 5 or sh[2:] != (self.V, 4, 3):
+            raise ValueError(f"eta must have shape (n_interp, n_hit, {self.V}, 4, 3)")
+        n_interp, n_hit = sh[:2]
+        x = np.zeros((n_interp, n_hit) if n_f == 2 else (n_interp, n_hit, 2))
+        var = np.zeros(n_interp)
+        lw = ctypes.c_double()
+        st = Stats()
+        code = _check(lib().ddwc_det_ratio_nested(
+            self._h, inner._h, int(colour), float(kappa1), float(kappa2), int(n_interp), int(n_f), _ptr(eta),
+            int(n_hit), float(tol), int(prec), x.ctypes.data_as(_PD), ctypes.byref(lw), var.ctypes.data_as(_PD),
+            ctypes.byref(st), _stream()), "ddwc_det_ratio_nested", allow=allow)
+        if n_f == 1:
+            x = x[..., 0] + 1j * x[..., 1]
+        return {"x": x, "log_w": lw.value, "step_var": var, "stats": st.as_dict(), "status": code}
+
+    def log_w_nested(self, inner, kappa1, kappa2, eta_gl, eta_nested, tol=1e-12, prec=FP64):
+        """Two-flavour log W with nested DD: log W_gl (this context, Schur) + the nested factors of both
+        colours + the exact inner block factors (sums of the entry points' outputs)."""
+        r = self.det_ratio_estimate(kappa1, kappa2, eta_gl, op=OP_SCHUR, tol=tol, prec=prec)
+        parts = {"log_w_gl": r["log_w_gl"]}
+        for c in (BLACK, WHITE):
+            parts[f"log_w_nested{c}"] = self.det_ratio_nested(inner, c, kappa1, kappa2, eta_nested[c], tol=tol,
+                                                              prec=prec)["log_w"]
+        parts["log_w_inner_blocks"] = inner.log_w_blocks(kappa1, kappa2)
+        parts["log_w"] = sum(parts.values())
+        return parts
 
     def det_ratio_grad(self, kappa1, kappa2, eta, gx, op=OP_SCHUR, tol=1e-12, prec=FP64, want_kappa2=True,
                        want_links=True):

@@ -93,6 +93,7 @@ struct ddwc_ctx {
     int lat[4], blk[4];
     int device = 0;
     double csw = 0;
+    double links_fp = 0;  // fingerprint of the canonical links (equal links give equal values)
     cx<double>* U64 = nullptr;
     cx<float>* U32 = nullptr;
     double2* K64 = nullptr;
@@ -255,12 +256,22 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
         launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Kh64, C->Kh32, C->nbr_eo);
         launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32, C->Uh16);
     }
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    double* fpp = nullptr;
+    if (ws_t(C, "fp_part", FP_BLOCKS, &fpp) != DDWC_OK) {
         ddwc_destroy(C);
-        return fail(DDWC_EHIP, std::string("setup kernels failed: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return fail(DDWC_EHIP, "device allocation failed");
     }
+    launch_link_fp(ex, links_dev, n, fpp);
+    std::vector<double> fph(FP_BLOCKS);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e3 = hipMemcpyAsync(fph.data(), fpp, sizeof(double) * FP_BLOCKS, hipMemcpyDeviceToHost, ex.stream);
+    hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        ddwc_destroy(C);
+        hipError_t eb = e1 != hipSuccess ? e1 : (e3 != hipSuccess ? e3 : e2);
+        return fail(DDWC_EHIP, std::string("setup kernels failed: ") + hipGetErrorString(eb));
+    }
+    for (int k = 0; k < FP_BLOCKS; ++k) C->links_fp += fph[k];
     *out = C;
     return DDWC_OK;
 }
@@ -1240,87 +1251,64 @@ extern "C" int ddwc_schur_apply(ddwc_ctx* C, double kappa, int inverse, const vo
     return st;
 }
 
-extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2, int n_interp, int op, int n_f,
-                                       const void* eta, int n_hit, double tol, int prec, double* x_host,
-                                       double* log_w_gl, double* step_var_host, ddwc_stats* stats, void* stream) {
-    auto t0 = std::chrono::steady_clock::now();
-    CK(check_common(C, kappa1, n_hit, prec));
-    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
-    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
-    if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
-    if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
-    if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
-    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
-    Exec ex = make_exec(C, stream);
+// x_i = dm P [D_bb(mp)^-1 D_bb(mn)^-1 D_bw D_ww(mp)^-1 + D_bb(mn)^-1 D_bw D_ww(mp)^-1 D_ww(mn)^-1] D_wb e
+// = (Dhat_P(mp) - Dhat_P(mn)) e for e on range(P), dm = mp - mn (the resolvent difference of
+// the block operators, whose masses are pure shifts).  With a region, the hops are cut to the
+// outer blocks of one colour: the same expression for the Dirichlet operator of those blocks
+// split by this context's blocks (nested domain decomposition).
+struct Region {
+    Ext4 Bo;
+    int colour;
+};
+static int schur_diff_source(ddwc_ctx* C, Exec& ex, double mp, double mn, const double2* E, double2* G, int nrhs,
+                             double tol, int prec, BlockInfo* bi, const Region* rg) {
     const Geom& g = C->g;
-    const int nrhs = n_hit;
     const size_t nw = vec_words(C, nrhs, true);
-    const int nt = tiles_of(g.V);
-    const double m1 = mass_of(kappa1), m2 = mass_of(kappa2);
-    double2 *E, *A, *W1, *W12, *A1, *G, *Z;
-    double *part, *sums, *hb;
-    CK(ws_t(C, "e_E", nw, &E));
+    double2 *A, *W1, *W12, *A1;
     CK(ws_t(C, "e_A", nw, &A));
     CK(ws_t(C, "e_W1", nw, &W1));
     CK(ws_t(C, "e_W12", nw, &W12));
     CK(ws_t(C, "e_A1", nw, &A1));
-    CK(ws_t(C, "e_G", nw, &G));
-    CK(ws_t(C, "e_Z", nw, &Z));
-    CK(ws_t(C, "e_part", (size_t)nt * nrhs * NPART, &part));
-    CK(ws_t(C, "e_sums", (size_t)nrhs * NPART, &sums));
-    SolveInfo si;
-    BlockInfo bi;
-    std::vector<double> hs((size_t)nrhs * NPART);
-    for (int i = 0; i < n_interp; ++i) {
-        // m_i = (i/N) m2 + ((N - i)/N) m1
-        const double mp = ((double)i / n_interp) * m2 + ((double)(n_interp - i) / n_interp) * m1;
-        const double mn = ((double)(i + 1) / n_interp) * m2 + ((double)(n_interp - i - 1) / n_interp) * m1;
-        const double dm = mp - mn;
-        const char* eta_i = (const char*)eta + (size_t)i * nrhs * g.V * 12 * 16;
-        double ca, cb;  // x = ca * Re<e, y> + cb * ||y||^2
-        if (op == DDWC_OP_FULL) {
-            // M eta - eta = dm D(mn)^-1 eta
-            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_ALL);
-            CK(solve_internal(C, ex, mn, E, Z, nrhs, tol, 5000, prec, &si));
-            ca = 2 * dm;
-            cb = dm * dm;
+    auto hop = [&](const double2* in, double2* out, int dir) {
+        launch_hop<double>(ex, g, C->U64, in, out, nrhs, dir);
+        if (rg) launch_region(ex, g, rg->Bo, rg->colour, out, nrhs);
+    };
+    hop(E, A, 1);
+    CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, 5000, prec, bi));
+    CK(block_internal(C, ex, 1, mn, W1, W12, nrhs, tol, 5000, prec, bi));
+    hop(W1, A, 0);
+    CK(block_internal(C, ex, 0, mp, A, A1, nrhs, tol, 5000, prec, bi));
+    hop(W12, A, 0);
+    launch_axpby(ex, g, 1.0, A1, 1.0, A, A, nrhs, MASK_BLACK);
+    CK(block_internal(C, ex, 0, mn, A, G, nrhs, tol, 5000, prec, bi));
+    launch_axpby(ex, g, mp - mn, G, 0.0, nullptr, G, nrhs, MASK_P);
+    return DDWC_OK;
+}
+
+// The exponents of one step from the per-RHS sums (Re<e, y>, Im<e, y>, ||y||^2) of y = M e - e:
+// two flavours x = ca Re<e, y> + cb ||y||^2, one flavour x = f1 <e, y> (complex pairs).
+static int store_exponents(const std::vector<double>& hs, int nrhs, int n_f, double ca, double cb, double f1,
+                           double* x_row) {
+    for (int j = 0; j < nrhs; ++j) {
+        const double dre = hs[j * NPART], dim = hs[j * NPART + 1], nz = hs[j * NPART + 2];
+        if (n_f == 2) {
+            const double x = ca * dre + cb * nz;
+            if (!isfinite(x)) return fail(DDWC_ENONFINITE, "non-finite exponent");
+            x_row[j] = x;
         } else {
-            // Mh eta - eta = Dhat(mn)^-1 g, g = dm P [D_bb(mp)^-1 D_bb(mn)^-1 D_bw D_ww(mp)^-1
-            //                + D_bb(mn)^-1 D_bw D_ww(mp)^-1 D_ww(mn)^-1] D_wb eta
-            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_P);
-            launch_hop<double>(ex, g, C->U64, E, A, nrhs, 1);
-            CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, 5000, prec, &bi));
-            CK(block_internal(C, ex, 1, mn, W1, W12, nrhs, tol, 5000, prec, &bi));
-            launch_hop<double>(ex, g, C->U64, W1, A, nrhs, 0);
-            CK(block_internal(C, ex, 0, mp, A, A1, nrhs, tol, 5000, prec, &bi));
-            launch_hop<double>(ex, g, C->U64, W12, A, nrhs, 0);
-            launch_axpby(ex, g, 1.0, A1, 1.0, A, A, nrhs, MASK_BLACK);
-            CK(block_internal(C, ex, 0, mn, A, G, nrhs, tol, 5000, prec, &bi));
-            launch_axpby(ex, g, dm, G, 0.0, nullptr, G, nrhs, MASK_P);
-            CK(schur_hat_inverse(C, ex, mn, G, Z, nrhs, tol, prec, &si));
-            ca = 2.0;
-            cb = 1.0;
-        }
-        launch_dots(ex, g, E, Z, part, nrhs);
-        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
-        HC(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, ex.stream));
-        HC(hipStreamSynchronize(ex.stream));
-        for (int j = 0; j < nrhs; ++j) {
-            const double dre = hs[j * NPART], dim = hs[j * NPART + 1], nz = hs[j * NPART + 2];
-            if (n_f == 2) {
-                const double x = ca * dre + cb * nz;
-                if (!isfinite(x)) return fail(DDWC_ENONFINITE, "non-finite exponent");
-                x_host[(size_t)i * nrhs + j] = x;
-            } else {
-                // x = eta^+ (M - 1) eta = <eta, y> with y = M eta - eta: dm <eta, psi> or <e, zeta>
-                const double f = op == DDWC_OP_FULL ? dm : 1.0;
-                const double xr = f * dre, xi = f * dim;
-                if (!isfinite(xr) || !isfinite(xi)) return fail(DDWC_ENONFINITE, "non-finite exponent");
-                x_host[2 * ((size_t)i * nrhs + j)] = xr;
-                x_host[2 * ((size_t)i * nrhs + j) + 1] = xi;
-            }
+            const double xr = f1 * dre, xi = f1 * dim;
+            if (!isfinite(xr) || !isfinite(xi)) return fail(DDWC_ENONFINITE, "non-finite exponent");
+            x_row[2 * j] = xr;
+            x_row[2 * j + 1] = xi;
         }
     }
+    return DDWC_OK;
+}
+
+// log W = sum_i log W_i from the exponents x [n_interp][nrhs] (complex pairs for one flavour), and
+// the per-step variances.
+static int combine_steps(const double* x_host, int n_interp, int nrhs, int n_f, double* log_w,
+                         double* step_var_host) {
     // Per step, with a = -Re x and a_max = max_j a_j, the weights w_j = Re exp(-x_j + a_max)
     // = exp(a_j - a_max) cos(Im x_j) (cos = 1 for two flavours): log W_i = a_max + ln sum_j w_j
     // - ln n_hit, and the step variance is var_j(w)/mean_j(w)^2.
@@ -1346,11 +1334,144 @@ extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2
         if (!isfinite(var)) undefined = true;
         if (step_var_host) step_var_host[i] = var;
     }
-    *log_w_gl = undefined ? NAN : lw;
-    fill_stats(stats, si.outer, si.inner, si.relres, t0);
+    *log_w = undefined ? NAN : lw;
     if (!isfinite(lw) || undefined)
         return fail(DDWC_EUNDEF, "estimate undefined (non-positive real step mean, or non-finite mean or variance)");
     return DDWC_OK;
+}
+
+extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2, int n_interp, int op, int n_f,
+                                       const void* eta, int n_hit, double tol, int prec, double* x_host,
+                                       double* log_w_gl, double* step_var_host, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(C, kappa1, n_hit, prec));
+    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
+    if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
+    if (!eta || !x_host || !log_w_gl) return fail(DDWC_EINVAL, "null argument");
+    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
+    Exec ex = make_exec(C, stream);
+    const Geom& g = C->g;
+    const int nrhs = n_hit;
+    const size_t nw = vec_words(C, nrhs, true);
+    const int nt = tiles_of(g.V);
+    const double m1 = mass_of(kappa1), m2 = mass_of(kappa2);
+    double2 *E, *G, *Z;
+    double *part, *sums;
+    CK(ws_t(C, "e_E", nw, &E));
+    CK(ws_t(C, "e_G", nw, &G));
+    CK(ws_t(C, "e_Z", nw, &Z));
+    CK(ws_t(C, "e_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(C, "e_sums", (size_t)nrhs * NPART, &sums));
+    SolveInfo si;
+    BlockInfo bi;
+    std::vector<double> hs((size_t)nrhs * NPART);
+    for (int i = 0; i < n_interp; ++i) {
+        // m_i = (i/N) m2 + ((N - i)/N) m1
+        const double mp = ((double)i / n_interp) * m2 + ((double)(n_interp - i) / n_interp) * m1;
+        const double mn = ((double)(i + 1) / n_interp) * m2 + ((double)(n_interp - i - 1) / n_interp) * m1;
+        const double dm = mp - mn;
+        const char* eta_i = (const char*)eta + (size_t)i * nrhs * g.V * 12 * 16;
+        double ca, cb;  // x = ca * Re<e, y> + cb * ||y||^2
+        if (op == DDWC_OP_FULL) {
+            // M eta - eta = dm D(mn)^-1 eta
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_ALL);
+            CK(solve_internal(C, ex, mn, E, Z, nrhs, tol, 5000, prec, &si));
+            ca = 2 * dm;
+            cb = dm * dm;
+        } else {
+            // Mh eta - eta = Dhat(mn)^-1 g, g = dm P [D_bb(mp)^-1 D_bb(mn)^-1 D_bw D_ww(mp)^-1
+            //                + D_bb(mn)^-1 D_bw D_ww(mp)^-1 D_ww(mn)^-1] D_wb eta
+            launch_import<double>(ex, g, eta_i, E, nrhs, MASK_P);
+            CK(schur_diff_source(C, ex, mp, mn, E, G, nrhs, tol, prec, &bi, nullptr));
+            CK(schur_hat_inverse(C, ex, mn, G, Z, nrhs, tol, prec, &si));
+            ca = 2.0;
+            cb = 1.0;
+        }
+        launch_dots(ex, g, E, Z, part, nrhs);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        HC(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, ex.stream));
+        HC(hipStreamSynchronize(ex.stream));
+        // one flavour: x = eta^+ (M - 1) eta = <eta, y> with y = M eta - eta: dm <eta, psi> or <e, zeta>
+        CK(store_exponents(hs, nrhs, n_f, ca, cb, op == DDWC_OP_FULL ? dm : 1.0,
+                           x_host + (size_t)i * nrhs * (n_f == 2 ? 1 : 2)));
+    }
+    *log_w_gl = NAN;
+    fill_stats(stats, si.outer, si.inner, si.relres, t0);
+    return combine_steps(x_host, n_interp, nrhs, n_f, log_w_gl, step_var_host);
+}
+
+// Nested domain decomposition (Sec. 2.2): for the outer blocks of one colour, A = D_cc split by
+// the inner context's blocks, Ahat = 1 - A_bb^-1 A_bw A_ww^-1 A_wb on range(P_c), P_c the black
+// inner face sites inside those outer blocks.  Per step, Mh e - e = Ahat(mn)^-1 g with g from
+// schur_diff_source (hops cut to the region), and Ahat(mn)^-1 g = g - P_c [A(mn)^-1 (0, A_wb g)]_b,
+// the inversion of A being the outer context's block solve of that colour.
+extern "C" int ddwc_det_ratio_nested(ddwc_ctx* O, ddwc_ctx* I, int colour, double kappa1, double kappa2,
+                                     int n_interp, int n_f, const void* eta, int n_hit, double tol, int prec,
+                                     double* x_host, double* log_w, double* step_var_host, ddwc_stats* stats,
+                                     void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    CK(check_common(I, kappa1, n_hit, prec));
+    CK(check_common(O, kappa1, n_hit, prec));
+    if (O == I) return fail(DDWC_EINVAL, "outer and inner must be different contexts");
+    for (int mu = 0; mu < 4; ++mu) {
+        if (O->lat[mu] != I->lat[mu]) return fail(DDWC_EINVAL, "outer and inner contexts differ in lattice size");
+        if (O->blk[mu] % I->blk[mu] != 0)
+            return fail(DDWC_EINVAL, "inner block extents must divide the outer block extents");
+    }
+    if (O->g.tbc != I->g.tbc || O->csw != I->csw || O->links_fp != I->links_fp)
+        return fail(DDWC_EINVAL, "outer and inner contexts differ in links, c_sw or time boundary");
+    if (colour != 0 && colour != 1) return fail(DDWC_EINVAL, "colour must be 0 or 1");
+    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
+    if (!eta || !x_host || !log_w) return fail(DDWC_EINVAL, "null argument");
+    if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
+    Exec ex = make_exec(I, stream), exo = make_exec(O, stream);
+    const Geom& g = I->g;
+    const int nrhs = n_hit;
+    const size_t nw = vec_words(I, nrhs, true);
+    const int nt = tiles_of(g.V);
+    const double m1 = mass_of(kappa1), m2 = mass_of(kappa2);
+    Region rg;
+    for (int mu = 0; mu < 4; ++mu) rg.Bo.v[mu] = O->blk[mu];
+    rg.colour = colour;
+    double2 *E, *G, *Z, *S, *So, *Xo;
+    double *part, *sums;
+    CK(ws_t(I, "e_E", nw, &E));
+    CK(ws_t(I, "e_G", nw, &G));
+    CK(ws_t(I, "e_Z", nw, &Z));
+    CK(ws_t(I, "n_S", nw, &S));
+    CK(ws_t(O, "n_So", nw, &So));
+    CK(ws_t(O, "n_Xo", nw, &Xo));
+    CK(ws_t(I, "e_part", (size_t)nt * nrhs * NPART, &part));
+    CK(ws_t(I, "e_sums", (size_t)nrhs * NPART, &sums));
+    BlockInfo bi, bo;
+    std::vector<double> hs((size_t)nrhs * NPART);
+    for (int i = 0; i < n_interp; ++i) {
+        const double mp = ((double)i / n_interp) * m2 + ((double)(n_interp - i) / n_interp) * m1;
+        const double mn = ((double)(i + 1) / n_interp) * m2 + ((double)(n_interp - i - 1) / n_interp) * m1;
+        const char* eta_i = (const char*)eta + (size_t)i * nrhs * g.V * 12 * 16;
+        launch_import<double>(ex, g, eta_i, E, nrhs, MASK_P);
+        launch_region(ex, g, rg.Bo, colour, E, nrhs);
+        CK(schur_diff_source(I, ex, mp, mn, E, G, nrhs, tol, prec, &bi, &rg));
+        // Ahat(mn)^-1 G
+        launch_hop<double>(ex, g, I->U64, G, S, nrhs, 1);
+        launch_region(ex, g, rg.Bo, colour, S, nrhs);
+        launch_relayout(ex, g, O->g, S, So, nrhs);
+        CK(block_internal(O, exo, colour, mn, So, Xo, nrhs, tol, 5000, prec, &bo));
+        launch_relayout(ex, O->g, g, Xo, S, nrhs);
+        launch_axpby(ex, g, 1.0, G, -1.0, S, Z, nrhs, MASK_P);
+        launch_dots(ex, g, E, Z, part, nrhs);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        HC(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, ex.stream));
+        HC(hipStreamSynchronize(ex.stream));
+        CK(store_exponents(hs, nrhs, n_f, 2.0, 1.0, 1.0, x_host + (size_t)i * nrhs * (n_f == 2 ? 1 : 2)));
+    }
+    *log_w = NAN;
+    fill_stats(stats, bo.outer, bo.inner, bo.relres, t0);
+    return combine_steps(x_host, n_interp, nrhs, n_f, log_w, step_var_host);
 }
 
 // Re <x, y> per RHS, to the host.

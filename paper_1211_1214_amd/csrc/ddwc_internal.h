@@ -142,6 +142,14 @@ void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, 
                   int nrhs, int mask);
 // y += c_r x per RHS (c device, nrhs complex).
 void launch_caxpy(Exec& e, const Geom& g, const double2* c, const double2* x, double2* y, int nrhs);
+// nested domain decomposition: cut to the outer blocks of one colour, copy between two block layouts
+struct Ext4 {
+    int v[4];
+};
+void launch_region(Exec& e, const Geom& g, const Ext4& Bo, int colour, double2* v, int nrhs);
+void launch_relayout(Exec& e, const Geom& gs, const Geom& gd, const double2* src, double2* dst, int nrhs);
+constexpr int FP_BLOCKS = 1024;  // workgroups of the link fingerprint
+void launch_link_fp(Exec& e, const void* links, size_t n, double* part);
 // partials: (x, y) complex and (y, y) per RHS; x may equal y.
 void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs);
 

@@ -571,6 +571,73 @@ void launch_caxpy(Exec& e, const Geom& g, const double2* c, const double2* x, do
     k_caxpy<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>((unsigned)g.V, c, x, y);
 }
 
+// ------------------------------------------------------------------ nested domain decomposition
+// v = 0 at every site outside the outer Schwarz blocks of one colour (outer extents Bo): the
+// cut that turns a hop of the inner decomposition into a hop of the Dirichlet operator of
+// those outer blocks.
+__global__ __launch_bounds__(WG) void k_region(Geom g, Ext4 Bo, int colour, double2* __restrict__ v, int nrhs) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (s >= g.V) return;
+    const Site S = decode(g, s);
+    int sum = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) sum += (S.n[mu] * g.b[mu] + S.l[mu]) / Bo.v[mu];
+    if ((sum & 1) == colour) return;
+    double2* f = v + (size_t)rhs * 12 * g.V;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) f[(size_t)c * g.V + s] = make_double2(0.0, 0.0);
+}
+
+void launch_region(Exec& e, const Geom& g, const Ext4& Bo, int colour, double2* v, int nrhs) {
+    Timed t(e, 4, 0);
+    k_region<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, Bo, colour, v, nrhs);
+}
+
+// dst (internal order of gd) = src (internal order of gs): the same lattice under two block sizes.
+__global__ __launch_bounds__(WG) void k_relayout(Geom gs, Geom gd, const double2* __restrict__ src,
+                                                 double2* __restrict__ dst, int nrhs) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (s >= gd.V) return;
+    const Site S = decode(gd, s);
+    int n[4], l[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int x = S.n[mu] * gd.b[mu] + S.l[mu];
+        n[mu] = x / gs.b[mu];
+        l[mu] = x % gs.b[mu];
+    }
+    const int t = block_base(gs, n) + local_index(gs, l);
+    const size_t off = (size_t)rhs * 12 * gd.V;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[off + (size_t)c * gd.V + s] = src[off + (size_t)c * gd.V + t];
+}
+
+void launch_relayout(Exec& e, const Geom& gs, const Geom& gd, const double2* src, double2* dst, int nrhs) {
+    Timed t(e, 4, 0);
+    k_relayout<<<dim3(tiles_of(gd.V), nrhs), WG, 0, e.stream>>>(gs, gd, src, dst, nrhs);
+}
+
+// Fingerprint of canonical links (n complex numbers): sum_i Re u_i h(2i) + Im u_i h(2i + 1) with
+// hash weights, in a fixed order (FP_BLOCKS workgroup partials, summed on the host in order), so
+// that equal link arrays give bit-equal fingerprints.
+__global__ __launch_bounds__(256) void k_link_fp(const double2* __restrict__ u, size_t n, double* __restrict__ part) {
+    double v[1] = {0.0};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)FP_BLOCKS * 256) {
+        const double2 w = u[i];
+        v[0] += w.x * (hash_unit(2 * i) - 0.5) + w.y * (hash_unit(2 * i + 1) - 0.5);
+    }
+    __shared__ double lds[16];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+void launch_link_fp(Exec& e, const void* links, size_t n, double* part) {
+    Timed t(e, 4, 0);
+    k_link_fp<<<FP_BLOCKS, 256, 0, e.stream>>>((const double2*)links, n, part);
+}
+
 __global__ __launch_bounds__(WG) void k_dots(Geom g, const double2* __restrict__ x, const double2* __restrict__ y,
                                              double* part, int nrhs, int ntiles) {
     TileRhs tr = tile_rhs(ntiles, nrhs);

@@ -1,0 +1,139 @@
+"""Nested domain decomposition through the C ABI (ddwc_det_ratio_nested).
+
+  * exponents of both outer colours against the oracle: assembled matrices on an 8x4^3
+    lattice with outer blocks 4x2^3 and inner blocks 2x1^3 (the lexicographic inner block
+    solver), the matrix-free C oracle on 8^4 with outer 4^4 and inner 2^4 blocks (even-odd
+    everywhere), FP64 and mixed precisions, two flavours and one flavour;
+  * the whole nested log W (W_gl, both nested factors, exact inner block determinants)
+    against the oracle's;
+  * argument validation (mismatched contexts, non-dividing blocks, colour).
+The 64x32^3 workload with 8^4 / 4^4 blocks is checked in test_gpu_64x32.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1211_1214_amd as dd  # noqa: E402
+from oracle import dirac, estimator  # noqa: E402
+from oracle.nested import Nested, NestedMatrixFree, log_w_total  # noqa: E402
+from paper_1211_1214_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+K1, K2 = 0.1200, 0.1210
+SMALL = ((8, 4, 4, 4), (4, 2, 2, 2), (2, 1, 1, 1))
+EVEN = ((8, 8, 8, 8), (4, 4, 4, 4), (2, 2, 2, 2))
+NHIT = 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+_want = {}
+
+
+def _oracle_x(case, colour, n_f):
+    """Oracle exponents of both flavour numbers from the same solves: with zeta = Mh e - e,
+    x = 2 Re<e, zeta> + ||zeta||^2 (two flavours) and <e, zeta> (one flavour)."""
+    if (case, colour) not in _want:
+        lat, outer, inner = SMALL if case == "small" else EVEN
+        U = inputs.make_links(lat, 0.3, 31)
+        eta = inputs.make_noise_batch(lat, 31 + colour, 2, NHIT)
+        ms = estimator.interpolation_masses(dirac.mass(K1), dirac.mass(K2), 2)
+        S = Nested(U, lat, outer, inner, 1.0, colour) if case == "small" else \
+            NestedMatrixFree(U, lat, outer, inner, 1.0, colour)
+        x2, x1 = np.zeros((2, NHIT)), np.zeros((2, NHIT), dtype=complex)
+        for i in range(2):
+            for j in range(NHIT):
+                e = S.restrict_P(eta[i, j])
+                zeta = S.hat_inverse(ms[i + 1], estimator.schur_difference_source(S, ms[i], ms[i + 1], e))
+                d = np.vdot(e.reshape(-1), np.asarray(zeta).reshape(-1))
+                x2[i, j] = 2 * d.real + np.vdot(zeta, zeta).real
+                x1[i, j] = d
+        if case != "small":
+            S.close()
+        _want[(case, colour)] = {2: x2, 1: x1}
+    return _want[(case, colour)][n_f]
+
+
+@pytest.mark.parametrize("n_f", [2, 1])
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
+@pytest.mark.parametrize("case", ["small", "even"])
+def test_nested_exponents(dev, case, prec, n_f):
+    lat, outer, inner = SMALL if case == "small" else EVEN
+    if prec == dd.MIXED16 and case == "small":
+        pytest.skip("FP16 storage needs even block extents")
+    say("nested", case, prec, n_f)
+    U = inputs.make_links(lat, 0.3, 31)
+    O = dd.Context(T(U, dev), lat, outer, -1, 1.0)
+    I = dd.Context(T(U, dev), lat, inner, -1, 1.0)
+    for colour in (0, 1):
+        eta = inputs.make_noise_batch(lat, 31 + colour, 2, NHIT)
+        r = O.det_ratio_nested(I, colour, K1, K2, T(eta, dev), tol=1e-12, prec=prec, n_f=n_f)
+        want = _oracle_x(case, colour, n_f)
+        scale = max(np.abs(want).max(), 1.0)
+        assert np.abs(r["x"] - want).max() <= 1e-8 * scale, (colour, r["x"], want)
+        lw = estimator.log_w_gl(want) if n_f == 2 else estimator.log_w_one_flavour(want)
+        assert abs(r["log_w"] - lw) <= 1e-8 * max(abs(lw), 1.0)
+        assert r["stats"]["rel_residual"] <= 1e-12
+    O.close()
+    I.close()
+
+
+def test_nested_total_log_w(dev):
+    lat, outer, inner = SMALL
+    say("nested total")
+    U = inputs.make_links(lat, 0.3, 32)
+    eta_gl = inputs.make_noise_batch(lat, 32, 2, 3)
+    eta_n = [inputs.make_noise_batch(lat, 33 + c, 2, 3) for c in (0, 1)]
+    O = dd.Context(T(U, dev), lat, outer, -1, 1.0)
+    I = dd.Context(T(U, dev), lat, inner, -1, 1.0)
+    got = O.log_w_nested(I, K1, K2, T(eta_gl, dev), [T(e, dev) for e in eta_n], tol=1e-12, prec=dd.FP64)
+    O.close()
+    I.close()
+    want = log_w_total(U, lat, outer, inner, 1.0, dirac.mass(K1), dirac.mass(K2), eta_gl, eta_n)
+    assert abs(got["log_w"] - want) <= 1e-8 * max(abs(want), 1.0), (got, want)
+
+
+def test_nested_validation(dev):
+    lat, outer, inner = SMALL
+    U = inputs.make_links(lat, 0.3, 34)
+    eta = T(inputs.make_noise_batch(lat, 34, 1, 2), dev)
+    O = dd.Context(T(U, dev), lat, outer, -1, 1.0)
+    I = dd.Context(T(U, dev), lat, inner, -1, 1.0)
+    U2 = U.copy()
+    U2[1, 7] = U2[1, 7] @ U2[2, 9]               # other links
+    I2 = dd.Context(T(U2, dev), lat, inner, -1, 1.0)
+    I3 = dd.Context(T(U, dev), lat, inner, -1, 0.5)  # other c_sw
+    for bad in (I2, I3, O):
+        with pytest.raises(dd.DDWCError) as e:
+            O.det_ratio_nested(bad, 0, K1, K2, eta)
+        assert e.value.code == -1
+    with pytest.raises(dd.DDWCError):
+        O.det_ratio_nested(I, 2, K1, K2, eta)
+    lat4 = (12, 4, 4, 4)
+    U4 = inputs.make_links(lat4, 0.3, 35)
+    O4 = dd.Context(T(U4, dev), lat4, (2, 2, 2, 2), -1, 1.0)
+    I4 = dd.Context(T(U4, dev), lat4, (3, 1, 1, 1), -1, 1.0)  # 3 does not divide 2
+    with pytest.raises(dd.DDWCError) as e:
+        O4.det_ratio_nested(I4, 0, K1, K2, T(inputs.make_noise_batch(lat4, 35, 1, 2), dev))
+    assert e.value.code == -1
+    with pytest.raises(dd.DDWCError):                # lattice sizes differ
+        O4.det_ratio_nested(I, 0, K1, K2, T(inputs.make_noise_batch(lat4, 35, 1, 2), dev))
+    for c in (O, I, I2, I3, O4, I4):
+        c.close()

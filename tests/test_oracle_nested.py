@@ -105,3 +105,18 @@ def test_whole_factorisation():
     f2, t2 = parts(m2)
     assert abs(f1 - t1) <= 1e-10 * abs(f1)
     assert abs(2 * (f2 - f1) - 2 * (t2 - t1)) <= 1e-9 * abs(f2 - f1)
+
+
+def test_matrix_free_route():
+    """The matrix-free C route (oracle/c) against the assembled matrices, both colours."""
+    from oracle.nested import NestedMatrixFree
+    lat, outer, inner = (8, 4, 4, 4), (4, 2, 2, 2), (2, 2, 2, 2)
+    U = inputs.make_links(lat, 0.3, 24)
+    eta = inputs.make_noise_batch(lat, 24, 1, 2)
+    m1, m2 = dirac.mass(K1), dirac.mass(K2)
+    for colour in (0, 1):
+        want = estimator.exponents(Nested(U, lat, outer, inner, 1.0, colour), m1, m2, eta, "schur", "diff")
+        R = NestedMatrixFree(U, lat, outer, inner, 1.0, colour)
+        got = estimator.exponents(R, m1, m2, eta, "schur", "diff")
+        R.close()
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max(), (colour, got, want)

@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule options")
+    ap.add_argument("--nested", action="store_true",
+                    help="time the nested-DD factor instead (64x32^3: 8^4 blocks split into 4^4 blocks)")
     ap.add_argument("--solver", choices=("bicgstab", "sap-gcr"), default="bicgstab",
                     help="global solver: even-odd BiCGStab or GCR preconditioned by Schwarz sweeps")
     ap.add_argument("--dslash-reps", type=int, default=20, help="launches per standalone Dslash measurement")
@@ -78,6 +80,8 @@ def main():
     import paper_1211_1214_amd as dd
     from paper_1211_1214_amd import inputs
 
+    if args.nested:
+        return nested_bench(args, dd, inputs, np, torch)
     cid = 3 if args.workload == "48x24" else 4
     cfg = inputs.CONFIGS[cid]
     lat, blk, nhit, nint = cfg["lat"], cfg["blk"], cfg["n_hit"], cfg["n_interp"]
@@ -214,6 +218,84 @@ def kernel_sources_digest():
 
 # kernel whose counters stand for each profiler class
 CLASS_KERNEL = {"block": "void ddwc::k_blk_inner<float>"}
+
+
+def nested_bench(args, dd, inputs, np, torch):
+    """Nested DD on the 64x32^3 workload: the Schur factor of the 8^4 blocks of each colour over
+    4^4 inner blocks (ddwc_det_ratio_nested), the first interpolation step with 24 RHS per
+    colour, FP16 storage in the inner solves.  One timed step = both colours."""
+    cfg = inputs.CONFIGS[4]
+    lat, blk, nhit = cfg["lat"], cfg["blk"], cfg["n_hit"]
+    inner = (4, 4, 4, 4)
+    m1, m2 = 1 / (2 * cfg["kappa1"]) - 4, 1 / (2 * cfg["kappa2"]) - 4
+    k_step = 1 / (2 * (m1 + (m2 - m1) / cfg["n_interp"] + 4))
+    prec = dd.MIXED16 if (args.inner or "fp16") == "fp16" else dd.MIXED32
+    dev = torch.device("cuda:0")
+    t = time.time()
+    Ud = torch.from_numpy(inputs.make_links(lat, cfg["eps"], 4)).to(dev)
+    O = dd.Context(Ud, lat, blk, -1, cfg["csw"])
+    I = dd.Context(Ud, lat, inner, -1, cfg["csw"])
+    del Ud
+    etas = [torch.from_numpy(inputs.make_noise_batch(lat, 40 + c, 1, nhit)).to(dev) for c in (0, 1)]
+    log(f"nested: contexts and noise in {time.time() - t:.1f}s")
+
+    def step():
+        return [O.det_ratio_nested(I, c, cfg["kappa1"], k_step, etas[c], tol=args.tol, prec=prec) for c in (0, 1)]
+
+    for w in range(args.warmup):
+        r = step()
+        log(f"nested warmup {w}: log W_c {r[0]['log_w']:.10f} {r[1]['log_w']:.10f}")
+    for c in (O, I):
+        c.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step()
+        log(f"nested step {k}: log W_c {r[0]['log_w']:.10f} {r[1]['log_w']:.10f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    for name, kc in (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32),
+                     ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER)):
+        a, b = O.profile_read(kc), I.profile_read(kc)
+        prof[name] = {k: a[k] + b[k] for k in a}
+    for c in (O, I):
+        c.profile_enable(False)
+    value = 2 * nhit * args.steps / elapsed
+    dom = max(("dslash32", "block", "dslash64", "blas"), key=lambda k: prof[k]["ms"])
+    pd = prof[dom]
+    per_ms = pd["ms"] / max(pd["launches"], 1)
+    per_b = pd["bytes"] / max(pd["launches"], 1)
+    achieved = per_b / (per_ms * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
+    parity = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_nested_64x32.json")
+    if os.path.exists(gpath):
+        for key, xo in json.load(open(gpath))["x_nested"].items():
+            c, i, j = map(int, key.split(","))
+            parity[f"x{c}_{i}{j}_rel"] = abs(r[c]["x"][i, j] - xo) / max(abs(xo), 1.0)
+    total_ms = sum(p["ms"] for p in prof.values())
+    line = {
+        "metric": "nested-DD Schur-factor estimates/s", "value": round(value, 3), "unit": "estimates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 storage, f32 arithmetic inner / f64 outer" if prec == dd.MIXED16 else "f32 inner / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": "nested DD factor, 64x32^3, 8^4 outer blocks split into 4^4 inner blocks, "
+                               "Wilson-clover c_sw=1, step kappa 0.1200 -> m_1 of 4 interpolation steps, 24 RHS "
+                               "per outer colour, both colours per step",
+                   "lattice": list(lat), "outer_blocks": list(blk), "inner_blocks": list(inner), "n_hit": nhit,
+                   "tol": args.tol},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "launches": pd["launches"], "avg_launch_us": round(per_ms * 1e3, 2), "bytes_per_launch": per_b},
+        "cpu_baseline": None,
+        "parity": parity,
+        "log_w": [r[0]["log_w"], r[1]["log_w"]],
+        "kernel_time_share": {k: round(p["ms"] / total_ms, 3) for k, p in prof.items()} if total_ms else None,
+    }
+    print(json.dumps(line), flush=True)
+    O.close()
+    I.close()
 
 
 def measured_traffic(workload, kclass):

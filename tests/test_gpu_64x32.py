@@ -5,7 +5,8 @@ The oracle cannot redo the batch in seconds, so the checks are
   * sampled exponents x_ij against the oracle values stored by tests/golden/make_golden_64x32.py,
   * the FP64 single-RHS path on noise vector 0 (all four steps) against the mixed batch,
   * the FP16-storage inner solver (DDWC_MIXED16) against the oracle values and the FP32 batch,
-  * the final residuals of the solver statistics.
+  * the final residuals of the solver statistics;
+  * nested DD (8^4 outer, 4^4 inner blocks) against the stored oracle exponents.
 """
 import json
 import os
@@ -63,3 +64,50 @@ def test_64x32_estimate():
                                  prec=dd.FP64)
     assert np.all(np.abs(r64["x"][:, 0] - x[:, 0]) <= 1e-8 * np.maximum(np.abs(x[:, 0]), 1.0))
     ctx.close()
+
+
+GOLDEN_NESTED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_nested_64x32.json")
+
+
+@pytest.mark.timeout(400)
+def test_64x32_nested():
+    """Nested DD on the 64x32^3 workload (Sec. 2.2): the 8^4 blocks split into 4^4 blocks.  The
+    first of the N = 4 interpolation steps (m_0 -> m_1) with 24 RHS per outer colour, FP16
+    storage and FP32 inner solves, against the oracle values stored by
+    tests/golden/make_golden_nested_64x32.py, and the two precisions against each other."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cfg = inputs.CONFIGS[4]
+    lat, blk = cfg["lat"], cfg["blk"]
+    m1 = 1 / (2 * cfg["kappa1"]) - 4
+    m2 = 1 / (2 * cfg["kappa2"]) - 4
+    k_step = 1 / (2 * (m1 + (m2 - m1) / cfg["n_interp"] + 4))   # kappa of m_1
+    gold = json.load(open(GOLDEN_NESTED))
+    say("64x32 nested: inputs and contexts (8^4 outer, 4^4 inner)")
+    U = inputs.make_links(lat, cfg["eps"], 4)
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(dev)
+    del U
+    O = dd.Context(Ud, lat, blk, -1, cfg["csw"])
+    I = dd.Context(Ud, lat, tuple(gold["inner_blocks"]), -1, cfg["csw"])
+    del Ud
+    for c in (0, 1):
+        eta = torch.from_numpy(inputs.make_noise_batch(lat, 40 + c, 1, cfg["n_hit"])).to(dev)
+        say(f"64x32 nested: colour {c}, FP16 storage")
+        r16 = O.det_ratio_nested(I, c, cfg["kappa1"], k_step, eta, tol=1e-10, prec=dd.MIXED16)
+        say(f"64x32 nested: colour {c}, FP32")
+        r32 = O.det_ratio_nested(I, c, cfg["kappa1"], k_step, eta, tol=1e-10, prec=dd.MIXED32)
+        del eta
+        for r in (r16, r32):
+            assert r["x"].shape == (1, cfg["n_hit"]) and np.isfinite(r["log_w"])
+            assert r["stats"]["rel_residual"] <= 1e-10
+        for key, xo in gold["x_nested"].items():
+            cc, i, j = map(int, key.split(","))
+            if cc != c:
+                continue
+            say(f"64x32 nested: x[{c}][{i},{j}] = {r16['x'][i, j]!r} (FP16), {r32['x'][i, j]!r} (FP32), oracle {xo!r}")
+            assert abs(r16["x"][i, j] - xo) <= 1e-8 * max(abs(xo), 1.0)
+            assert abs(r32["x"][i, j] - xo) <= 1e-8 * max(abs(xo), 1.0)
+        assert np.all(np.abs(r16["x"] - r32["x"]) <= 1e-8 * np.maximum(np.abs(r32["x"]), 1.0))
+    O.close()
+    I.close()

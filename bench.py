@@ -118,7 +118,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {name: ctx.profile_read(kc) for name, kc in
-            (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32),
+            (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32), ("eohop", dd.binding.K_EOHOP),
              ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER))}
     ctx.profile_enable(False)
     elapsed = t1 - t0
@@ -155,14 +155,24 @@ def main():
              for i in range(nint)), default=None)
     parity["x_mixed_vs_fp64_rel_max"] = d
 
-    # roofline of the dominant kernel class (live HIP-event durations over the timed region)
-    dom = max(("dslash32", "block", "dslash64", "blas"), key=lambda k: prof[k]["ms"])
+    # Roofline of the Dslash the metric names: the even-odd hop-and-inverse kernel of the global
+    # solver (one kernel; live HIP-event durations over the timed region).  The persistent block
+    # solver, which takes a similar share of the time, keeps its vectors in the last-level cache
+    # (its algorithmic bytes per second exceed the HBM peak), so it is reported beside it.
+    dom = "eohop" if prof["eohop"]["launches"] else max(("dslash32", "block", "dslash64", "blas"),
+                                                         key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     per_launch_ms = pd["ms"] / max(pd["launches"], 1)
     per_launch_bytes = pd["bytes"] / max(pd["launches"], 1)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
-    ds = prof["dslash32"]
-    dslash_gbs = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9 if ds["ms"] > 0 else None
+    ds_ms, ds_b = prof["dslash32"]["ms"] + prof["eohop"]["ms"], prof["dslash32"]["bytes"] + prof["eohop"]["bytes"]
+    dslash_gbs = ds_b / (ds_ms * 1e-3) / 1e9 if ds_ms > 0 else None
+    pb = prof["block"]
+    block = None if not pb["launches"] else {
+        "launches": pb["launches"], "avg_launch_us": round(1e3 * pb["ms"] / pb["launches"], 2),
+        "algorithmic_gbs": round(pb["bytes"] / (pb["ms"] * 1e-3) / 1e9, 1),
+        "note": "algorithmic bytes of the block BiCGStab per second; above the HBM peak the block vectors "
+                "are served from the Infinity Cache"}
     traffic = measured_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
@@ -188,6 +198,7 @@ def main():
         "schedule": tuned,
         "cpu_baseline": cpu,
         "dslash": dslash,
+        "block_solver": block,
         "dslash32_in_solver_gbs": None if dslash_gbs is None else round(dslash_gbs, 1),
         "dslash32_in_solver_frac": None if dslash_gbs is None else round(dslash_gbs / HBM_PEAK_GBS, 4),
         "fp64_single_rhs_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 3),
@@ -217,7 +228,7 @@ def kernel_sources_digest():
 
 
 # kernel whose counters stand for each profiler class
-CLASS_KERNEL = {"block": "void ddwc::k_blk_inner<float>"}
+CLASS_KERNEL = {"eohop": "void ddwc::k_eo_hopinv<float, true>", "block": "void ddwc::k_blk_inner<float>"}
 
 
 def nested_bench(args, dd, inputs, np, torch):
@@ -256,13 +267,14 @@ def nested_bench(args, dd, inputs, np, torch):
     elapsed = time.perf_counter() - t0
     prof = {}
     for name, kc in (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32),
-                     ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER)):
+                     ("eohop", dd.binding.K_EOHOP), ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS),
+                     ("other", dd.binding.K_OTHER)):
         a, b = O.profile_read(kc), I.profile_read(kc)
         prof[name] = {k: a[k] + b[k] for k in a}
     for c in (O, I):
         c.profile_enable(False)
     value = 2 * nhit * args.steps / elapsed
-    dom = max(("dslash32", "block", "dslash64", "blas"), key=lambda k: prof[k]["ms"])
+    dom = max(("dslash32", "eohop", "block", "dslash64", "blas"), key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     per_ms = pd["ms"] / max(pd["launches"], 1)
     per_b = pd["bytes"] / max(pd["launches"], 1)

@@ -213,17 +213,28 @@ int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_ho
  *                          the exact FP64 residual) preconditioned by the Schwarz alternating
  *                          procedure: 3 multiplicative cycles over the black then the white
  *                          blocks, each block solve by the persistent block solver to 1e-1.
- * Results do not depend on the graph option; the others can change iteration counts and
+ *   DDWC_OPT_BLOCK_LDS     KiB of LDS reserved (not used) by each persistent block-solver workgroup,
+ *                          which caps the workgroups resident per CU and so the block vectors in
+ *                          flight (0 = none; at most the device's per-workgroup LDS minus 1 KiB).
+ * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
-typedef enum { DDWC_OPT_GRAPHS = 0, DDWC_OPT_POLL = 1, DDWC_OPT_BLOCK_THREADS = 2, DDWC_OPT_SOLVER = 3 } ddwc_option;
+typedef enum {
+    DDWC_OPT_GRAPHS = 0,
+    DDWC_OPT_POLL = 1,
+    DDWC_OPT_BLOCK_THREADS = 2,
+    DDWC_OPT_SOLVER = 3,
+    DDWC_OPT_BLOCK_LDS = 4
+} ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
 
 /*
  * Autotuner: times the schedule options on this lattice with nrhs reproducible right-hand
  * sides at the given kappa and precision (a block sweep of one colour for each workgroup
- * size; a global solve for each poll interval with and without graphs, tolerance 1e-8) and
+ * size, without and with the LDS reservation that leaves room for two block-solver
+ * workgroups per CU; a global solve for each poll interval with and without graphs,
+ * tolerance 1e-8) and
  * sets the fastest.  *seconds_host (may be null) receives the tuning time.  Synchronises.
  */
 int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *seconds_host, void *stream);
@@ -236,11 +247,13 @@ int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *secon
  */
 typedef enum {
     DDWC_K_DSLASH64 = 0,  /* full-lattice Dslash, FP64 */
-    DDWC_K_DSLASH32 = 1,  /* full-lattice Dslash, FP32 */
+    DDWC_K_DSLASH32 = 1,  /* Dslash in FP32/FP16: full lattice, and the diagonal-and-hop half of the
+                             even-odd operator in the global solver */
     DDWC_K_BLOCK = 2,     /* persistent block solver */
     DDWC_K_BLAS = 3,      /* vector updates and reductions */
     DDWC_K_OTHER = 4,     /* hops, conversions, projections */
-    DDWC_K_COUNT = 5
+    DDWC_K_EOHOP = 5,     /* hop-and-inverse half of the even-odd operator in the FP32/FP16 global solver */
+    DDWC_K_COUNT = 6
 } ddwc_kernel_class;
 int ddwc_profile_enable(ddwc_ctx *ctx, int on);
 int ddwc_profile_read(ddwc_ctx *ctx, int kclass, long long *launches, double *total_ms, double *bytes);

@@ -18,8 +18,8 @@ OK, EINVAL, ENOCONV, EHIP, ENONFINITE, EUNDEF = 0, -1, -2, -3, -4, -5
 FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
-K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER = range(5)
-OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER = range(4)
+K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER, K_EOHOP = range(6)
+OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS = range(5)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.
@@ -299,7 +299,8 @@ class Context:
         _check(lib().ddwc_autotune(self._h, float(kappa), int(nrhs), int(prec), ctypes.byref(t), _stream()),
                "ddwc_autotune")
         return {"graphs": self.get_option(OPT_GRAPHS), "poll": self.get_option(OPT_POLL),
-                "block_threads": self.get_option(OPT_BLOCK_THREADS), "seconds": t.value}
+                "block_threads": self.get_option(OPT_BLOCK_THREADS), "block_lds": self.get_option(OPT_BLOCK_LDS),
+                "seconds": t.value}
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

@@ -127,6 +127,7 @@ struct ddwc_ctx {
     int opt_poll = 2;         // BiCGStab iterations between host convergence checks
     int opt_blk_threads = 0;  // block-solver workgroup size (0: default rule)
     int opt_solver = 0;       // global solver: 0 even-odd BiCGStab, 1 SAP-preconditioned GCR
+    int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
     struct Graph {
         std::vector<uintptr_t> key;
@@ -175,6 +176,7 @@ static double mass_of(double kappa) { return 1.0 / (2.0 * kappa) - 4.0; }
 static Exec make_exec(ddwc_ctx* C, void* stream) {
     Exec ex{(hipStream_t)stream, &C->prof, C->nbr};
     ex.blk_threads = C->opt_blk_threads;
+    ex.blk_lds = C->opt_blk_lds;
     return ex;
 }
 
@@ -659,7 +661,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     // `iters` BiCGStab iterations on stream ee (the caller's, or the capture stream)
     auto chunk = [&](Exec& ee, int iters) {
         auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
-            launch_eo_hopinv<S>(ee, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, kcl, hbytes);
+            launch_eo_hopinv<S>(ee, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, fp64 ? kcl : DDWC_K_EOHOP, hbytes);
             launch_eo_diaghop<S>(ee, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
                                  hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
         };
@@ -1270,8 +1272,7 @@ static int schur_diff_source(ddwc_ctx* C, Exec& ex, double mp, double mn, const 
     CK(ws_t(C, "e_W12", nw, &W12));
     CK(ws_t(C, "e_A1", nw, &A1));
     auto hop = [&](const double2* in, double2* out, int dir) {
-        launch_hop<double>(ex, g, C->U64, in, out, nrhs, dir);
-        if (rg) launch_region(ex, g, rg->Bo, rg->colour, out, nrhs);
+        launch_hop<double>(ex, g, C->U64, in, out, nrhs, dir, rg ? &rg->Bo : nullptr, rg ? rg->colour : -1);
     };
     hop(E, A, 1);
     CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, 5000, prec, bi));
@@ -1457,8 +1458,7 @@ extern "C" int ddwc_det_ratio_nested(ddwc_ctx* O, ddwc_ctx* I, int colour, doubl
         launch_region(ex, g, rg.Bo, colour, E, nrhs);
         CK(schur_diff_source(I, ex, mp, mn, E, G, nrhs, tol, prec, &bi, &rg));
         // Ahat(mn)^-1 G
-        launch_hop<double>(ex, g, I->U64, G, S, nrhs, 1);
-        launch_region(ex, g, rg.Bo, colour, S, nrhs);
+        launch_hop<double>(ex, g, I->U64, G, S, nrhs, 1, &rg.Bo, colour);
         launch_relayout(ex, g, O->g, S, So, nrhs);
         CK(block_internal(O, exo, colour, mn, So, Xo, nrhs, tol, 5000, prec, &bo));
         launch_relayout(ex, O->g, g, Xo, S, nrhs);
@@ -1734,6 +1734,15 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
             if (value != 0 && value != 1) return fail(DDWC_EINVAL, "solver must be 0 or 1");
             C->opt_solver = value;
             break;
+        case DDWC_OPT_BLOCK_LDS: {
+            int maxlds = 0;
+            HC(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device));
+            if (value < 0 || ((long long)value << 10) + 1024 > maxlds)
+                return fail(DDWC_EINVAL, "block LDS reservation must be in [0, " + std::to_string(maxlds / 1024 - 1) +
+                                             "] KiB");
+            C->opt_blk_lds = value;
+            break;
+        }
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1748,6 +1757,7 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_POLL: *value = C->opt_poll; break;
         case DDWC_OPT_BLOCK_THREADS: *value = C->opt_blk_threads; break;
         case DDWC_OPT_SOLVER: *value = C->opt_solver; break;
+        case DDWC_OPT_BLOCK_LDS: *value = C->opt_blk_lds; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;
@@ -1780,23 +1790,32 @@ extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, doub
         }
         return best;
     };
-    const int saved_threads = C->opt_blk_threads;
+    // block solver: workgroup size x residency (no LDS reservation, or one that leaves room for two
+    // persistent workgroups per CU)
+    int maxlds = 0;
+    HC(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device));
+    const int two_per_cu = std::max(0, (maxlds / 2 - 2048) >> 10);
+    const int saved_threads = C->opt_blk_threads, saved_lds = C->opt_blk_lds;
     double best = 1e300;
-    int pick = saved_threads;
-    for (int T : {0, 128, 192, 256}) {
-        C->opt_blk_threads = T;
-        const double t = timed([&]() {
-            Exec ex = make_exec(C, stream);
-            BlockInfo bi;
-            return block_internal(C, ex, 0, mass, b, x, nrhs, 1e-8, 5000, prec, &bi);
-        });
-        if (t < 0) {
-            C->opt_blk_threads = saved_threads;
-            return fail(DDWC_ENOCONV, "autotune: block solve failed");
+    int pick = saved_threads, pick_lds = saved_lds;
+    for (int T : {0, 128, 192, 256})
+        for (int L : {0, two_per_cu}) {
+            C->opt_blk_threads = T;
+            C->opt_blk_lds = L;
+            const double t = timed([&]() {
+                Exec ex = make_exec(C, stream);
+                BlockInfo bi;
+                return block_internal(C, ex, 0, mass, b, x, nrhs, 1e-8, 5000, prec, &bi);
+            });
+            if (t < 0) {
+                C->opt_blk_threads = saved_threads;
+                C->opt_blk_lds = saved_lds;
+                return fail(DDWC_ENOCONV, "autotune: block solve failed");
+            }
+            if (t < best) best = t, pick = T, pick_lds = L;
         }
-        if (t < best) best = t, pick = T;
-    }
     C->opt_blk_threads = pick;
+    C->opt_blk_lds = pick_lds;
     const int saved_poll = C->opt_poll, saved_graphs = C->opt_graphs;
     best = 1e300;
     int pp = saved_poll, pg = saved_graphs;

@@ -416,7 +416,9 @@ void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typena
     bw.tmp = (W*)w[6];
     // the inner solve stops at this relative residual at the least (the storage's reach)
     const double floor_eps = std::is_same<S, double>::value ? 0.0 : std::is_same<S, H16>::value ? 1e-3 : 2e-6;
-    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
+    // e.blk_lds KiB of dynamic LDS (unused by the kernel) caps the workgroups resident per CU, and so
+    // the slabs in flight, which then stay in the last-level cache
+    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), (size_t)e.blk_lds << 10, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
                                                                        floor_eps, maxit, iters, colour, nrhs);
 }
 size_t blk_slab_bytes(int prec, unsigned n2) {

@@ -48,6 +48,7 @@ struct Exec {
     Profiler* prof;
     const int* nbr;        // neighbour table [8][V] of the context
     int blk_threads = 0;   // workgroup size of the block-solver kernels (0: the default rule)
+    int blk_lds = 0;       // KiB of LDS reserved per persistent block-solver workgroup (caps residency)
 };
 
 // RAII-free scoped timing helper used by the launchers.
@@ -98,11 +99,18 @@ template <class R>
 void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
                      const typename Traits<R>::word* x, const typename Traits<R>::word* b,
                      typename Traits<R>::word* r, double* part, int nrhs, int kclass, double bytes);
+// Extents of an outer block decomposition (nested domain decomposition).
+struct Ext4 {
+    int v[4];
+};
+
 // out = hops crossing block faces into sites of colour `to_colour` (D_wb for white, D_bw for
-// black); out is zero on the other colour.
+// black); out is zero on the other colour.  With cut, out is also zero outside the outer blocks
+// (extents *cut) of colour cut_colour: the hops of the Dirichlet operator of those blocks.
 template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
-                typename Traits<R>::word* out, int nrhs, int to_colour);
+                typename Traits<R>::word* out, int nrhs, int to_colour, const Ext4* cut = nullptr,
+                int cut_colour = -1);
 
 // BiCGStab vector kernels on fields of n sites, nrhs RHS, per-RHS scalars in st, storage S
 // (double, float or H16; H16 fields must be RHS-innermost).  ri selects the RHS-innermost
@@ -143,9 +151,6 @@ void launch_axpby(Exec& e, const Geom& g, double a, const double2* x, double b, 
 // y += c_r x per RHS (c device, nrhs complex).
 void launch_caxpy(Exec& e, const Geom& g, const double2* c, const double2* x, double2* y, int nrhs);
 // nested domain decomposition: cut to the outer blocks of one colour, copy between two block layouts
-struct Ext4 {
-    int v[4];
-};
 void launch_region(Exec& e, const Geom& g, const Ext4& Bo, int colour, double2* v, int nrhs);
 void launch_relayout(Exec& e, const Geom& gs, const Geom& gd, const double2* src, double2* dst, int nrhs);
 constexpr int FP_BLOCKS = 1024;  // workgroups of the link fingerprint

@@ -204,13 +204,21 @@ template <class R>
 __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __restrict__ U,
                                             const typename Traits<R>::word* __restrict__ in,
                                             typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour,
-                                            const int* __restrict__ nbr, int ndir) {
+                                            const int* __restrict__ nbr, int ndir, Ext4 cut, int cut_colour) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
     if (s >= g.V) return;
     const size_t off = (size_t)rhs * Traits<R>::NCW * g.V;
     cx<R> y[12];
-    if ((s / (g.V / 2)) == to_colour) {
+    bool keep = (s / (g.V / 2)) == to_colour;
+    if (keep && cut_colour >= 0) {  // output cut to the outer blocks (extents cut) of one colour
+        const Site S = decode(g, s);
+        int sum = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) sum += (S.n[mu] * g.b[mu] + S.l[mu]) / cut.v[mu];
+        keep = (sum & 1) == cut_colour;
+    }
+    if (keep) {
         site_operator<R, false, HOPS_CROSSING, true>(g, s, in + off, U, nullptr, nbr, R(0), y, ndir);
     } else {
 #pragma unroll
@@ -221,9 +229,11 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __rest
 
 template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
-                typename Traits<R>::word* out, int nrhs, int to_colour) {
+                typename Traits<R>::word* out, int nrhs, int to_colour, const Ext4* cut, int cut_colour) {
     Timed t(e, 4, 0);
-    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour, e.nbr, 8);
+    const Ext4 c = cut ? *cut : Ext4{{1, 1, 1, 1}};
+    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour, e.nbr, 8, c,
+                                                             cut ? cut_colour : -1);
 }
 
 // ------------------------------------------------------------------ BiCGStab vector kernels
@@ -675,7 +685,7 @@ void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, dou
                                      const Traits<R>::word*, const Traits<R>::word*, Traits<R>::word*, double*,   \
                                      int, int, double);                                                           \
     template void launch_hop<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, Traits<R>::word*, int,  \
-                                int);                                                                             \
+                                int, const Ext4*, int);                                                           \
     template void launch_bicg_init<R>(Exec&, unsigned, bool, const double2*, const double*, Traits<R>::word*,      \
                                       Traits<R>::word*, Traits<R>::word*, Traits<R>::word*, double*, int);        \
     template void launch_bicg_s<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \

@@ -1,6 +1,7 @@
 """Schedule options through the C ABI: HIP-graph replay of the global solver's iteration
 chunks (bit-identical to eager launches, replayed many times with other work in between),
-block-solver workgroup sizes and poll intervals (each against the oracle), the SAP-preconditioned
+block-solver workgroup sizes, LDS residency caps and poll intervals (each against the oracle or
+bit-identical to the default), the SAP-preconditioned
 GCR global solver (against the oracle's solve and exponents), option validation and the autotuner."""
 import sys
 
@@ -75,6 +76,21 @@ def test_block_threads_option(env, threads):
     ctx.set_option(binding.OPT_BLOCK_THREADS, 0)
 
 
+@pytest.mark.parametrize("lds", [30, 78])
+def test_block_lds_option(env, lds):
+    """An LDS reservation only caps residency: the block solution is bit-identical."""
+    dev, U, ctx, S = env
+    say("block lds", lds)
+    b = T(inputs.make_spinor(LAT, 87, nrhs=2), dev)
+    for prec in (dd.MIXED32, dd.MIXED16, dd.FP64):
+        x0, _ = ctx.block_solve(1, 0.121, b, tol=1e-12, prec=prec)
+        ctx.set_option(binding.OPT_BLOCK_LDS, lds)
+        assert ctx.get_option(binding.OPT_BLOCK_LDS) == lds
+        x1, _ = ctx.block_solve(1, 0.121, b, tol=1e-12, prec=prec)
+        ctx.set_option(binding.OPT_BLOCK_LDS, 0)
+        assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
+
+
 @pytest.mark.parametrize("poll", [1, 8])
 def test_poll_option(env, poll):
     dev, U, ctx, S = env
@@ -92,6 +108,7 @@ def test_option_validation(env):
     dev, U, ctx, S = env
     for opt, bad in ((binding.OPT_GRAPHS, 2), (binding.OPT_POLL, 0), (binding.OPT_POLL, 65),
                      (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 512), (binding.OPT_SOLVER, 2),
+                     (binding.OPT_BLOCK_LDS, -1), (binding.OPT_BLOCK_LDS, 4096),
                      (7, 1)):
         with pytest.raises(dd.DDWCError) as e:
             ctx.set_option(opt, bad)
@@ -106,6 +123,7 @@ def test_autotune(env):
     say("autotune")
     r = ctx.autotune(0.121, 4, dd.MIXED32)
     assert r["graphs"] in (0, 1) and r["poll"] in (2, 4, 8) and r["block_threads"] in (0, 128, 192, 256)
+    assert 0 <= r["block_lds"] < 160
     assert r["seconds"] > 0
     b = inputs.make_spinor(LAT, 85, nrhs=4)
     x, st = ctx.solve(0.121, T(b, dev), tol=1e-12, prec=dd.MIXED32)

@@ -104,6 +104,8 @@ struct ddwc_ctx {
     cx<float>* Uh32 = nullptr;
     double2* Kh64 = nullptr;
     cx<f16>* Uh16 = nullptr;  // FP16 half-order links (storage of the FP16 inner solver)
+    cx<float>* Uh32s = nullptr;  // site-major copies of the FP32 and FP16 half-order links, read by the
+    cx<f16>* Uh16s = nullptr;    // RHS-innermost kernels of the global solver
     float4* Kh32 = nullptr;
     int* nbr_eo = nullptr;
     struct Ainv {
@@ -251,12 +253,15 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
             hipMalloc(&C->Kh64, (size_t)2 * 36 * n2 * sizeof(double2)) != hipSuccess ||
             hipMalloc(&C->Kh32, (size_t)2 * 18 * n2 * sizeof(float4)) != hipSuccess ||
             hipMalloc(&C->nbr_eo, (size_t)2 * 8 * n2 * sizeof(int)) != hipSuccess ||
-            hipMalloc(&C->Uh16, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess) {
+            hipMalloc(&C->Uh16, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess ||
+            hipMalloc(&C->Uh32s, (size_t)2 * 36 * n2 * sizeof(cx<float>)) != hipSuccess ||
+            hipMalloc(&C->Uh16s, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess) {
             ddwc_destroy(C);
             return fail(DDWC_EHIP, "device allocation of the even-odd fields failed");
         }
-        launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Kh64, C->Kh32, C->nbr_eo);
+        launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Uh32s, C->Kh64, C->Kh32, C->nbr_eo);
         launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32, C->Uh16);
+        launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32s, C->Uh16s);
     }
     double* fpp = nullptr;
     if (ws_t(C, "fp_part", FP_BLOCKS, &fpp) != DDWC_OK) {
@@ -295,7 +300,8 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     if (C->K64) (void)hipFree(C->K64);
     if (C->K32) (void)hipFree(C->K32);
     if (C->nbr) (void)hipFree(C->nbr);
-    for (void* q : {(void*)C->Uh64, (void*)C->Uh32, (void*)C->Kh64, (void*)C->Kh32, (void*)C->nbr_eo, (void*)C->Uh16})
+    for (void* q : {(void*)C->Uh64, (void*)C->Uh32, (void*)C->Kh64, (void*)C->Kh32, (void*)C->nbr_eo, (void*)C->Uh16,
+                    (void*)C->Uh32s, (void*)C->Uh16s})
         if (q) (void)hipFree(q);
     for (auto& a : C->ainv) {
         (void)hipFree(a.a64);
@@ -439,10 +445,12 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
 }
 
 // ------------------------------------------------------------------ even-odd global solver
+// Half-field operator data.  site_major selects the site-major link copies (FP32, FP16) that the
+// RHS-innermost kernels of the global solver read; the block solver and FP64 read entry-major links.
 template <class R>
-static EoFields<R> eo_fields(const ddwc_ctx* C);
+static EoFields<R> eo_fields(const ddwc_ctx* C, bool site_major = false);
 template <>
-EoFields<double> eo_fields<double>(const ddwc_ctx* C) {
+EoFields<double> eo_fields<double>(const ddwc_ctx* C, bool) {
     EoFields<double> F;
     F.n2 = C->g.V / 2;
     for (int p = 0; p < 2; ++p) {
@@ -453,11 +461,11 @@ EoFields<double> eo_fields<double>(const ddwc_ctx* C) {
     return F;
 }
 template <>
-EoFields<float> eo_fields<float>(const ddwc_ctx* C) {
+EoFields<float> eo_fields<float>(const ddwc_ctx* C, bool site_major) {
     EoFields<float> F;
     F.n2 = C->g.V / 2;
     for (int p = 0; p < 2; ++p) {
-        F.U[p] = C->Uh32 + (size_t)p * 36 * F.n2;
+        F.U[p] = (site_major ? C->Uh32s : C->Uh32) + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
         F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
     }
@@ -465,11 +473,11 @@ EoFields<float> eo_fields<float>(const ddwc_ctx* C) {
 }
 
 template <>
-EoFields<H16> eo_fields<H16>(const ddwc_ctx* C) {
+EoFields<H16> eo_fields<H16>(const ddwc_ctx* C, bool site_major) {
     EoFields<H16> F;
     F.n2 = C->g.V / 2;
     for (int p = 0; p < 2; ++p) {
-        F.U[p] = C->Uh16 + (size_t)p * 36 * F.n2;
+        F.U[p] = (site_major ? C->Uh16s : C->Uh16) + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
         F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
     }
@@ -568,7 +576,6 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     const Geom& g = C->g;
     const bool fp64 = std::is_same<S, double>::value, h16 = std::is_same<S, H16>::value;
     const EoFields<double> F64 = eo_fields<double>(C);
-    const EoFields<S> FR = eo_fields<S>(C);
     const unsigned n2 = F64.n2;
     Geom gh = g;  // geometry of the half fields for the vector kernels (only V is used)
     gh.V = (int)n2;
@@ -578,6 +585,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     // (FP16 fields, whose scale plane follows the word planes, always are)
     if (h16 && nrhs > WG) return fail(DDWC_EINVAL, "the FP16 inner solver takes at most 256 RHS");
     const bool ri = h16 || (nrhs > 1 && nrhs <= WG);
+    const EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read site-major links
     const int ntR = vector_tiles(n2, nrhs, ri);
     const double mass4 = 4.0 + mass;
     const double2* A64;

@@ -307,6 +307,22 @@ DDWC_HD void load_link(const cx<L>* __restrict__ U, unsigned V, int mu, unsigned
     }
 }
 
+// Site-major links [n][4][9]: the four forward links of a site are one contiguous record, so the
+// lanes of a site (RHS-innermost kernels) read whole cache lines at once.
+template <bool SITE_MAJOR, class R, class L>
+DDWC_HD void load_link_l(const cx<L>* __restrict__ U, unsigned V, int mu, unsigned s, cx<R> u[9]) {
+    if (!SITE_MAJOR) {
+        load_link(U, V, mu, s, u);
+        return;
+    }
+    const cx<L>* p = U + ((size_t)s * 4 + mu) * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const cx<L> w = p[k];
+        u[k] = mk((R)w.re, (R)w.im);
+    }
+}
+
 // FP16 spinors: words k = 0..2 hold complex 4k .. 4k + 3; the scale plane follows the three
 // word planes of the field (f is the field base, `stride` its plane length).
 DDWC_HD float* scale_plane(hw16* f, unsigned stride) { return (float*)(f + 3 * (size_t)stride); }
@@ -516,8 +532,9 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // (PIPE: the next direction's loads are issued before the current one is computed).
 //
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
-// component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).
-template <class R, int HOPS, bool PIPE, class W, class L>
+// component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
+// entry-major [4][9][n], or site-major [n][4][9] with SITE_MAJOR.
+template <class R, int HOPS, bool PIPE, bool SITE_MAJOR = false, class W, class L>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
                      const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
                      unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
@@ -537,9 +554,9 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 cx<R> q[12], u[9];
                 load_spinor(in, sstride, t * smul + sadd, q);
                 if (d & 1)
-                    load_link(Ub, n, d >> 1, t, u);
+                    load_link_l<SITE_MAJOR>(Ub, n, d >> 1, t, u);
                 else
-                    load_link(Uf, n, d >> 1, s, u);
+                    load_link_l<SITE_MAJOR>(Uf, n, d >> 1, s, u);
                 if (e < 0) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) q[c] = -q[c];
@@ -557,7 +574,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
         {
             const int e = ent[0];
             load_spinor(in, sstride, (e < 0 ? (unsigned)~e : (unsigned)e) * smul + sadd, q);
-            load_link(Uf, n, 0, s, u);
+            load_link_l<SITE_MAJOR>(Uf, n, 0, s, u);
         }
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
@@ -575,9 +592,9 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
                 load_spinor(in, sstride, tn * smul + sadd, qn);
                 if ((d + 1) & 1)
-                    load_link(Ub, n, (d + 1) >> 1, tn, un);
+                    load_link_l<SITE_MAJOR>(Ub, n, (d + 1) >> 1, tn, un);
                 else
-                    load_link(Uf, n, (d + 1) >> 1, s, un);
+                    load_link_l<SITE_MAJOR>(Uf, n, (d + 1) >> 1, s, un);
             }
             if (take) {
                 if (e < 0) {

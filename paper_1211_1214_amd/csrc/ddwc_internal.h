@@ -193,8 +193,10 @@ struct EoFields {
 
 // FP16 copy of n FP32 complex link entries.
 void launch_links_to_half(Exec& e, size_t n, const cx<float>* src, cx<f16>* dst);
+// Half-field links: entry-major Uh64, Uh32 [2][4][9][V/2], and the site-major FP32 copy Uh32s
+// [2][V/2][4][9] read by the RHS-innermost kernels of the global solver.
 void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
-                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo);
+                     cx<double>* Uh64, cx<float>* Uh32, cx<float>* Uh32s, double2* Kh64, float4* Kh32, int* nbr_eo);
 void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
 void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs);
 void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);

@@ -8,7 +8,8 @@ namespace ddwc {
 // ------------------------------------------------------------------ setup
 __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const double2* __restrict__ K64,
                            const int* __restrict__ nbr, cx<double>* __restrict__ Uh64, cx<float>* __restrict__ Uh32,
-                           double2* __restrict__ Kh64, float4* __restrict__ Kh32, int* __restrict__ nbr_eo) {
+                           cx<float>* __restrict__ Uh32s, double2* __restrict__ Kh64, float4* __restrict__ Kh32,
+                           int* __restrict__ nbr_eo) {
     const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= (unsigned)g.V) return;
     const size_t V = g.V, V2 = g.V / 2;
@@ -20,6 +21,7 @@ __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const dou
             const size_t o = (((size_t)p * 4 + mu) * 9 + k) * V2 + i;
             Uh64[o] = u;
             Uh32[o] = mk((float)u.re, (float)u.im);
+            Uh32s[(size_t)p * 36 * V2 + ((size_t)i * 4 + mu) * 9 + k] = mk((float)u.re, (float)u.im);
         }
     double a[72];
     for (int k = 0; k < 36; ++k) {
@@ -35,9 +37,9 @@ __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const dou
 }
 
 void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
-                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo) {
+                     cx<double>* Uh64, cx<float>* Uh32, cx<float>* Uh32s, double2* Kh64, float4* Kh32, int* nbr_eo) {
     Timed t(e, 4, 0);
-    k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Kh64, Kh32, nbr_eo);
+    k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Uh32s, Kh64, Kh32, nbr_eo);
 }
 
 // FP16 copy of the FP32 half-order links (setup).
@@ -103,6 +105,13 @@ void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* h
 }
 
 // ------------------------------------------------------------------ operator kernels
+// The RHS-innermost FP32/FP16 kernels (the global solver) read site-major links; FP64 and the
+// RHS-major kernels read entry-major links (EoFields of eo_fields with site_major set alike).
+template <class S, bool RI>
+constexpr bool site_major_links() {
+    return RI && !std::is_same<S, double>::value;
+}
+
 // Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the
 // RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
@@ -123,7 +132,8 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
     const VView<RI, S> w(n2, nrhs, it.i, it.r);
     cx<R> acc[12], out[12];
     if (alpha != R(0))
-        hop_sum<R, HOPS_ALL, true>(n2, it.i, x + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Up, Uq, nbrp, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride);
     else
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = mk(R(0), R(0));
@@ -165,7 +175,8 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
     if (it.ok) {
         const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
-        hop_sum<R, HOPS_ALL, true>(n2, it.i, t + w.base, Up, Uq, nbrp, acc, 8, RI ? nrhs : 1, RI ? it.r : 0, w.stride);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Up, Uq, nbrp, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride);
         load_spinor(c + w.base, w.stride, w.idx, cc);
         if (USE_A) {
             apply_diag<R>(Kp, n2, it.i, mass4, cc, acc, beta);

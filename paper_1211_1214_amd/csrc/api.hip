@@ -96,6 +96,7 @@ struct ddwc_ctx {
     double links_fp = 0;  // fingerprint of the canonical links (equal links give equal values)
     cx<double>* U64 = nullptr;
     cx<float>* U32 = nullptr;
+    cx<float>* U32s = nullptr;  // site-major FP32 links [V][4][9] (RHS-innermost full Dslash)
     double2* K64 = nullptr;
     float4* K32 = nullptr;
     int* nbr = nullptr;  // neighbour table [8][V]
@@ -236,6 +237,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     size_t n = (size_t)4 * 9 * g.V;
     if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
         hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
+        hipMalloc(&C->U32s, n * sizeof(cx<float>)) != hipSuccess ||
         hipMalloc(&C->K64, (size_t)36 * g.V * sizeof(double2)) != hipSuccess ||
         hipMalloc(&C->K32, (size_t)18 * g.V * sizeof(float4)) != hipSuccess ||
         hipMalloc(&C->nbr, (size_t)8 * g.V * sizeof(int)) != hipSuccess) {
@@ -244,7 +246,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     }
     Exec ex = make_exec(C, stream);
     launch_nbr_build(ex, g, C->nbr);
-    launch_links_import(ex, g, links_dev, C->U64, C->U32);
+    launch_links_import(ex, g, links_dev, C->U64, C->U32, C->U32s);
     launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
     if (g.eo) {
         const size_t n2 = g.V / 2;
@@ -297,6 +299,7 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     C->prof.harvest();
     if (C->U64) (void)hipFree(C->U64);
     if (C->U32) (void)hipFree(C->U32);
+    if (C->U32s) (void)hipFree(C->U32s);
     if (C->K64) (void)hipFree(C->K64);
     if (C->K32) (void)hipFree(C->K32);
     if (C->nbr) (void)hipFree(C->nbr);
@@ -982,6 +985,15 @@ extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void
         launch_dslash<double>(ex, g, C->U64, C->K64, mass4, a, b, nrhs, DDWC_K_DSLASH64,
                               ddwc_dslash_bytes(C, nrhs, DDWC_FP64));
         launch_export<double>(ex, g, b, out, nrhs, MASK_ALL);
+    } else if (nrhs > 1 && nrhs <= WG) {
+        // several RHS: RHS-innermost fields, the RHS of a site share its links and clover
+        float4 *a, *b;
+        CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));
+        CK(ws_t(C, "d_out32", vec_words(C, nrhs, false), &b));
+        launch_import_ri32(ex, g, in, a, nrhs);
+        launch_dslash_ri32(ex, g, C->U32s, C->K32, mass4, a, b, nrhs, DDWC_K_DSLASH32,
+                           ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
+        launch_export_ri32(ex, g, b, out, nrhs);
     } else {
         float4 *a, *b;
         CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));

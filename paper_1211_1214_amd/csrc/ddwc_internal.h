@@ -70,7 +70,14 @@ constexpr int NPART = 4; // doubles per partial-sum slot
 
 inline int tiles_of(int n) { return (n + WG - 1) / WG; }
 
-void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32);
+// Links to the internal layouts: U64, U32 entry-major [4][9][V], U32s site-major [V][4][9].
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32,
+                         cx<float>* U32s);
+// Full-lattice FP32 Dslash on RHS-innermost fields [6][V][nrhs] (canonical FP64 in and out).
+void launch_import_ri32(Exec& e, const Geom& g, const void* canon, float4* out, int nrhs);
+void launch_export_ri32(Exec& e, const Geom& g, const float4* in, void* canon, int nrhs);
+void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float4* K, double mass4, const float4* in,
+                        float4* out, int nrhs, int kclass, double bytes);
 void launch_nbr_build(Exec& e, const Geom& g, int* nbr);
 void launch_clover_build(Exec& e, const Geom& g, const cx<double>* U64, double csw, double2* K64, float4* K32);
 

@@ -19,7 +19,7 @@ namespace ddwc {
 
 // ------------------------------------------------------------------ conversions
 __global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<double>* __restrict__ U64,
-                               cx<float>* __restrict__ U32) {
+                               cx<float>* __restrict__ U32, cx<float>* __restrict__ U32s) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int mu = blockIdx.y;
     if (s >= g.V) return;
@@ -31,13 +31,15 @@ __global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<doubl
         size_t o = ((size_t)mu * 9 + k) * g.V + s;
         U64[o] = mk(w.x, w.y);
         U32[o] = mk((float)w.x, (float)w.y);
+        U32s[((size_t)s * 4 + mu) * 9 + k] = mk((float)w.x, (float)w.y);
     }
 }
 
-void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32) {
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32,
+                         cx<float>* U32s) {
     Timed t(e, 4, 0);
     dim3 grid(tiles_of(g.V), 4);
-    k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32);
+    k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32, U32s);
 }
 
 // Neighbour table [8][V] (setup, once per geometry).
@@ -668,6 +670,68 @@ void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, dou
     Timed t(e, 3, 0);
     int nt = tiles_of(g.V);
     k_dots<<<nt * nrhs, WG, 0, e.stream>>>(g, x, y, part, nrhs, nt);
+}
+
+// ------------------------------------------------------------------ RHS-innermost FP32 full Dslash
+// Fields [6][V][nrhs] float4 (vec_items.h), site-major FP32 links [V][4][9]: the lanes of a site
+// (its RHS) share one link record and one clover load, as in the global solver's kernels.
+__global__ __launch_bounds__(WG) void k_import_ri32(Geom g, const double2* __restrict__ can, float4* __restrict__ out,
+                                                    int nrhs, int ntiles) {
+    const VItem it = vitem<true>((unsigned)g.V, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
+    const double2* src = can + ((size_t)it.r * g.V + canonical_index(g, decode(g, (int)it.i))) * 12;
+    cx<float> q[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double2 v = src[c];
+        q[c] = mk((float)v.x, (float)v.y);
+    }
+    store_spinor(out, w.stride, w.idx, q);
+}
+
+__global__ __launch_bounds__(WG) void k_export_ri32(Geom g, const float4* __restrict__ in, double2* __restrict__ can,
+                                                    int nrhs, int ntiles) {
+    const VItem it = vitem<true>((unsigned)g.V, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
+    cx<float> q[12];
+    load_spinor(in, w.stride, w.idx, q);
+    double2* dst = can + ((size_t)it.r * g.V + canonical_index(g, decode(g, (int)it.i))) * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[c] = make_double2((double)q[c].re, (double)q[c].im);
+}
+
+__global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __restrict__ Us,
+                                                    const float4* __restrict__ K, float mass4,
+                                                    const float4* __restrict__ in, float4* __restrict__ out,
+                                                    const int* __restrict__ nbr, int nrhs, int ntiles) {
+    const VItem it = vitem<true>((unsigned)g.V, nrhs, ntiles);
+    if (!it.ok) return;
+    const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
+    cx<float> acc[12], c[12];
+    hop_sum<float, HOPS_ALL, true, true>((unsigned)g.V, it.i, in, Us, Us, nbr, acc, 8, (unsigned)nrhs,
+                                         (unsigned)it.r, w.stride);
+    load_spinor(in, w.stride, w.idx, c);
+    apply_diag<float>(K, (unsigned)g.V, it.i, mass4, c, acc, -0.5f);
+    store_spinor(out, w.stride, w.idx, acc);
+}
+
+void launch_import_ri32(Exec& e, const Geom& g, const void* canon, float4* out, int nrhs) {
+    Timed t(e, 4, 0);
+    const int nt = tiles_of(g.V * nrhs);
+    k_import_ri32<<<nt, WG, 0, e.stream>>>(g, (const double2*)canon, out, nrhs, nt);
+}
+void launch_export_ri32(Exec& e, const Geom& g, const float4* in, void* canon, int nrhs) {
+    Timed t(e, 4, 0);
+    const int nt = tiles_of(g.V * nrhs);
+    k_export_ri32<<<nt, WG, 0, e.stream>>>(g, in, (double2*)canon, nrhs, nt);
+}
+void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float4* K, double mass4, const float4* in,
+                        float4* out, int nrhs, int kclass, double bytes) {
+    Timed t(e, kclass, bytes);
+    const int nt = tiles_of(g.V * nrhs);
+    k_dslash_ri32<<<nt, WG, 0, e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs, nt);
 }
 
 // ------------------------------------------------------------------ instantiations

@@ -74,11 +74,12 @@ def test_dslash_fp64(dev, name):
 def test_dslash_fp32(dev, name):
     lat, blk, U, ctx, S = setup(name, dev)
     say("dslash fp32", name)
-    psi = inputs.make_spinor(lat, 12, nrhs=2)
-    got = ctx.dslash_apply(0.121, T(psi, dev), prec=dd.MIXED32).cpu().numpy()
     D = S.D(dirac.mass(0.121))
-    want = np.stack([dirac.apply(D, p) for p in psi])
-    assert rel(got, want) < 2e-6
+    for nrhs in (1, 2, 5):  # one RHS: RHS-major fields; several: RHS-innermost fields
+        psi = inputs.make_spinor(lat, 12, nrhs=nrhs)
+        got = ctx.dslash_apply(0.121, T(psi, dev), prec=dd.MIXED32).cpu().numpy()
+        want = np.stack([dirac.apply(D, p) for p in psi])
+        assert rel(got, want) < 2e-6, nrhs
 
 
 def test_dslash_periodic_and_wilson(dev):

@@ -1,0 +1,110 @@
+"""Degenerate and boundary inputs through the C ABI.
+
+  * zero right-hand sides and zero noise: solutions exactly zero, exponents exactly zero,
+    log W = 0, mixed with non-zero RHS in the same batch;
+  * kappa1 = kappa2: every exponent is exactly zero (dm = 0 in the difference form);
+  * the largest RHS batch of the RHS-innermost kernels (256) and one beyond it (RHS-major FP32
+    fields; the FP16 solver refuses it);
+  * an empty batch is refused.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1211_1214_amd as dd  # noqa: E402
+from oracle import dirac  # noqa: E402
+from oracle.schwarz import Schwarz  # noqa: E402
+from paper_1211_1214_amd import binding, inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+LAT, BLK = (4, 4, 4, 4), (2, 2, 2, 2)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    U = inputs.make_links(LAT, 0.3, 91)
+    ctx = dd.Context(torch.from_numpy(U).to(dev), LAT, BLK, -1, 1.0)
+    yield dev, U, ctx
+    ctx.close()
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
+def test_zero_rhs(env, prec):
+    dev, U, ctx = env
+    say("zero rhs", prec)
+    b = inputs.make_spinor(LAT, 92, nrhs=3)
+    b[1] = 0
+    x, st = ctx.solve(0.121, T(b, dev), tol=1e-12, prec=prec)
+    x = x.cpu().numpy()
+    assert np.all(x[1] == 0) and np.all(np.isfinite(x))
+    S = Schwarz(U, LAT, BLK, 1.0)
+    want = S.inv_full(dirac.mass(0.121))(b[0].reshape(-1)).reshape(b[0].shape)
+    assert np.abs(x[0] - want).max() <= 1e-9 * np.abs(want).max()
+    for colour in (0, 1):
+        xb, _ = ctx.block_solve(colour, 0.121, T(np.zeros_like(b), dev), tol=1e-12, prec=prec)
+        assert np.all(xb.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("op", [dd.OP_FULL, dd.OP_SCHUR])
+def test_zero_noise_and_equal_kappa(env, op):
+    dev, U, ctx = env
+    say("zero noise / equal kappa", op)
+    eta = inputs.make_noise_batch(LAT, 93, 2, 3)
+    eta[0, 1] = 0
+    r = ctx.det_ratio_estimate(0.12, 0.121, T(eta, dev), op=op, tol=1e-12, prec=dd.MIXED32)
+    assert r["x"][0, 1] == 0 and np.all(np.isfinite(r["x"]))
+    eta0 = np.zeros_like(eta)
+    r = ctx.det_ratio_estimate(0.12, 0.121, T(eta0, dev), op=op, tol=1e-12, prec=dd.MIXED32)
+    assert np.all(r["x"] == 0) and r["log_w_gl"] == 0.0 and np.all(r["step_var"] == 0)
+    r = ctx.det_ratio_estimate(0.121, 0.121, T(eta, dev), op=op, tol=1e-12, prec=dd.MIXED32)
+    assert np.all(r["x"] == 0) and r["log_w_gl"] == 0.0
+
+
+@pytest.mark.parametrize("nrhs", [256, 257])
+def test_largest_batches(env, nrhs):
+    dev, U, ctx = env
+    say("batch", nrhs)
+    b = inputs.make_spinor(LAT, 94, nrhs=nrhs)
+    S = Schwarz(U, LAT, BLK, 1.0)
+    inv = S.inv_full(dirac.mass(0.121))
+    want = np.stack([inv(b[j].reshape(-1)).reshape(b[j].shape) for j in (0, nrhs - 1)])
+    x, st = ctx.solve(0.121, T(b, dev), tol=1e-12, prec=dd.MIXED32)
+    got = x.cpu().numpy()[[0, nrhs - 1]]
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+    D = S.D(dirac.mass(0.121))
+    y = ctx.dslash_apply(0.121, T(b, dev), prec=dd.MIXED32).cpu().numpy()
+    for j in (0, nrhs // 2, nrhs - 1):
+        w = dirac.apply(D, b[j])
+        assert np.abs(y[j] - w).max() <= 2e-6 * np.abs(w).max()
+    if nrhs > 256:
+        with pytest.raises(dd.DDWCError) as e:
+            ctx.solve(0.121, T(b, dev), tol=1e-12, prec=dd.MIXED16)
+        assert e.value.code == -1
+    else:
+        x16, _ = ctx.solve(0.121, T(b, dev), tol=1e-12, prec=dd.MIXED16)
+        assert np.abs(x16.cpu().numpy()[[0, nrhs - 1]] - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_empty_batch(env):
+    dev, U, ctx = env
+    e = torch.zeros((0, 4, 4, 3), dtype=torch.complex128, device=dev)
+    for call in (lambda: ctx.dslash_apply(0.12, e), lambda: ctx.solve(0.121, e)):
+        with pytest.raises((dd.DDWCError, ValueError)):
+            call()
+    status = binding.lib().ddwc_solve(ctx._h, 0.121, e.data_ptr(), e.data_ptr(), 0, 1e-12, 10, dd.FP64, None, None)
+    assert status == binding.EINVAL

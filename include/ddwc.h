@@ -232,7 +232,7 @@ int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
 /*
  * Autotuner: times the schedule options on this lattice with nrhs reproducible right-hand
  * sides at the given kappa and precision (a block sweep of one colour for each workgroup
- * size, without and with the LDS reservation that leaves room for two block-solver
+ * size, without and with the LDS reservations that leave room for 2, 4 or 8 block-solver
  * workgroups per CU; a global solve for each poll interval with and without graphs,
  * tolerance 1e-8) and
  * sets the fastest.  *seconds_host (may be null) receives the tuning time.  Synchronises.

@@ -1810,16 +1810,16 @@ extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, doub
         }
         return best;
     };
-    // block solver: workgroup size x residency (no LDS reservation, or one that leaves room for two
-    // persistent workgroups per CU)
+    // block solver: workgroup size x residency (no LDS reservation, or one that leaves room for
+    // 2, 4 or 8 persistent workgroups per CU)
     int maxlds = 0;
     HC(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device));
-    const int two_per_cu = std::max(0, (maxlds / 2 - 2048) >> 10);
+    auto per_cu = [&](int k) { return std::max(0, (maxlds / k - 2048) >> 10); };
     const int saved_threads = C->opt_blk_threads, saved_lds = C->opt_blk_lds;
     double best = 1e300;
     int pick = saved_threads, pick_lds = saved_lds;
-    for (int T : {0, 128, 192, 256})
-        for (int L : {0, two_per_cu}) {
+    for (int T : {0, 64, 128, 192, 256})
+        for (int L : {0, per_cu(2), per_cu(4), per_cu(8)}) {
             C->opt_blk_threads = T;
             C->opt_blk_lds = L;
             const double t = timed([&]() {

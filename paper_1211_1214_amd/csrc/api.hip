@@ -1107,7 +1107,6 @@ static int sap_gcr(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doubl
         return DDWC_OK;
     };
     BlockInfo bi;
-    int sweeps = 0;
     // out = M_sap eta
     auto sap = [&](const double2* eta, double2* out) -> int {
         HC(hipMemsetAsync(out, 0, sizeof(double2) * nw, ex.stream));
@@ -1116,7 +1115,6 @@ static int sap_gcr(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doubl
             for (int colour = 0; colour < 2; ++colour) {
                 const int st = block_internal(C, ex, colour, mass, rho, dl, nrhs, btol, 1000, prec, &bi);
                 if (st != DDWC_OK && st != DDWC_ENOCONV) return st;
-                ++sweeps;
                 launch_axpby(ex, g, 1.0, out, 1.0, dl, out, nrhs, MASK_ALL);
                 launch_residual<double>(ex, g, C->U64, C->K64, mass4, out, eta, rho, part, nrhs, DDWC_K_DSLASH64,
                                         dbytes);
@@ -1208,7 +1206,6 @@ static int sap_gcr(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doubl
         info->inner += total;
         info->relres = fmax(info->relres, worst);
     }
-    (void)sweeps;
     if (!converged) return fail(DDWC_ENOCONV, "global solve did not reach its tolerance within maxit");
     return DDWC_OK;
 }

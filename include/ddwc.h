@@ -207,7 +207,8 @@ int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_ho
  *                          profiling); 0: launches them one by one.  Default 1.
  *   DDWC_OPT_POLL          iterations between the host's convergence checks, [1, 64]; default 2.
  *   DDWC_OPT_BLOCK_THREADS workgroup size of the Schwarz block kernels: 0 (enough waves for one
- *                          block parity, at most 256) or a multiple of 64 in [64, 256].
+ *                          block parity, at most 768 for the FP32/FP16 inner solver and 256 for
+ *                          the FP64 kernels) or a multiple of 64 in [64, 768] (capped alike).
  *   DDWC_OPT_SOLVER        global solver: 0 even-odd BiCGStab (default; lexicographic BiCGStab when
  *                          a block extent is odd), 1 GCR (8 directions per cycle, restarted with
  *                          the exact FP64 residual) preconditioned by the Schwarz alternating
@@ -232,7 +233,7 @@ int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
 /*
  * Autotuner: times the schedule options on this lattice with nrhs reproducible right-hand
  * sides at the given kappa and precision (a block sweep of one colour for each workgroup
- * size, without and with the LDS reservations that leave room for 2, 4 or 8 block-solver
+ * size, without and with the LDS reservations that leave room for 2 or 4 block-solver
  * workgroups per CU; a global solve for each poll interval with and without graphs,
  * tolerance 1e-8) and
  * sets the fastest.  *seconds_host (may be null) receives the tuning time.  Synchronises.

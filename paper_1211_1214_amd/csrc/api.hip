@@ -1743,8 +1743,8 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
             C->opt_poll = value;
             break;
         case DDWC_OPT_BLOCK_THREADS:
-            if (value != 0 && (value < 64 || value > 256 || value % 64 != 0))
-                return fail(DDWC_EINVAL, "block threads must be 0 or a multiple of 64 in [64, 256]");
+            if (value != 0 && (value < 64 || value > 768 || value % 64 != 0))
+                return fail(DDWC_EINVAL, "block threads must be 0 or a multiple of 64 in [64, 768]");
             C->opt_blk_threads = value;
             break;
         case DDWC_OPT_SOLVER:
@@ -1808,15 +1808,15 @@ extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, doub
         return best;
     };
     // block solver: workgroup size x residency (no LDS reservation, or one that leaves room for
-    // 2, 4 or 8 persistent workgroups per CU)
+    // 2 or 4 persistent workgroups per CU)
     int maxlds = 0;
     HC(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device));
     auto per_cu = [&](int k) { return std::max(0, (maxlds / k - 2048) >> 10); };
     const int saved_threads = C->opt_blk_threads, saved_lds = C->opt_blk_lds;
     double best = 1e300;
     int pick = saved_threads, pick_lds = saved_lds;
-    for (int T : {0, 64, 128, 192, 256})
-        for (int L : {0, per_cu(2), per_cu(4), per_cu(8)}) {
+    for (int T : {0, 128, 256, 512})
+        for (int L : {0, per_cu(2), per_cu(4)}) {
             C->opt_blk_threads = T;
             C->opt_blk_lds = L;
             const double t = timed([&]() {

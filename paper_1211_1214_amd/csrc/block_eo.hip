@@ -18,14 +18,23 @@
 
 namespace ddwc {
 
-constexpr int BE_MAX_THREADS = 256;
+constexpr int BE_MAX_THREADS = 256;  // FP64 kernels: prep, resid, recon and the FP64 inner solver
+constexpr int BE_INNER_MAX = 768;    // FP32/FP16 inner solver: up to 12 waves (3 per SIMD at its VGPR use)
 
-// Workgroup size of the block kernels: `req` (a multiple of 64 up to BE_MAX_THREADS, set by the
-// autotuner) or, by default, enough waves for one block parity up to BE_MAX_THREADS.
-int block_eo_threads(const Geom& g, int req) {
-    if (req > 0) return req > BE_MAX_THREADS ? BE_MAX_THREADS : ((req + 63) / 64) * 64;
-    int t = ((g.hvb + 63) / 64) * 64;
-    return t < BE_MAX_THREADS ? t : BE_MAX_THREADS;
+// Workgroup size of a block kernel of at most `cap` threads: `req` (a multiple of 64, from the
+// schedule options) or, by default, enough waves for one block parity.
+static int block_threads_for(const Geom& g, int req, int cap) {
+    const int t = req > 0 ? ((req + 63) / 64) * 64 : ((g.hvb + 63) / 64) * 64;
+    return t < cap ? t : cap;
+}
+int block_eo_threads(const Geom& g, int req) { return block_threads_for(g, req, BE_MAX_THREADS); }
+
+// The persistent inner solver in FP32/FP16 storage runs up to BE_INNER_MAX threads: a 6^4 block
+// parity (648 sites) is then one pass of 11 waves, and one such workgroup per CU keeps the
+// block vectors in flight small enough for the last-level cache.
+template <class S>
+constexpr int be_inner_max() {
+    return std::is_same<S, double>::value ? BE_MAX_THREADS : BE_INNER_MAX;
 }
 
 struct BlkIdx {
@@ -255,7 +264,7 @@ __device__ __forceinline__ void apply_Mk(const Geom& g, const EoFields<S>& F, co
 }
 
 template <class S>
-__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_inner(Geom g, EoFields<S> F,
+__global__ __launch_bounds__(be_inner_max<S>()) void k_blk_inner(Geom g, EoFields<S> F,
                                                              const typename Traits<S>::kword* __restrict__ Ainv,
                                                              const double2* __restrict__ re, double2* __restrict__ xe,
                                                              BlkInner<S> w, const double* __restrict__ bb,
@@ -418,7 +427,8 @@ void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typena
     const double floor_eps = std::is_same<S, double>::value ? 0.0 : std::is_same<S, H16>::value ? 1e-3 : 2e-6;
     // e.blk_lds KiB of dynamic LDS (unused by the kernel) caps the workgroups resident per CU, and so
     // the slabs in flight, which then stay in the last-level cache
-    k_blk_inner<S><<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), (size_t)e.blk_lds << 10, e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
+    k_blk_inner<S><<<g.NBc * nrhs, block_threads_for(g, e.blk_threads, be_inner_max<S>()), (size_t)e.blk_lds << 10,
+                     e.stream>>>(g, F, Ainv, re, xe, bw, bb, rr, mass4, tol,
                                                                        floor_eps, maxit, iters, colour, nrhs);
 }
 size_t blk_slab_bytes(int prec, unsigned n2) {

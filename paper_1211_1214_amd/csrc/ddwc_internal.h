@@ -222,7 +222,6 @@ void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, b
                        int nrhs, int kclass, double bytes);
 
 // ------------------------------------------------------------------ even-odd block solver (block_eo.hip)
-int block_eo_threads(const Geom& g);
 void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                      double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs);
 void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,

@@ -61,7 +61,7 @@ def test_graph_replay_matches_eager(env, prec):
     assert np.array_equal(x2.cpu().numpy(), x0)
 
 
-@pytest.mark.parametrize("threads", [64, 128, 192, 256])
+@pytest.mark.parametrize("threads", [64, 128, 192, 256, 512, 768])
 def test_block_threads_option(env, threads):
     dev, U, ctx, S = env
     say("block threads", threads)
@@ -107,7 +107,7 @@ def test_poll_option(env, poll):
 def test_option_validation(env):
     dev, U, ctx, S = env
     for opt, bad in ((binding.OPT_GRAPHS, 2), (binding.OPT_POLL, 0), (binding.OPT_POLL, 65),
-                     (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 512), (binding.OPT_SOLVER, 2),
+                     (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 832), (binding.OPT_SOLVER, 2),
                      (binding.OPT_BLOCK_LDS, -1), (binding.OPT_BLOCK_LDS, 4096),
                      (7, 1)):
         with pytest.raises(dd.DDWCError) as e:
@@ -122,7 +122,7 @@ def test_autotune(env):
     dev, U, ctx, S = env
     say("autotune")
     r = ctx.autotune(0.121, 4, dd.MIXED32)
-    assert r["graphs"] in (0, 1) and r["poll"] in (2, 4, 8) and r["block_threads"] in (0, 64, 128, 192, 256)
+    assert r["graphs"] in (0, 1) and r["poll"] in (2, 4, 8) and r["block_threads"] in (0, 128, 256, 512)
     assert 0 <= r["block_lds"] < 160
     assert r["seconds"] > 0
     b = inputs.make_spinor(LAT, 85, nrhs=4)

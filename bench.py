@@ -24,10 +24,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 METRIC = "Dslash GB/s (% HBM peak); det-ratio estimates/s, mixed vs FP64 at 1e-8"
-WORKLOADS = {
-    3: "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205, "
+DESCRIPTIONS = {
+    "48x24^3": "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205, "
        "N_hit=12 as one multi-RHS batch, FP32 block/inner solves + FP64 defect correction",
-    4: "Schur det-ratio estimate, 64x32^3, 8^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205 in "
+    "64x32^3": "Schur det-ratio estimate, 64x32^3, 8^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205 in "
        "N=4 mass-interpolation steps, 24 RHS as one multi-RHS batch, FP32 block/inner solves + FP64 defect "
        "correction",
 }
@@ -82,21 +82,21 @@ def main():
 
     if args.nested:
         return nested_bench(args, dd, inputs, np, torch)
-    cid = 3 if args.workload == "48x24" else 4
-    cfg = inputs.CONFIGS[cid]
+    wname = "48x24^3" if args.workload == "48x24" else "64x32^3"
+    cfg = inputs.WORKLOADS[wname]
     lat, blk, nhit, nint = cfg["lat"], cfg["blk"], cfg["n_hit"], cfg["n_interp"]
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     dev = torch.device("cuda:0")
     t = time.time()
-    U = inputs.make_links(lat, cfg["eps"], cid)
-    eta = inputs.make_noise_batch(lat, cid, nint, nhit)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
+    eta = inputs.make_noise_batch(lat, cfg["seed"], nint, nhit)
     log(f"inputs generated in {time.time() - t:.1f}s")
     Ud = torch.from_numpy(U).to(dev)
     etad = torch.from_numpy(eta).to(dev)
     ctx = dd.Context(Ud, lat, blk, -1, cfg["csw"])
     torch.cuda.synchronize()
 
-    inner = args.inner or ("fp32" if cid == 3 else "fp16")
+    inner = args.inner or ("fp32" if wname == "48x24^3" else "fp16")
     prec = dd.MIXED16 if inner == "fp16" else dd.MIXED32
     if args.solver == "sap-gcr":
         ctx.set_option(dd.binding.OPT_SOLVER, 1)
@@ -180,7 +180,7 @@ def main():
                 "bytes_per_launch": per_launch_bytes}
 
     cpu = None
-    if cid == 3 and not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
+    if wname == "48x24^3" and not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
         cpu = cpu_baseline(U, eta[0, 0], cfg, golden, args.cpu_cap)
 
     total_ms = sum(p["ms"] for p in prof.values())
@@ -190,7 +190,7 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 inner / f64 outer" if inner == "fp32" else "f16 storage, f32 arithmetic inner / f64 outer",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[cid] + ("" if inner == "fp32" else
+        "config": {"workload": DESCRIPTIONS[wname] + ("" if inner == "fp32" else
                                                  "; global inner solver in FP16 storage (per-site scales, FP16 links)"),
                    "lattice": list(lat), "blocks": list(blk), "n_interp": nint, "n_hit": nhit, "tol": args.tol,
                    "inner": inner, "solver": args.solver},
@@ -235,7 +235,7 @@ def nested_bench(args, dd, inputs, np, torch):
     """Nested DD on the 64x32^3 workload: the Schur factor of the 8^4 blocks of each colour over
     4^4 inner blocks (ddwc_det_ratio_nested), the first interpolation step with 24 RHS per
     colour, FP16 storage in the inner solves.  One timed step = both colours."""
-    cfg = inputs.CONFIGS[4]
+    cfg = inputs.WORKLOADS["64x32^3"]
     lat, blk, nhit = cfg["lat"], cfg["blk"], cfg["n_hit"]
     inner = (4, 4, 4, 4)
     m1, m2 = 1 / (2 * cfg["kappa1"]) - 4, 1 / (2 * cfg["kappa2"]) - 4
@@ -243,7 +243,7 @@ def nested_bench(args, dd, inputs, np, torch):
     prec = dd.MIXED16 if (args.inner or "fp16") == "fp16" else dd.MIXED32
     dev = torch.device("cuda:0")
     t = time.time()
-    Ud = torch.from_numpy(inputs.make_links(lat, cfg["eps"], 4)).to(dev)
+    Ud = torch.from_numpy(inputs.make_links(lat, cfg["eps"], cfg["seed"])).to(dev)
     O = dd.Context(Ud, lat, blk, -1, cfg["csw"])
     I = dd.Context(Ud, lat, inner, -1, cfg["csw"])
     del Ud

@@ -107,17 +107,18 @@ def make_gauge_transform(lat, seed: int) -> np.ndarray:
     return (Q * np.exp(1j * w)[:, None, :]) @ Q.conj().swapaxes(-1, -2)
 
 
-# The benchmark and test configurations: lattice (T, L1, L2, L3), Schwarz block,
-# kappa_1 -> kappa_2, interpolation steps N, noise vectors N_hit.
-CONFIGS = {
-    1: dict(name="4x4^3 blocks 2^4", lat=(4, 4, 4, 4), blk=(2, 2, 2, 2), kappa1=0.1200,
-            kappa2=0.1210, n_interp=1, n_hit=8, csw=1.0, eps=0.3),
-    2: dict(name="8x8^3 blocks 4^4", lat=(8, 8, 8, 8), blk=(4, 4, 4, 4), kappa1=0.1200,
-            kappa2=0.1210, n_interp=1, n_hit=16, csw=1.0, eps=0.3),
-    3: dict(name="48x24^3 blocks 6^4", lat=(48, 24, 24, 24), blk=(6, 6, 6, 6), kappa1=0.1200,
-            kappa2=0.1205, n_interp=1, n_hit=12, csw=1.0, eps=0.3),
-    4: dict(name="64x32^3 blocks 8^4", lat=(64, 32, 32, 32), blk=(8, 8, 8, 8), kappa1=0.1200,
-            kappa2=0.1205, n_interp=4, n_hit=24, csw=1.0, eps=0.3),
-    5: dict(name="32x16^3 blocks 4^4", lat=(32, 16, 16, 16), blk=(4, 4, 4, 4), kappa1=0.1200,
-            kappa2=0.1205, n_interp=1, n_hit=8, csw=1.0, eps=0.3),
+# The benchmark and test workloads, by lattice size: lattice (T, L1, L2, L3), Schwarz block,
+# kappa_1 -> kappa_2, interpolation steps N, noise vectors N_hit, and the seed that selects
+# their link and noise streams (make_links(lat, eps, seed), make_noise(lat, seed, i, j)).
+WORKLOADS = {
+    "4x4^3": dict(seed=1, name="4x4^3 blocks 2^4", lat=(4, 4, 4, 4), blk=(2, 2, 2, 2), kappa1=0.1200,
+                  kappa2=0.1210, n_interp=1, n_hit=8, csw=1.0, eps=0.3),
+    "8x8^3": dict(seed=2, name="8x8^3 blocks 4^4", lat=(8, 8, 8, 8), blk=(4, 4, 4, 4), kappa1=0.1200,
+                  kappa2=0.1210, n_interp=1, n_hit=16, csw=1.0, eps=0.3),
+    "48x24^3": dict(seed=3, name="48x24^3 blocks 6^4", lat=(48, 24, 24, 24), blk=(6, 6, 6, 6), kappa1=0.1200,
+                    kappa2=0.1205, n_interp=1, n_hit=12, csw=1.0, eps=0.3),
+    "64x32^3": dict(seed=4, name="64x32^3 blocks 8^4", lat=(64, 32, 32, 32), blk=(8, 8, 8, 8), kappa1=0.1200,
+                    kappa2=0.1205, n_interp=4, n_hit=24, csw=1.0, eps=0.3),
+    "32x16^3": dict(seed=5, name="32x16^3 blocks 4^4", lat=(32, 16, 16, 16), blk=(4, 4, 4, 4), kappa1=0.1200,
+                    kappa2=0.1205, n_interp=1, n_hit=8, csw=1.0, eps=0.3),
 }

@@ -23,16 +23,16 @@ from paper_1211_1214_amd import inputs  # noqa: E402
 
 
 def main(n_schur=2):
-    cfg = inputs.CONFIGS[3]
+    cfg = inputs.WORKLOADS["48x24^3"]
     lat, blk = cfg["lat"], cfg["blk"]
-    U = inputs.make_links(lat, cfg["eps"], 3)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
     R = cref.CRef(U, lat, blk, cfg["csw"], -1)
     m1, m2 = dirac.mass(cfg["kappa1"]), dirac.mass(cfg["kappa2"])
     out = {"workload": "48x24^3, blocks 6^4, eps 0.3 links seed [1211,3], c_sw 1, antiperiodic time, "
                        "kappa 0.1200->0.1205, noise seed [1214,3,0,j]",
            "tol": 1e-13, "x_schur": {}, "x_full": {}, "threads": cref.CRef.threads()}
     for j in range(n_schur):
-        eta = inputs.make_noise(lat, 3, 0, j)
+        eta = inputs.make_noise(lat, cfg["seed"], 0, j)
         t0 = time.time()
         x, iters, secs = R.exponent_recorded("schur", "diff", m1, m2, eta, 1e-13)
         out["x_schur"][str(j)] = x
@@ -41,7 +41,7 @@ def main(n_schur=2):
             out["schur_solve_seconds"] = secs
             out["schur_seconds"] = time.time() - t0
         print("schur", j, x, iters, time.time() - t0, flush=True)
-    eta = inputs.make_noise(lat, 3, 0, 0)
+    eta = inputs.make_noise(lat, cfg["seed"], 0, 0)
     x, iters, secs = R.exponent_recorded("full", "diff", m1, m2, eta, 1e-13)
     out["x_full"]["0"] = x
     out["full_solve_iterations"] = iters

@@ -22,9 +22,9 @@ from paper_1211_1214_amd import inputs  # noqa: E402
 
 
 def main(n_first=1):
-    cfg = inputs.CONFIGS[4]
+    cfg = inputs.WORKLOADS["64x32^3"]
     lat, blk, n = cfg["lat"], cfg["blk"], cfg["n_interp"]
-    U = inputs.make_links(lat, cfg["eps"], 4)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
     R = cref.CRef(U, lat, blk, cfg["csw"], -1)
     ms = estimator.interpolation_masses(dirac.mass(cfg["kappa1"]), dirac.mass(cfg["kappa2"]), n)
     out = {"workload": "64x32^3, blocks 8^4, eps 0.3 links seed [1211,4], c_sw 1, antiperiodic time, "
@@ -32,7 +32,7 @@ def main(n_first=1):
            "tol": 1e-13, "x_schur": {}, "threads": cref.CRef.threads(), "seconds": {}}
     todo = [(0, j) for j in range(n_first)] + [(n - 1, 0)]
     for i, j in todo:
-        eta = inputs.make_noise(lat, 4, i, j)
+        eta = inputs.make_noise(lat, cfg["seed"], i, j)
         t0 = time.time()
         x = R.exponent("schur", "diff", ms[i], ms[i + 1], eta, 1e-13)
         out["x_schur"][f"{i},{j}"] = x

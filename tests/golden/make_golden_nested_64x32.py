@@ -26,9 +26,9 @@ INNER = (4, 4, 4, 4)
 
 
 def main(n_first=1):
-    cfg = inputs.CONFIGS[4]
+    cfg = inputs.WORKLOADS["64x32^3"]
     lat, blk, n = cfg["lat"], cfg["blk"], cfg["n_interp"]
-    U = inputs.make_links(lat, cfg["eps"], 4)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
     ms = estimator.interpolation_masses(dirac.mass(cfg["kappa1"]), dirac.mass(cfg["kappa2"]), n)
     out = {"workload": "64x32^3, outer blocks 8^4, inner blocks 4^4, eps 0.3 links seed [1211,4], c_sw 1, "
                        "antiperiodic time, kappa 0.1200->0.1205 in 4 steps linear in m, "

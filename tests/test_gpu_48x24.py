@@ -34,9 +34,9 @@ def say(*a):
 def lat48():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    cfg = inputs.CONFIGS[3]
+    cfg = inputs.WORKLOADS["48x24^3"]
     say("48x24: generating inputs")
-    U = inputs.make_links(cfg["lat"], cfg["eps"], 3)
+    U = inputs.make_links(cfg["lat"], cfg["eps"], cfg["seed"])
     dev = torch.device("cuda:0")
     ctx = dd.Context(torch.from_numpy(U).to(dev), cfg["lat"], cfg["blk"], -1, cfg["csw"])
     say("48x24: building the C oracle field")
@@ -69,7 +69,7 @@ def test_48x24_solve_residuals(lat48):
     cfg, U, dev, ctx, R = lat48
     lat = cfg["lat"]
     m = dirac.mass(cfg["kappa2"])
-    b = inputs.make_noise_batch(lat, 3, 1, 2)[0]
+    b = inputs.make_noise_batch(lat, cfg["seed"], 1, 2)[0]
     say("48x24 global solve, mixed")
     x, st = ctx.solve(cfg["kappa2"], torch.from_numpy(b).to(dev), tol=TOL, prec=dd.MIXED32)
     x = x.cpu().numpy()
@@ -95,7 +95,7 @@ def test_48x24_exponents_against_oracle(lat48):
     cfg, U, dev, ctx, R = lat48
     gold = json.load(open(GOLDEN))
     lat, nhit = cfg["lat"], cfg["n_hit"]
-    eta = inputs.make_noise_batch(lat, 3, 1, nhit)
+    eta = inputs.make_noise_batch(lat, cfg["seed"], 1, nhit)
     etad = torch.from_numpy(eta).to(dev)
     say("48x24 estimate, mixed, 12 RHS")
     res = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad, op=dd.OP_SCHUR, tol=TOL, prec=dd.MIXED32)

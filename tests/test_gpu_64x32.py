@@ -32,11 +32,11 @@ def say(*a):
 def test_64x32_estimate():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    cfg = inputs.CONFIGS[4]
+    cfg = inputs.WORKLOADS["64x32^3"]
     lat, blk = cfg["lat"], cfg["blk"]
     say("64x32: generating inputs")
-    U = inputs.make_links(lat, cfg["eps"], 4)
-    eta = inputs.make_noise_batch(lat, 4, cfg["n_interp"], cfg["n_hit"])
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
+    eta = inputs.make_noise_batch(lat, cfg["seed"], cfg["n_interp"], cfg["n_hit"])
     dev = torch.device("cuda:0")
     ctx = dd.Context(torch.from_numpy(U).to(dev), lat, blk, -1, cfg["csw"])
     etad = torch.from_numpy(eta).to(dev)
@@ -77,14 +77,14 @@ def test_64x32_nested():
     tests/golden/make_golden_nested_64x32.py, and the two precisions against each other."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    cfg = inputs.CONFIGS[4]
+    cfg = inputs.WORKLOADS["64x32^3"]
     lat, blk = cfg["lat"], cfg["blk"]
     m1 = 1 / (2 * cfg["kappa1"]) - 4
     m2 = 1 / (2 * cfg["kappa2"]) - 4
     k_step = 1 / (2 * (m1 + (m2 - m1) / cfg["n_interp"] + 4))   # kappa of m_1
     gold = json.load(open(GOLDEN_NESTED))
     say("64x32 nested: inputs and contexts (8^4 outer, 4^4 inner)")
-    U = inputs.make_links(lat, cfg["eps"], 4)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
     dev = torch.device("cuda:0")
     Ud = torch.from_numpy(U).to(dev)
     del U

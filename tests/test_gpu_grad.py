@@ -129,11 +129,11 @@ def test_autograd_matches_abi(dev):
 def test_c5_gradient_vs_finite_differences(dev):
     """32x16^3, 4^4 blocks, N_hit = 8, kappa 0.1200 -> 0.1205: d log W_gl / d kappa2 and along
     one random link direction, against extrapolated central differences of the GPU estimate."""
-    cfg = inputs.CONFIGS[5]
+    cfg = inputs.WORKLOADS["32x16^3"]
     lat, blk = cfg["lat"], cfg["blk"]
     say("c5: inputs")
-    U = inputs.make_links(lat, cfg["eps"], 5)
-    eta = T(inputs.make_noise_batch(lat, 5, cfg["n_interp"], cfg["n_hit"]), dev)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
+    eta = T(inputs.make_noise_batch(lat, cfg["seed"], cfg["n_interp"], cfg["n_hit"]), dev)
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     dirU = np.random.default_rng(55).standard_normal(U.shape) * (1 + 1j) / np.sqrt(2)
 

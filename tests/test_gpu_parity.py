@@ -44,11 +44,11 @@ def dev():
 _cache = {}
 
 
-def setup(name, dev, cfg=1):
-    key = (name, cfg)
+def setup(name, dev, seed=1):
+    key = (name, seed)
     if key not in _cache:
         lat, blk = GEOMS[name]
-        U = inputs.make_links(lat, 0.3, cfg)
+        U = inputs.make_links(lat, 0.3, seed)
         ctx = dd.Context(torch.from_numpy(U).to(dev), lat, blk, -1, 1.0)
         _cache[key] = (lat, blk, U, ctx, Schwarz(U, lat, blk, 1.0))
     return _cache[key]
@@ -150,10 +150,10 @@ def test_solve(dev, name, prec):
 @pytest.mark.parametrize("prec", [dd.FP64, dd.MIXED32, dd.MIXED16])
 @pytest.mark.parametrize("op", ["full", "schur"])
 def test_det_ratio_c1(dev, op, prec):
-    cfg = inputs.CONFIGS[1]
+    cfg = inputs.WORKLOADS["4x4^3"]
     lat, blk, U, ctx, S = setup("4x4^3/2^4", dev)
     say("det ratio C1", op, prec)
-    eta = inputs.make_noise_batch(lat, 1, 1, cfg["n_hit"])
+    eta = inputs.make_noise_batch(lat, cfg["seed"], 1, cfg["n_hit"])
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     res = ctx.det_ratio_estimate(k1, k2, T(eta, dev), op=dd.OP_FULL if op == "full" else dd.OP_SCHUR,
                                  tol=1e-12, prec=prec)
@@ -168,10 +168,10 @@ def test_det_ratio_c1(dev, op, prec):
 @pytest.mark.parametrize("op", ["full", "schur"])
 def test_det_ratio_one_flavour(dev, op, prec):
     """n_f = 1 (Eq. 11): complex exponents eta^+ (M - 1) eta and ln Re mean exp(-x)."""
-    cfg = inputs.CONFIGS[1]
+    cfg = inputs.WORKLOADS["4x4^3"]
     lat, blk, U, ctx, S = setup("4x4^3/2^4", dev)
     say("det ratio one flavour C1", op, prec)
-    eta = inputs.make_noise_batch(lat, 1, 1, cfg["n_hit"])
+    eta = inputs.make_noise_batch(lat, cfg["seed"], 1, cfg["n_hit"])
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     res = ctx.det_ratio_estimate(k1, k2, T(eta, dev), op=dd.OP_FULL if op == "full" else dd.OP_SCHUR,
                                  tol=1e-12, prec=prec, n_f=1)
@@ -209,15 +209,15 @@ def test_det_ratio_interpolation(dev):
 def test_det_ratio_c2(dev):
     """8^4 lattice, 4^4 blocks, N_hit = 16: Schur estimator vs the C oracle on every noise vector,
     full-M estimator on four of them."""
-    cfg = inputs.CONFIGS[2]
+    cfg = inputs.WORKLOADS["8x8^3"]
     lat, blk = cfg["lat"], cfg["blk"]
     say("det ratio C2")
-    U = inputs.make_links(lat, 0.3, 2)
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
     ctx = dd.Context(T(U, dev), lat, blk, -1, 1.0)
     R = cref.CRef(U, lat, blk, 1.0)
     k1, k2 = cfg["kappa1"], cfg["kappa2"]
     m1, m2 = dirac.mass(k1), dirac.mass(k2)
-    eta = inputs.make_noise_batch(lat, 2, 1, cfg["n_hit"])
+    eta = inputs.make_noise_batch(lat, cfg["seed"], 1, cfg["n_hit"])
     for op, nchk in (("schur", 16), ("full", 4)):
         for prec in (dd.FP64, dd.MIXED32):
             res = ctx.det_ratio_estimate(k1, k2, T(eta, dev), op=dd.OP_SCHUR if op == "schur" else dd.OP_FULL,

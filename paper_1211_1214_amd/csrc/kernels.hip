@@ -450,7 +450,7 @@ void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed) {
 }
 
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
                                                   double* __restrict__ sums, BiState* __restrict__ st, int stage,
                                                   const double* __restrict__ thr_rel2) {
     const int rhs = blockIdx.x;
@@ -531,7 +531,8 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
                      const double* thr_rel2) {
     Timed t(e, 3, 0);
-    k_finalize<<<nrhs, 256, 0, e.stream>>>(part, ntiles, nrhs, sums, st, stage, thr_rel2);
+    // one workgroup of 16 waves per RHS: the partial sums of up to ~10^4 tiles in a few strides
+    k_finalize<<<nrhs, 1024, 0, e.stream>>>(part, ntiles, nrhs, sums, st, stage, thr_rel2);
 }
 
 // ------------------------------------------------------------------ FP64 helpers

@@ -820,11 +820,7 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     CK(ws_t(C, "be_rr", nb, &rr));
     CK(ws_t(C, "be_iters", nb, &iters));
     HC(hipMemsetAsync(iters, 0, nb * sizeof(int), ex.stream));
-    const size_t half = (size_t)g.V / 2;
-    for (int k = 0; k < nrhs; ++k)
-        for (int c = 0; c < 12; ++c)
-            HC(hipMemsetAsync(x64 + ((size_t)k * 12 + c) * g.V + (colour == 0 ? half : 0), 0, half * sizeof(double2),
-                              ex.stream));
+    // (k_blk_recon writes this colour's solution and clears the other colour)
     launch_blk_prep(ex, g, F64, A64, b64, bpe, re, xe, to, bb, rr, colour, nrhs);
     std::vector<double> hbb(nb), hrr(nb);
     std::vector<int> hit(nb);

@@ -211,6 +211,12 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, EoFields<d
         load_spinor(xe + oh, n2, j, e);
         store_spinor(x + of, g.V, full_index(g, j, 0), e);
     }
+    // the solution is zero on the other colour: clear the block of the other colour with the same
+    // rank (sites (B2 * Vb .. B2 * Vb + Vb) of the full field), so every such block is cleared once
+    const unsigned s0 = (unsigned)((1 - colour) * g.NBc + k.rank) * (unsigned)g.Vb;
+    const cx<double> z[12] = {};
+#pragma unroll 1
+    for (int l = threadIdx.x; l < g.Vb; l += blockDim.x) store_spinor(x + of, g.V, s0 + l, z);
 }
 
 template <class S>

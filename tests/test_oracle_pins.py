@@ -366,6 +366,132 @@ def test_log_domain_combination():
     assert abs(estimator.step_variance(x)[0] - w.var(ddof=1) / w.mean() ** 2) < 1e-14
 
 
+# Pins of the per-step variance (Sec. 2.1 asks for the variance of each factor, with Eq. (4)
+# its expectation; Sec. 3 gives Eq. (12) for one flavour).  Each check takes the variance
+# function as an argument, so that the tests below can also show that plausible mistakes
+# planted in it (population instead of sample variance, the wrong power of the mean) fail.
+def _check_variance_by_hand(fn):
+    """Values worked out by hand: x = (0, ln 2) gives weights (1, 1/2), sample variance 1/8
+    about the mean 3/4, relative 2/9; x = (0, ln 2, ln 4) gives (1, 1/2, 1/4), variance 7/48
+    about 7/12, relative 3/7; a constant shift of x changes nothing; one step per row."""
+    x = np.array([[0.0, np.log(2.0)], [50.0, 50.0 + np.log(2.0)]])
+    ok = np.allclose(fn(x), [2 / 9, 2 / 9], rtol=1e-13, atol=0)
+    x3 = np.array([[0.0, np.log(2.0), np.log(4.0)]]) + 1234.5
+    return ok and abs(fn(x3)[0] - 3 / 7) < 1e-12
+
+
+def _dense_ratio_2x4(kappa2):
+    lat, blk = (2, 2, 2, 2), (1, 1, 1, 1)
+    S = Schwarz(inputs.make_links(lat, 0.3, 5), lat, blk, 1.0)
+    m1, m2 = dirac.mass(0.1200), dirac.mass(kappa2)
+    return np.linalg.solve(S.hat_dense(m2), S.hat_dense(m1))
+
+
+def _check_variance_sampled(fn, M, n_hit=8, batches=60000, seed=21):
+    """The mean over batches of N_hit noise vectors of fn(x) * mean_j(w)^2, the sample variance
+    of the weights w = exp(-x), equals Eq. (4), 1/det(2 M^+M - 1) - 1/det(M^+M)^2, within five
+    standard errors (an unbiased sample variance has that expectation for any N_hit)."""
+    n = M.shape[0]
+    MM = M.conj().T @ M
+    target = 1 / np.linalg.det(MM).real
+    var = 1 / np.linalg.det(2 * MM - np.eye(n)).real - target ** 2
+    rng = np.random.default_rng(seed)
+    s2 = np.empty(batches)
+    chunk = 5000
+    for b in range(0, batches, chunk):
+        eta = (rng.standard_normal((n, chunk * n_hit)) + 1j * rng.standard_normal((n, chunk * n_hit))) * np.sqrt(0.5)
+        x = (np.sum(np.abs(M @ eta) ** 2, axis=0) - np.sum(np.abs(eta) ** 2, axis=0)).reshape(chunk, n_hit)
+        s2[b:b + chunk] = fn(x) * np.exp(-x).mean(axis=1) ** 2
+    se = s2.std(ddof=1) / np.sqrt(batches)
+    return abs(s2.mean() - var) < 5 * se and se < 0.02 * var
+
+
+def test_step_variance_by_hand():
+    assert _check_variance_by_hand(estimator.step_variance)
+
+
+def test_step_variance_expectation_is_eq4():
+    """Sec. 2.1 / Eq. (4) by sampling 4.8e5 noise vectors (6e4 batches of 8) with the dense Schur
+    ratio matrix on a 2^4 lattice."""
+    assert _check_variance_sampled(estimator.step_variance, _dense_ratio_2x4(0.1206))
+
+
+def test_step_variance_pins_catch_planted_mistakes():
+    """The two pins above reject a population variance (ddof = 0, biased by (N_hit - 1)/N_hit) and
+    a variance divided by the mean instead of its square."""
+    def ddof0(x):
+        a = -np.asarray(x, dtype=float)
+        w = np.exp(a - a.max(axis=1, keepdims=True))
+        return w.var(axis=1) / w.mean(axis=1) ** 2
+
+    def over_mean(x):
+        a = -np.asarray(x, dtype=float)
+        w = np.exp(a - a.max(axis=1, keepdims=True))
+        return w.var(axis=1, ddof=1) / w.mean(axis=1)
+
+    M = _dense_ratio_2x4(0.1206)
+    assert not (_check_variance_by_hand(ddof0) and _check_variance_sampled(ddof0, M))
+    assert not (_check_variance_by_hand(over_mean) and _check_variance_sampled(over_mean, M))
+    # the sampling pin alone also sees the ddof mistake
+    assert not _check_variance_sampled(ddof0, M)
+
+
+def _check_one_flavour_variance_by_hand(fn):
+    """x = (0, ln 2 + i pi): real weights (1, -1/2), mean 1/4, sample variance 9/8, relative 18;
+    x = (i pi/3, 0): weights (1/2, 1), relative 2/9."""
+    x = np.array([[0.0, np.log(2.0) + 1j * np.pi], [1j * np.pi / 3, 0.0]])
+    return np.allclose(fn(x), [18.0, 2 / 9], rtol=1e-12, atol=0)
+
+
+def _check_one_flavour_variance_sampled(fn, M, n_hit=8, batches=60000, seed=23):
+    """With w = exp(-eta^+ (M - 1) eta), Eq. (12) gives E|w|^2 = 1/det(M^+ + M - 1), and the same
+    Gaussian integral gives E w^2 = 1/det(2M - 1), so the real weights Re w have the variance
+    (1/2)[1/det(M^+ + M - 1) + Re 1/det(2M - 1)] - (1/det M)^2.  The mean over batches of
+    fn(x) * mean_j(Re w)^2 must equal it within five standard errors."""
+    n = M.shape[0]
+    I = np.eye(n)
+    e_abs2 = 1 / np.linalg.det(M.conj().T + M - I).real
+    e_sq = 1 / np.linalg.det(2 * M - I)
+    mean = 1 / np.linalg.det(M).real
+    var = 0.5 * (e_abs2 + e_sq.real) - mean ** 2
+    A = M - I
+    rng = np.random.default_rng(seed)
+    s2 = np.empty(batches)
+    chunk = 5000
+    for b in range(0, batches, chunk):
+        eta = (rng.standard_normal((n, chunk * n_hit)) + 1j * rng.standard_normal((n, chunk * n_hit))) * np.sqrt(0.5)
+        x = np.sum(eta.conj() * (A @ eta), axis=0).reshape(chunk, n_hit)
+        s2[b:b + chunk] = fn(x) * np.exp(-x).real.mean(axis=1) ** 2
+    se = s2.std(ddof=1) / np.sqrt(batches)
+    return abs(s2.mean() - var) < 5 * se and se < 0.02 * var
+
+
+def test_step_variance_one_flavour_by_hand():
+    assert _check_one_flavour_variance_by_hand(estimator.step_variance_one_flavour)
+
+
+def test_step_variance_one_flavour_expectation():
+    """Sec. 3 / Eq. (12) by sampling 4.8e5 noise vectors with the dense Schur ratio matrix."""
+    M = _dense_ratio_2x4(0.1206)
+    assert np.linalg.eigvalsh(M.conj().T + M).min() > 1  # Eq. (12) exists
+    assert _check_one_flavour_variance_sampled(estimator.step_variance_one_flavour, M)
+
+
+def test_step_variance_one_flavour_pins_catch_planted_mistakes():
+    def ddof0(x):
+        _, w = estimator._one_flavour_weights(x)
+        return w.var(axis=1) / w.mean(axis=1) ** 2
+
+    def abs_weights(x):  # |w| instead of Re w
+        x = np.asarray(x, dtype=complex)
+        w = np.exp(-x.real + x.real.min(axis=1, keepdims=True))
+        return w.var(axis=1, ddof=1) / w.mean(axis=1) ** 2
+
+    M = _dense_ratio_2x4(0.1206)
+    assert not _check_one_flavour_variance_sampled(ddof0, M)
+    assert not _check_one_flavour_variance_by_hand(abs_weights)
+
+
 # --------------------------------------------------------------------------- one flavour (Eq. 11, 12)
 def test_one_flavour_plane_wave_closed_form():
     """U = 1: a plane wave e^{ipx} u c with u an eigenvector of sum gamma_mu sin p_mu (eigenvalue

@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# FP32 vector peak without packed instructions (which the library does not use): 256 CUs x 4 SIMDs x
+# 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_VALU_TFLOPS = 78.6
 METRIC = "Dslash GB/s (% HBM peak); det-ratio estimates/s, mixed vs FP64 at 1e-8"
 DESCRIPTIONS = {
     "48x24^3": "Schur det-ratio estimate, 48x24^3, 6^4 blocks (512), Wilson-clover c_sw=1, kappa 0.1200->0.1205, "
@@ -48,7 +51,10 @@ def main():
     ap.add_argument("--inner", choices=("fp32", "fp16"), default=None,
                     help="storage of the global inner solver (default: fp32 at 48x24, fp16 at 64x32)")
     ap.add_argument("--fp64-samples", type=int, default=2, help="noise vectors for the FP64 single-RHS path")
-    ap.add_argument("--cpu-cap", type=int, default=6, help="BiCGStab iterations per solve in the CPU sample")
+    ap.add_argument("--cpu-threads-1", action="store_true",
+                    help="also time one oracle estimate on a single thread (about 16x the all-core time)")
+    ap.add_argument("--profile-steps", type=int, default=3, help="steps of the profiled pass (kernel timings)")
+    ap.add_argument("--stream-gib", type=float, default=2.0, help="GiB of the streaming reference copy (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule options")
     ap.add_argument("--nested", action="store_true",
@@ -61,6 +67,8 @@ def main():
                     help="time the one-flavour estimator (Eq. 11) instead (48x24^3)")
     ap.add_argument("--solver", choices=("bicgstab", "sap-gcr"), default="bicgstab",
                     help="global solver: even-odd BiCGStab or GCR preconditioned by Schwarz sweeps")
+    ap.add_argument("--block-kernel", choices=("auto", "global"), default="auto",
+                    help="Schwarz block inner solver: LDS-resident where it fits (auto) or the global-memory kernel")
     ap.add_argument("--dslash-reps", type=int, default=20, help="launches per standalone Dslash measurement")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (calibrates HBM counters) and exit")
@@ -112,6 +120,8 @@ def main():
     prec = dd.MIXED16 if inner == "fp16" else dd.MIXED32
     if args.solver == "sap-gcr":
         ctx.set_option(dd.binding.OPT_SOLVER, 1)
+    if args.block_kernel == "global":
+        ctx.set_option(dd.binding.OPT_BLOCK_KERNEL, 1)
     tuned = ctx.autotune(k2, nhit, prec) if not args.no_autotune else None
     log(f"autotune: {tuned}")
 
@@ -121,7 +131,7 @@ def main():
     for w in range(args.warmup):
         r = step()
         log(f"warmup {w}: log W_gl {r['log_w_gl']:.10f}, {r['stats']}")
-    ctx.profile_enable(True)
+    # the timed region: what ships (the autotuned schedule, graph replay allowed, no per-launch events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -129,14 +139,26 @@ def main():
         log(f"step {k}: log W_gl {r['log_w_gl']:.10f}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = nint * nhit * args.steps / elapsed
+    x_mixed = r["x"]
+    log(f"timed {args.steps} steps in {elapsed:.3f}s: {value:.2f} estimates/s")
+
+    # profiled pass: the same step with HIP events around every launch on its stream (graphs off
+    # while profiling) for the kernel classes and the roofline of the dominant kernel
+    psteps = max(1, min(args.profile_steps, args.steps))
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for k in range(psteps):
+        step()
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - tp0
     prof = {name: ctx.profile_read(kc) for name, kc in
             (("dslash64", dd.binding.K_DSLASH64), ("dslash32", dd.binding.K_DSLASH32), ("eohop", dd.binding.K_EOHOP),
              ("block", dd.binding.K_BLOCK), ("blas", dd.binding.K_BLAS), ("other", dd.binding.K_OTHER))}
     ctx.profile_enable(False)
-    elapsed = t1 - t0
-    value = nint * nhit * args.steps / elapsed
-    x_mixed = r["x"]
-    log(f"timed {args.steps} steps in {elapsed:.3f}s: {value:.2f} estimates/s; profile {prof}")
+    log(f"profiled {psteps} steps in {prof_elapsed:.3f}s; profile {prof}")
 
     # FP64 single-RHS path on the first noise vectors (all interpolation steps)
     fp64_t = 0.0
@@ -152,25 +174,33 @@ def main():
     fp64_rate = nint * args.fp64_samples / fp64_t if args.fp64_samples else None
 
     dslash = dslash_rates(ctx, dd, inputs, lat, dev, args.dslash_reps) if args.dslash_reps > 0 else None
+    stream_gbs = stream_peak(dd, torch) if args.stream_gib > 0 else None
 
-    # parity against the stored oracle exponents (written by tests/golden/make_golden_{48x24,64x32}.py)
+    # parity against the stored oracle values (written by tests/golden/make_golden_{48x24,64x32}.py)
     parity = {}
     gpath = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     if golden:
+        worst = 0.0
         for key, xo in golden["x_schur"].items():
             i, j = (0, int(key)) if "," not in key else map(int, key.split(","))
-            parity[f"x{i}{j}_mixed_rel"] = abs(x_mixed[i, j] - xo) / max(abs(xo), 1.0)
+            e = abs(x_mixed[i, j] - xo) / max(abs(xo), 1.0)
+            worst = max(worst, e)
             if j < len(x64):
                 parity[f"x{i}{j}_fp64_rel"] = abs(x64[j][i] - xo) / max(abs(xo), 1.0)
+        parity["x_mixed_rel_max"] = worst
+        parity["x_compared"] = len(golden["x_schur"])
+        if "log_w_gl" in golden:
+            lw = golden["log_w_gl"]
+            parity["log_w_gl_oracle"] = lw
+            parity["log_w_gl_rel"] = abs(r["log_w_gl"] - lw) / max(abs(lw), 1.0)
+            parity["step_var_rel"] = abs(r["step_var"][0] - golden["step_var"]) / golden["step_var"]
     d = max((abs(x_mixed[i, j] - x64[j][i]) / max(abs(x64[j][i]), 1.0) for j in range(len(x64))
              for i in range(nint)), default=None)
     parity["x_mixed_vs_fp64_rel_max"] = d
 
     # Roofline of the Dslash the metric names: the even-odd hop-and-inverse kernel of the global
-    # solver (one kernel; live HIP-event durations over the timed region).  The persistent block
-    # solver, which takes a similar share of the time, keeps its vectors in the last-level cache
-    # (its algorithmic bytes per second exceed the HBM peak), so it is reported beside it.
+    # solver (one kernel; HIP-event durations of its launches in the profiled pass).
     dom = "eohop" if prof["eohop"]["launches"] else max(("dslash32", "block", "dslash64", "blas"),
                                                          key=lambda k: prof[k]["ms"])
     pd = prof[dom]
@@ -179,21 +209,19 @@ def main():
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
     ds_ms, ds_b = prof["dslash32"]["ms"] + prof["eohop"]["ms"], prof["dslash32"]["bytes"] + prof["eohop"]["bytes"]
     dslash_gbs = ds_b / (ds_ms * 1e-3) / 1e9 if ds_ms > 0 else None
-    pb = prof["block"]
-    block = None if not pb["launches"] else {
-        "launches": pb["launches"], "avg_launch_us": round(1e3 * pb["ms"] / pb["launches"], 2),
-        "algorithmic_gbs": round(pb["bytes"] / (pb["ms"] * 1e-3) / 1e9, 1),
-        "note": "algorithmic bytes of the block BiCGStab per second; above the HBM peak the block vectors "
-                "are served from the Infinity Cache"}
+    block = block_summary(prof["block"])
     traffic = measured_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "launches": pd["launches"], "avg_launch_us": round(per_launch_ms * 1e3, 2),
-                "bytes_per_launch": per_launch_bytes}
+                "bytes_per_launch": per_launch_bytes,
+                "peak_measured": None if stream_gbs is None else round(stream_gbs, 1),
+                "frac_of_measured": None if not stream_gbs else round(achieved / stream_gbs, 4),
+                "timing": f"HIP events around each launch on its stream, profiled pass of {psteps} steps"}
 
     cpu = None
-    if wname == "48x24^3" and not args.no_cpu_baseline and golden and "schur_solve_iterations" in golden:
-        cpu = cpu_baseline(U, eta[0, 0], cfg, golden, args.cpu_cap)
+    if wname == "48x24^3" and not args.no_cpu_baseline and golden:
+        cpu = cpu_baseline(U, eta[0, 0], cfg, golden, args.cpu_threads_1)
 
     total_ms = sum(p["ms"] for p in prof.values())
     line = {
@@ -205,7 +233,7 @@ def main():
         "config": {"workload": DESCRIPTIONS[wname] + ("" if inner == "fp32" else
                                                  "; global inner solver in FP16 storage (per-site scales, FP16 links)"),
                    "lattice": list(lat), "blocks": list(blk), "n_interp": nint, "n_hit": nhit, "tol": args.tol,
-                   "inner": inner, "solver": args.solver},
+                   "inner": inner, "solver": args.solver, "block_kernel": args.block_kernel},
         "roofline": roofline,
         "schedule": tuned,
         "cpu_baseline": cpu,
@@ -217,10 +245,46 @@ def main():
         "speedup_vs_fp64_single_rhs": None if not fp64_rate else round(value / fp64_rate, 2),
         "parity": parity,
         "log_w_gl": r["log_w_gl"],
+        "profiled_ms_per_step": round(1e3 * prof_elapsed / psteps, 3),
         "kernel_time_share": {k: round(p["ms"] / total_ms, 3) for k, p in prof.items()} if total_ms else None,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def stream_peak(dd, torch, gib=2.0, reps=5):
+    """The library's streaming reference copy (ddwc_stream_copy) of a `gib` GiB buffer: read plus
+    written bytes over the median duration from torch events on the launch stream."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    dd.binding.stream_copy(a, b)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dd.binding.stream_copy(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    gbs = 2 * 4 * n / times[len(times) // 2] / 1e9
+    log(f"stream copy: {gbs:.0f} GB/s (read + write, {gib} GiB)")
+    del a, b
+    return gbs
+
+
+def block_summary(pb):
+    """The persistent block solver class: launches, duration, and its ALU roofline (FP32 vector
+    rate without packed instructions); its working set is on chip and in the caches, so an HBM
+    fraction does not apply."""
+    if not pb["launches"]:
+        return None
+    flops = pb["bytes"]  # the block class accumulates flops in the byte slot (see the library's model)
+    tf = flops / (pb["ms"] * 1e-3) / 1e12 if pb["ms"] > 0 else 0.0
+    return {"launches": pb["launches"], "avg_launch_us": round(1e3 * pb["ms"] / pb["launches"], 2),
+            "bound": "alu", "achieved": round(tf, 2), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / FP32_VALU_TFLOPS, 4)}
 
 
 def kernel_sources_digest():
@@ -519,28 +583,52 @@ def dslash_rates(ctx, dd, inputs, lat, dev, reps):
     return out
 
 
-def cpu_baseline(U, eta0, cfg, golden, cap):
-    """The C oracle on a bounded sample: one Schur exponent with each of its five solves
-    capped at `cap` BiCGStab iterations; the per-iteration time of each solve times the
-    oracle's own iteration count for that solve (stored with the golden exponents) gives
-    the time of one estimate."""
+def cpu_baseline(U, eta0, cfg, golden, one_thread):
+    """The C oracle timed on the host: one complete Schur estimate (all five solves to 1e-13, the
+    exponent checked against the stored oracle value) on every core, and the oracle's Dslash in
+    GB/s under the library's byte model (1536 bytes per site in FP64) on every core and on one
+    thread; optionally the complete estimate on one thread too."""
+    import numpy as np
     from oracle import cref, dirac
     t = time.time()
     R = cref.CRef(U, cfg["lat"], cfg["blk"], cfg["csw"], -1)
     setup = time.time() - t
+    cores = cref.CRef.threads()
     m1, m2 = dirac.mass(cfg["kappa1"]), dirac.mass(cfg["kappa2"])
+    V = int(np.prod(cfg["lat"]))
+
+    def dslash_gbs(reps):
+        psi = eta0
+        R.dslash(m2, psi)
+        ts = []
+        for _ in range(reps):
+            ta = time.perf_counter()
+            R.dslash(m2, psi)
+            ts.append(time.perf_counter() - ta)
+        ts.sort()
+        return 1536.0 * V / ts[len(ts) // 2] / 1e9
+
+    g_all = dslash_gbs(5)
     t = time.time()
-    _, iters, secs = R.exponent_recorded("schur", "diff", m1, m2, eta0, 1e-13, cap=cap)
+    x, iters, secs = R.exponent_recorded("schur", "diff", m1, m2, eta0, 1e-13)
     wall = time.time() - t
-    full = golden["schur_solve_iterations"]
-    est = sum(s / max(i, 1) * f for s, i, f in zip(secs, iters, full)) + (wall - sum(secs))
+    xo = golden["x_schur"]["0"]
+    out = {"value": round(1.0 / wall, 5), "unit": "estimates/s", "cores": cores, "kind": "oracle",
+           "sample": f"one complete Schur estimate x_00 of the same 48x24^3 workload (difference form, its "
+                     f"{len(iters)} BiCGStab solves to 1e-13: {iters} iterations) in {wall:.1f}s on {cores} "
+                     f"threads, x_00 = {x!r} (stored oracle value {xo!r})",
+           "x00_rel": abs(x - xo) / max(abs(xo), 1.0),
+           "dslash_gbs": round(g_all, 2), "setup_s": round(setup, 1)}
+    cref.CRef.set_threads(1)
+    out["dslash_gbs_1thread"] = round(dslash_gbs(2), 2)
+    if one_thread:
+        t = time.time()
+        R.exponent("schur", "diff", m1, m2, eta0, 1e-13)
+        out["value_1thread"] = round(1.0 / (time.time() - t), 6)
+    cref.CRef.set_threads(cores)
     R.close()
-    log(f"cpu sample: {wall:.1f}s (setup {setup:.1f}s), per-solve iters {iters} secs {secs}; "
-        f"one estimate ~ {est:.1f}s")
-    return {"value": round(1.0 / est, 5), "unit": "estimates/s", "cores": cref.CRef.threads(), "kind": "oracle",
-            "sample": f"one Schur exponent on the same 48x24^3 workload with each of its {len(iters)} BiCGStab "
-                      f"solves capped at {cap} iterations ({wall:.1f}s), scaled per solve by the oracle's own "
-                      f"iteration counts {full} for a full estimate (tests/golden/oracle_48x24.json)"}
+    log(f"cpu baseline: {out}")
+    return out
 
 
 if __name__ == "__main__":

@@ -40,6 +40,8 @@
 #ifndef DDWC_H
 #define DDWC_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -58,8 +60,9 @@ typedef enum {
 /* DDWC_MIXED16: as DDWC_MIXED32, except that the inner BiCGStab of the even-odd global solver
  * and of the even-odd Schwarz block solver keeps its vectors in FP16 with one FP32 scale per
  * site and RHS, and its links in FP16 (clover, arithmetic and the solution correction in
- * FP32; FP64 defect correction restores the tolerance).  ddwc_dslash_apply and lattices with
- * an odd block extent run as DDWC_MIXED32.  At most 256 RHS per call in the global solver. */
+ * FP32; FP64 defect correction restores the tolerance).  ddwc_dslash_apply, lattices with an
+ * odd block extent, and block solves on blocks that the LDS-resident inner kernel takes
+ * (DDWC_OPT_BLOCK_KERNEL) run as DDWC_MIXED32.  At most 256 RHS per call in the global solver. */
 typedef enum { DDWC_FP64 = 0, DDWC_MIXED32 = 1, DDWC_MIXED16 = 2 } ddwc_precision;
 typedef enum { DDWC_BLACK = 0, DDWC_WHITE = 1 } ddwc_colour;
 typedef enum { DDWC_OP_FULL = 0, DDWC_OP_SCHUR = 1 } ddwc_operator;
@@ -201,6 +204,45 @@ int ddwc_link_force(ddwc_ctx *ctx, const void *a, const void *b, int nrhs, const
 int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_host, int *sign_host, void *stream);
 
 /*
+ * The block factor of the two-flavour log W (Eq. 7: det D = det Dhat * det D_bb * det D_ww):
+ *   *out_host = 2 sum_k [ln|det D_k(m2)| - ln|det D_k(m1)|] over the blocks of both colours,
+ * from four ddwc_block_logdet calls (same limits and errors).  Synchronises the stream.
+ */
+int ddwc_log_w_blocks(ddwc_ctx *ctx, double kappa1, double kappa2, double *out_host, void *stream);
+
+/*
+ * Combination of given exponents, on the host (no context, no device work): Eq. (8) per step
+ * for n_f = 2, Eq. (11) with the real part of each step's mean for n_f = 1, exactly as
+ * ddwc_det_ratio_estimate combines its own exponents.
+ *   x_host        [n_interp][n_hit] (n_f = 2) or [n_interp][n_hit][2] (n_f = 1, re/im pairs)
+ *   log_w         sum_i ln Re[(1/n_hit) sum_j exp(-x_ij)] (NaN with DDWC_EUNDEF)
+ *   step_var_host [n_interp] relative sample variances (N_hit - 1 in the denominator); may be null
+ *   gx_host       [n_interp][n_hit] d log_w / d x_ij = -exp(-x_ij) / sum_j exp(-x_ij) (n_f = 2
+ *                 only, EINVAL otherwise); may be null.  This is the upstream gradient that
+ *                 ddwc_det_ratio_grad takes for L = log W_gl.
+ * EINVAL for non-finite exponents or bad sizes; EUNDEF when a step's real mean is not positive
+ * or a mean or variance is not finite.
+ */
+int ddwc_log_w_combine(const double *x_host, int n_interp, int n_hit, int n_f, double *log_w, double *step_var_host,
+                       double *gx_host);
+
+/*
+ * Total two-flavour log W with nested domain decomposition (Sec. 2.2):
+ *   parts_host[0] = log W_gl of the outer context (ddwc_det_ratio_estimate, op = SCHUR, eta_gl,
+ *                   n_hit_gl noise vectors per step);
+ *   parts_host[1], [2] = the nested factors of the black and white outer blocks
+ *                   (ddwc_det_ratio_nested with eta_black, eta_white, n_hit_nested per step);
+ *   parts_host[3] = the exact block factor of the inner blocks (ddwc_log_w_blocks on inner);
+ *   parts_host[4] = their sum, log W.
+ * Every eta is canonical [n_interp][n_hit][V][4][3] on the device.  Same rules and errors as the
+ * calls it makes; stats: the global solves of parts_host[0].  Synchronises the stream.
+ */
+int ddwc_log_w_nested_total(ddwc_ctx *outer, ddwc_ctx *inner, double kappa1, double kappa2, int n_interp,
+                            const void *eta_gl, int n_hit_gl, const void *eta_black, const void *eta_white,
+                            int n_hit_nested, double tol, int prec, double *parts_host, ddwc_stats *stats,
+                            void *stream);
+
+/*
  * Schedule options of a context.
  *   DDWC_OPT_GRAPHS        1: the global solver replays each chunk of BiCGStab iterations from
  *                          a captured HIP graph (cached per buffer set and mass; not while
@@ -214,9 +256,13 @@ int ddwc_block_logdet(ddwc_ctx *ctx, double kappa, int colour, double *logabs_ho
  *                          the exact FP64 residual) preconditioned by the Schwarz alternating
  *                          procedure: 3 multiplicative cycles over the black then the white
  *                          blocks, each block solve by the persistent block solver to 1e-1.
- *   DDWC_OPT_BLOCK_LDS     KiB of LDS reserved (not used) by each persistent block-solver workgroup,
+ *   DDWC_OPT_BLOCK_LDS     KiB of LDS reserved (not used) by each global-memory block-solver workgroup,
  *                          which caps the workgroups resident per CU and so the block vectors in
  *                          flight (0 = none; at most the device's per-workgroup LDS minus 1 KiB).
+ *   DDWC_OPT_BLOCK_KERNEL  inner solver of the even-odd Schwarz block solves in DDWC_MIXED32 and
+ *                          DDWC_MIXED16: 0 (default) the LDS-resident FP32 kernel wherever a block
+ *                          parity has at most 768 sites and its two staged fields fit the LDS (both
+ *                          precisions then run it, FP32 storage); 1 the global-memory kernel.
  * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
@@ -225,7 +271,8 @@ typedef enum {
     DDWC_OPT_POLL = 1,
     DDWC_OPT_BLOCK_THREADS = 2,
     DDWC_OPT_SOLVER = 3,
-    DDWC_OPT_BLOCK_LDS = 4
+    DDWC_OPT_BLOCK_LDS = 4,
+    DDWC_OPT_BLOCK_KERNEL = 5
 } ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
@@ -244,7 +291,11 @@ int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *secon
  * Kernel timing for measurement.  When enabled, launches of the library's kernels
  * are bracketed with HIP events on their stream; ddwc_profile_read synchronises and
  * returns, for kernel class `kclass` (DDWC_K_*), the number of launches and their
- * summed duration in milliseconds since the last reset.
+ * summed duration in milliseconds since the last reset, and in *bytes the algorithmic HBM
+ * bytes of the operator classes' launches.  For DDWC_K_BLOCK, whose kernels work from LDS and
+ * the caches, *bytes holds instead the model's floating-point operation count (per inner
+ * iteration and even site: two block-operator applications over both parities at 180 flops per
+ * in-block hop and 540 per site for the clover, plus 400 for the vector updates).
  */
 typedef enum {
     DDWC_K_DSLASH64 = 0,  /* full-lattice Dslash, FP64 */
@@ -258,6 +309,15 @@ typedef enum {
 } ddwc_kernel_class;
 int ddwc_profile_enable(ddwc_ctx *ctx, int on);
 int ddwc_profile_read(ddwc_ctx *ctx, int kclass, long long *launches, double *total_ms, double *bytes);
+
+/*
+ * Streaming reference: dst = src for `bytes` bytes (device buffers, 16-byte aligned, bytes a multiple
+ * of 16; they must not overlap), by the library's own copy kernel (float4 words, four loads in flight
+ * per thread, grid-stride rounds).  Its rate is the practical HBM streaming ceiling that the operator
+ * kernels are measured against beside the nominal peak; with a known size it also calibrates memory
+ * counters.  Asynchronous on `stream`; needs no context.
+ */
+int ddwc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Algorithmic HBM bytes of one full-lattice Dslash launch at this geometry (per RHS count). */
 double ddwc_dslash_bytes(const ddwc_ctx *ctx, int nrhs, int prec);

@@ -378,6 +378,11 @@ int ref_record(int on, int cap, int *iters, double *secs) {
 
 int ref_threads(void) { return omp_get_max_threads(); }
 
+/* Thread count of the following parallel regions (timing only; results do not depend on it). */
+void ref_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
+
 static void mask_P(const ref_t *h, const cplx *in, cplx *out) {
     for (long s = 0; s < h->V; s++)
         for (int i = 0; i < 12; i++) out[12 * s + i] = h->pmask[s] ? in[12 * s + i] : 0;

@@ -55,6 +55,8 @@ def _load():
         L.ref_record.argtypes = [I, I, P, P]
         L.ref_record.restype = I
         L.ref_threads.restype = I
+        L.ref_set_threads.argtypes = [I]
+        L.ref_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -156,6 +158,11 @@ class CRef:
     @staticmethod
     def threads() -> int:
         return int(_load().ref_threads())
+
+    @staticmethod
+    def set_threads(n: int) -> None:
+        """Thread count of the oracle's OpenMP regions from now on (timing only)."""
+        _load().ref_set_threads(int(n))
 
     def exponent(self, op: str, form: str, m1, m2, eta, tol=1e-13) -> float:
         eta = _c(eta)

@@ -5,19 +5,18 @@ float64 CPU tensor that is differentiable in ``kappa2`` (a 0-dim float64 tensor)
 ``links`` (the complex128 [4, V, 3, 3] device tensor the Context was created from).  The
 backward pass calls ddwc_det_ratio_grad, which recomputes every solve of the forward pass
 and runs the adjoint solves; nothing but the inputs is kept between the two passes.
-``log_w_gl(x)`` is the log-domain combination of Eq. (8) in torch operations, so
-log W_gl and its gradients follow from autograd.
+``log_w_gl(x)`` is the log-domain combination of Eq. (8) computed by ddwc_log_w_combine
+(value and d log W_gl / dx_ij on the host, in the library), wrapped so that the gradient
+flows back through ``exponents``.
 
 A Context holds its own copy of the links: to differentiate at other links, create a new
 Context from them.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
-from .binding import FP64, OP_SCHUR
+from .binding import FP64, OP_SCHUR, log_w_combine
 
 
 class _Exponents(torch.autograd.Function):
@@ -45,6 +44,19 @@ def exponents(handle, kappa1: float, kappa2: torch.Tensor, links: torch.Tensor, 
     return _Exponents.apply(kappa2, links, handle, kappa1, eta, op, tol, prec)
 
 
+class _LogWGl(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, x):
+        r = log_w_combine(x.detach().cpu().numpy(), n_f=2, grad=True)
+        fctx.save_for_backward(torch.from_numpy(r["gx"]).to(x.device, x.dtype))
+        return torch.tensor(r["log_w"], dtype=x.dtype, device=x.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        (gx,) = fctx.saved_tensors
+        return g * gx
+
+
 def log_w_gl(x: torch.Tensor) -> torch.Tensor:
-    """sum_i [logsumexp_j(-x_ij) - ln n_hit]."""
-    return (torch.logsumexp(-x, dim=1) - math.log(x.shape[1])).sum()
+    """sum_i [logsumexp_j(-x_ij) - ln n_hit] (Eq. 8), by ddwc_log_w_combine; differentiable in x."""
+    return _LogWGl.apply(x)

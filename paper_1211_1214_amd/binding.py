@@ -19,7 +19,7 @@ FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER, K_EOHOP = range(6)
-OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS = range(5)
+OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS, OPT_BLOCK_KERNEL = range(6)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.
@@ -48,12 +48,16 @@ SIGNATURES = {
     "ddwc_det_ratio_grad": (_I, [_P, _D, _D, _I, _I, _P, _I, _D, _I, _PD, _PD, _P, _PS, _P]),
     "ddwc_link_force": (_I, [_P, _P, _P, _I, _PD, _P, _P]),
     "ddwc_block_logdet": (_I, [_P, _D, _I, _PD, _PI, _P]),
+    "ddwc_log_w_blocks": (_I, [_P, _D, _D, _PD, _P]),
+    "ddwc_log_w_combine": (_I, [_PD, _I, _I, _I, _PD, _PD, _PD]),
+    "ddwc_log_w_nested_total": (_I, [_P, _P, _D, _D, _I, _P, _I, _P, _P, _I, _D, _I, _PD, _PS, _P]),
     "ddwc_set_option": (_I, [_P, _I, _I]),
     "ddwc_get_option": (_I, [_P, _I, _PI]),
     "ddwc_autotune": (_I, [_P, _D, _I, _I, _PD, _P]),
     "ddwc_profile_enable": (_I, [_P, _I]),
     "ddwc_profile_read": (_I, [_P, _I, _PLL, _PD, _PD]),
     "ddwc_dslash_bytes": (_D, [_P, _I, _I]),
+    "ddwc_stream_copy": (_I, [_P, _P, ctypes.c_size_t, _P]),
     "ddwc_last_error": (ctypes.c_char_p, []),
     "ddwc_version": (ctypes.c_char_p, []),
 }
@@ -114,6 +118,34 @@ def _spinors(t, V, what):
     if sh[-3:] != (V, 4, 3):
         raise ValueError(f"{what} must end in ({V}, 4, 3), got {sh}")
     return int(np.prod(sh[:-3])) if len(sh) > 3 else 1
+
+
+def log_w_combine(x, n_f=2, grad=False, allow=()):
+    """ddwc_log_w_combine on given exponents x [n_interp, n_hit] (complex for n_f = 1), on the host:
+    {"log_w", "step_var", "gx" (d log_w / dx for n_f = 2 when grad), "status"}."""
+    x = np.asarray(x)
+    if x.ndim != 2:
+        raise ValueError("x must have shape (n_interp, n_hit)")
+    n_interp, n_hit = x.shape
+    xa = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1) if n_f == 1 else x, dtype=np.float64)
+    lw = ctypes.c_double()
+    var = np.zeros(n_interp)
+    gx = np.zeros((n_interp, n_hit)) if grad else None
+    code = _check(lib().ddwc_log_w_combine(xa.ctypes.data_as(_PD), int(n_interp), int(n_hit), int(n_f),
+                                           ctypes.byref(lw), var.ctypes.data_as(_PD),
+                                           gx.ctypes.data_as(_PD) if grad else None), "ddwc_log_w_combine",
+                  allow=allow)
+    return {"log_w": lw.value, "step_var": var, "gx": gx, "status": code}
+
+
+def stream_copy(src, dst):
+    """dst = src by the library's streaming reference kernel (same-size contiguous device tensors)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst must have the same size in bytes")
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous device tensors")
+    _check(lib().ddwc_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  src.numel() * src.element_size(), _stream()), "ddwc_stream_copy")
 
 
 def mass(kappa: float) -> float:
@@ -225,16 +257,23 @@ class Context:
         return {"x": x, "log_w": lw.value, "step_var": var, "stats": st.as_dict(), "status": code}
 
     def log_w_nested(self, inner, kappa1, kappa2, eta_gl, eta_nested, tol=1e-12, prec=FP64):
-        """Two-flavour log W with nested DD: log W_gl (this context, Schur) + the nested factors of both
-        colours + the exact inner block factors (sums of the entry points' outputs)."""
-        r = self.det_ratio_estimate(kappa1, kappa2, eta_gl, op=OP_SCHUR, tol=tol, prec=prec)
-        parts = {"log_w_gl": r["log_w_gl"]}
-        for c in (BLACK, WHITE):
-            parts[f"log_w_nested{c}"] = self.det_ratio_nested(inner, c, kappa1, kappa2, eta_nested[c], tol=tol,
-                                                              prec=prec)["log_w"]
-        parts["log_w_inner_blocks"] = inner.log_w_blocks(kappa1, kappa2)
-        parts["log_w"] = sum(parts.values())
-        return parts
+        """Two-flavour log W with nested DD (ddwc_log_w_nested_total): log W_gl of this context (outer
+        blocks, Schur), the nested factors of both colours, the exact inner block factor, and the total.
+        eta_gl [n_interp, n_hit, V, 4, 3]; eta_nested = (black, white), each [n_interp, n_hit2, V, 4, 3]."""
+        sh, sb, sw = tuple(eta_gl.shape), tuple(eta_nested[0].shape), tuple(eta_nested[1].shape)
+        for s_ in (sh, sb, sw):
+            if len(s_) != 5 or s_[2:] != (self.V, 4, 3):
+                raise ValueError(f"noise must have shape (n_interp, n_hit, {self.V}, 4, 3)")
+        if sb != sw or sb[0] != sh[0]:
+            raise ValueError("the nested noise of both colours must have one shape and the same n_interp")
+        parts = np.zeros(5)
+        st = Stats()
+        _check(lib().ddwc_log_w_nested_total(
+            self._h, inner._h, float(kappa1), float(kappa2), int(sh[0]), _ptr(eta_gl, what="eta_gl"), int(sh[1]),
+            _ptr(eta_nested[0], what="eta_black"), _ptr(eta_nested[1], what="eta_white"), int(sb[1]), float(tol),
+            int(prec), parts.ctypes.data_as(_PD), ctypes.byref(st), _stream()), "ddwc_log_w_nested_total")
+        names = ("log_w_gl", "log_w_nested0", "log_w_nested1", "log_w_inner_blocks", "log_w")
+        return {k: float(v) for k, v in zip(names, parts)}
 
     def det_ratio_grad(self, kappa1, kappa2, eta, gx, op=OP_SCHUR, tol=1e-12, prec=FP64, want_kappa2=True,
                        want_links=True):
@@ -280,10 +319,10 @@ class Context:
 
     def log_w_blocks(self, kappa1, kappa2):
         """Block factor of log W for two flavours (Eq. 7): 2 sum_k [ln|det D_k(m2)| - ln|det D_k(m1)|]."""
-        tot = 0.0
-        for c in (BLACK, WHITE):
-            tot += self.block_logdet(kappa2, c)[0].sum() - self.block_logdet(kappa1, c)[0].sum()
-        return 2 * tot
+        out = ctypes.c_double()
+        _check(lib().ddwc_log_w_blocks(self._h, float(kappa1), float(kappa2), ctypes.byref(out), _stream()),
+               "ddwc_log_w_blocks")
+        return out.value
 
     def set_option(self, option, value):
         _check(lib().ddwc_set_option(self._h, int(option), int(value)), "ddwc_set_option")

@@ -105,7 +105,7 @@ struct ddwc_ctx {
     cx<float>* Uh32 = nullptr;
     double2* Kh64 = nullptr;
     cx<f16>* Uh16 = nullptr;  // FP16 half-order links (storage of the FP16 inner solver)
-    cx<float>* Uh32s = nullptr;  // site-major copies of the FP32 and FP16 half-order links, read by the
+    cx<float>* Uh32s = nullptr;  // own-site link records [2][V/2][8][9] (FP32, FP16) read by the
     cx<f16>* Uh16s = nullptr;    // RHS-innermost kernels of the global solver
     float4* Kh32 = nullptr;
     int* nbr_eo = nullptr;
@@ -131,6 +131,8 @@ struct ddwc_ctx {
     int opt_blk_threads = 0;  // block-solver workgroup size (0: default rule)
     int opt_solver = 0;       // global solver: 0 even-odd BiCGStab, 1 SAP-preconditioned GCR
     int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
+    int opt_blk_kernel = 0;   // block inner solver: 0 LDS-resident where it fits (FP32/FP16), 1 global-memory
+    int lds_max = 0;          // LDS bytes per workgroup of the device
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
     struct Graph {
         std::vector<uintptr_t> key;
@@ -198,6 +200,20 @@ static int check_common(const ddwc_ctx* C, double kappa, int nrhs, int prec) {
     return DDWC_OK;
 }
 
+// RHS-innermost fields address (site, RHS) element i * nrhs + r of a component plane with a
+// 32-bit byte offset (at() in ddwc_device.h): usable while one plane of n * nrhs 16-byte words
+// stays within 4 GiB.  Otherwise the fields are RHS-major.
+static bool ri_fits(unsigned n, int nrhs) { return (uint64_t)n * (uint64_t)nrhs * 16u <= ((uint64_t)1 << 32); }
+
+// The FP16 inner solver of the even-odd global solve needs RHS-innermost fields of at most WG RHS;
+// checked at every entry point that can reach it, before any launch.
+static int check_h16_global(const ddwc_ctx* C, int nrhs, int prec) {
+    if (prec != DDWC_MIXED16 || !C->g.eo || C->opt_solver != 0) return DDWC_OK;
+    if (nrhs > WG || !ri_fits((unsigned)(C->g.V / 2), nrhs))
+        return fail(DDWC_EINVAL, "the FP16 inner solver takes at most 256 RHS (and V/2 * nrhs <= 2^28)");
+    return DDWC_OK;
+}
+
 static size_t vec_words(const ddwc_ctx* C, int nrhs, bool fp64) {
     return (size_t)nrhs * (fp64 ? 12 : 6) * C->g.V;  // 16-byte words
 }
@@ -234,6 +250,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     }
     C->csw = c_sw;
     hipError_t e0 = hipGetDevice(&C->device);
+    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&C->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device);
     size_t n = (size_t)4 * 9 * g.V;
     if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
         hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
@@ -256,14 +273,15 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
             hipMalloc(&C->Kh32, (size_t)2 * 18 * n2 * sizeof(float4)) != hipSuccess ||
             hipMalloc(&C->nbr_eo, (size_t)2 * 8 * n2 * sizeof(int)) != hipSuccess ||
             hipMalloc(&C->Uh16, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess ||
-            hipMalloc(&C->Uh32s, (size_t)2 * 36 * n2 * sizeof(cx<float>)) != hipSuccess ||
-            hipMalloc(&C->Uh16s, (size_t)2 * 36 * n2 * sizeof(cx<f16>)) != hipSuccess) {
+            hipMalloc(&C->Uh32s, (size_t)2 * 72 * n2 * sizeof(cx<float>)) != hipSuccess ||
+            hipMalloc(&C->Uh16s, (size_t)2 * 72 * n2 * sizeof(cx<f16>)) != hipSuccess) {
             ddwc_destroy(C);
             return fail(DDWC_EHIP, "device allocation of the even-odd fields failed");
         }
-        launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Uh32s, C->Kh64, C->Kh32, C->nbr_eo);
+        launch_eo_setup(ex, g, C->U64, C->K64, C->nbr, C->Uh64, C->Uh32, C->Kh64, C->Kh32, C->nbr_eo);
+        launch_eo_links_own(ex, (unsigned)n2, C->Uh32, C->nbr_eo, C->Uh32s);
         launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32, C->Uh16);
-        launch_links_to_half(ex, (size_t)2 * 36 * n2, C->Uh32s, C->Uh16s);
+        launch_links_to_half(ex, (size_t)2 * 72 * n2, C->Uh32s, C->Uh16s);
     }
     double* fpp = nullptr;
     if (ws_t(C, "fp_part", FP_BLOCKS, &fpp) != DDWC_OK) {
@@ -448,8 +466,9 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
 }
 
 // ------------------------------------------------------------------ even-odd global solver
-// Half-field operator data.  site_major selects the site-major link copies (FP32, FP16) that the
-// RHS-innermost kernels of the global solver read; the block solver and FP64 read entry-major links.
+// Half-field operator data.  site_major selects the own-site link records (FP32, FP16) that the
+// RHS-innermost kernels of the global solver read (U[p]: the records of parity p); the block
+// solver and FP64 read entry-major links.
 template <class R>
 static EoFields<R> eo_fields(const ddwc_ctx* C, bool site_major = false);
 template <>
@@ -468,7 +487,7 @@ EoFields<float> eo_fields<float>(const ddwc_ctx* C, bool site_major) {
     EoFields<float> F;
     F.n2 = C->g.V / 2;
     for (int p = 0; p < 2; ++p) {
-        F.U[p] = (site_major ? C->Uh32s : C->Uh32) + (size_t)p * 36 * F.n2;
+        F.U[p] = site_major ? C->Uh32s + (size_t)p * 72 * F.n2 : C->Uh32 + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
         F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
     }
@@ -480,7 +499,7 @@ EoFields<H16> eo_fields<H16>(const ddwc_ctx* C, bool site_major) {
     EoFields<H16> F;
     F.n2 = C->g.V / 2;
     for (int p = 0; p < 2; ++p) {
-        F.U[p] = (site_major ? C->Uh16s : C->Uh16) + (size_t)p * 36 * F.n2;
+        F.U[p] = site_major ? C->Uh16s + (size_t)p * 72 * F.n2 : C->Uh16 + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
         F.nbr[p] = C->nbr_eo + (size_t)p * 8 * F.n2;
     }
@@ -586,9 +605,9 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     const int ntf = tiles_of(g.V);
     // low-precision fields RHS-innermost: the RHS of a site share its links, clover and table
     // (FP16 fields, whose scale plane follows the word planes, always are)
-    if (h16 && nrhs > WG) return fail(DDWC_EINVAL, "the FP16 inner solver takes at most 256 RHS");
-    const bool ri = h16 || (nrhs > 1 && nrhs <= WG);
-    const EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read site-major links
+    CK(check_h16_global(C, nrhs, h16 ? DDWC_MIXED16 : DDWC_MIXED32));
+    const bool ri = h16 || (nrhs > 1 && nrhs <= WG && ri_fits(n2, nrhs));
+    const EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read own-site link records
     const int ntR = vector_tiles(n2, nrhs, ri);
     const double mass4 = 4.0 + mass;
     const double2* A64;
@@ -786,6 +805,20 @@ struct BlockInfo {
     long long block_iters = 0;  // summed over blocks and RHS
 };
 
+// Floating-point operations of one inner BiCGStab iteration of a block solve, per even site (eo)
+// or per block site: two applications of the block operator, each a pass over both parities
+// (eo) or one full pass, with 180 flops per hop term (spin projection, two 3x3 complex
+// products, reconstruction) over the hops that stay inside the block (2 sum_mu (b_mu - 1)/b_mu
+// per site on average) and 540 per site for the two packed Hermitian 6x6 blocks, plus about 400
+// for the vector updates and dot products.  The block class of the profiler accumulates this
+// model: the block kernels work from LDS and the caches, so their roofline is the ALU.
+static double block_flops_per_site(const Geom& g, bool eo) {
+    double hops = 0;
+    for (int mu = 0; mu < 4; ++mu) hops += 2.0 * (g.b[mu] - 1) / g.b[mu];
+    const double pass = hops * 180.0 + 540.0;
+    return 2.0 * (eo ? 2.0 : 1.0) * pass + 400.0;
+}
+
 // Even-odd preconditioned block solves (every block extent even): FP64 prep, then FP64
 // defect-correction steps around the persistent inner solver until every block of the
 // colour has ||b'_e - M_k x_e|| <= tol ||b_k||, then the odd sites.
@@ -799,10 +832,13 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     CK(get_ainv(C, ex, mass4, &A64, &A32));
     const EoFields<double> F64 = eo_fields<double>(C);
     const unsigned n2 = F64.n2;
-    const bool h16 = prec == DDWC_MIXED16;
+    // blocks whose parity fits the LDS-resident kernel run it in FP32 for both low precisions
+    const bool lds = !fp64 && C->opt_blk_kernel == 0 && blk_lds_fits(g, C->lds_max);
+    const bool h16 = prec == DDWC_MIXED16 && !lds;
     const size_t hw64 = (size_t)nrhs * 12 * n2;
     // the correction vector (slot 5) is kept in FP32 when the others are FP16
-    const size_t slabS = blk_slab_bytes(prec, n2), slabX = blk_slab_bytes(h16 ? DDWC_MIXED32 : prec, n2);
+    const int sprec = lds ? DDWC_MIXED32 : prec;
+    const size_t slabS = blk_slab_bytes(sprec, n2), slabX = blk_slab_bytes(h16 ? DDWC_MIXED32 : sprec, n2);
     double2 *bpe, *re, *xe, *to;
     CK(ws_t(C, "be_bpe", hw64, &bpe));
     CK(ws_t(C, "be_re", hw64, &re));
@@ -813,6 +849,7 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     for (int k = 0; k < 7; ++k)
         CK(ws_get(C, std::string(names[k]) + (fp64 ? "64" : h16 ? "16" : "32"), (k == 5 ? slabX : slabS) * nrhs,
                   &w[k]));
+    // (the LDS-resident kernel uses slots 1, 3, 5 only)
     const size_t nb = (size_t)nrhs * g.NBc;
     double *bb, *rr;
     int* iters;
@@ -851,6 +888,9 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
         if (fp64) {
             const EoFields<double> F = F64;
             launch_blk_inner<double>(ex, g, F, A64, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
+        } else if (lds) {
+            const EoFields<float> F = eo_fields<float>(C);
+            launch_blk_lds(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
         } else if (h16) {
             const EoFields<H16> F = eo_fields<H16>(C);
             launch_blk_inner<H16>(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
@@ -871,14 +911,7 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
         info->relres = fmax(info->relres, worst);
         info->block_iters += isum;
     }
-    if (C->prof.on) {
-        // algorithmic bytes of the persistent inner kernel per even site and iteration: 25
-        // half-spinor passes and two applications of M_k, each reading both parities' links
-        // twice (16 links per even-odd pair), the even clover and the odd inverse.
-        const double S = h16 ? 52.0 : 24.0 * (fp64 ? 8 : 4);
-        const double Gk = 16 * 18.0 * (fp64 ? 8 : h16 ? 2 : 4) + 144.0 * (fp64 ? 8 : 4);
-        C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * (25 * S + 2 * Gk);
-    }
+    if (C->prof.on) C->prof.bytes[DDWC_K_BLOCK] += (double)isum * g.hvb * block_flops_per_site(g, true);
     if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
     if (!converged) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");
     return DDWC_OK;
@@ -940,18 +973,7 @@ static int block_internal(ddwc_ctx* C, Exec& ex, int colour, double mass, const 
         info->relres = fmax(info->relres, worst);
         info->block_iters += sum;
     }
-    if (C->prof.on) {
-        // algorithmic bytes of this launch: per block site, an inner iteration streams 19 spinors
-        // and twice the links + clover (two operator applications); a defect-correction step
-        // streams 5 inner spinors, 3 FP64 spinors, the FP64 x update and the FP64 links + clover;
-        // the setup reads b and writes r64 and x once.
-        const double S = 24.0 * (fp64 ? 8 : 4), G = 144.0 * (fp64 ? 8 : 4);
-        double b = 0;
-        long long souter = 0;
-        for (size_t k = 0; k < nb; ++k) souter += ou[k];
-        b = (double)sum * (19 * S + 2 * G) + (double)souter * (2304.0 + 5 * S) + 576.0 * (double)nb;
-        C->prof.bytes[DDWC_K_BLOCK] += b * g.Vb;
-    }
+    if (C->prof.on) C->prof.bytes[DDWC_K_BLOCK] += (double)sum * g.Vb * block_flops_per_site(g, false);
     if (!finite) return fail(DDWC_ENONFINITE, "non-finite residual in a block solve");
     if (worst > tol) return fail(DDWC_ENOCONV, "a block solve did not reach its tolerance within maxit");
     return DDWC_OK;
@@ -981,7 +1003,7 @@ extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void
         launch_dslash<double>(ex, g, C->U64, C->K64, mass4, a, b, nrhs, DDWC_K_DSLASH64,
                               ddwc_dslash_bytes(C, nrhs, DDWC_FP64));
         launch_export<double>(ex, g, b, out, nrhs, MASK_ALL);
-    } else if (nrhs > 1 && nrhs <= WG) {
+    } else if (nrhs > 1 && nrhs <= WG && ri_fits((unsigned)g.V, nrhs)) {
         // several RHS: RHS-innermost fields, the RHS of a site share its links and clover
         float4 *a, *b;
         CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));
@@ -1029,6 +1051,7 @@ extern "C" int ddwc_solve(ddwc_ctx* C, double kappa, const void* b, void* x, int
                           int prec, ddwc_stats* stats, void* stream) {
     auto t0 = std::chrono::steady_clock::now();
     CK(check_common(C, kappa, nrhs, prec));
+    CK(check_h16_global(C, nrhs, prec));
     if (!b || !x) return fail(DDWC_EINVAL, "null vector");
     if (!(tol > 0) || maxit < 1) return fail(DDWC_EINVAL, "tol must be > 0 and maxit >= 1");
     Exec ex = make_exec(C, stream);
@@ -1240,6 +1263,7 @@ extern "C" int ddwc_schur_apply(ddwc_ctx* C, double kappa, int inverse, const vo
     CK(check_common(C, kappa, nrhs, prec));
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
     if (inverse != 0 && inverse != 1) return fail(DDWC_EINVAL, "inverse must be 0 or 1");
+    if (inverse) CK(check_h16_global(C, nrhs, prec));
     if (!(tol > 0)) return fail(DDWC_EINVAL, "tol must be > 0");
     Exec ex = make_exec(C, stream);
     double2 *e, *o;
@@ -1354,11 +1378,36 @@ static int combine_steps(const double* x_host, int n_interp, int nrhs, int n_f, 
     return DDWC_OK;
 }
 
+extern "C" int ddwc_log_w_combine(const double* x_host, int n_interp, int n_hit, int n_f, double* log_w,
+                                  double* step_var_host, double* gx_host) {
+    if (!x_host || !log_w) return fail(DDWC_EINVAL, "null argument");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (n_hit < 1 || n_hit > 65535) return fail(DDWC_EINVAL, "n_hit must be in [1, 65535]");
+    if (n_f != 1 && n_f != 2) return fail(DDWC_EINVAL, "n_f must be 1 or 2");
+    if (gx_host && n_f != 2) return fail(DDWC_EINVAL, "the gradient is defined for two flavours only");
+    const size_t nx = (size_t)n_interp * n_hit * (n_f == 2 ? 1 : 2);
+    for (size_t k = 0; k < nx; ++k)
+        if (!isfinite(x_host[k])) return fail(DDWC_EINVAL, "non-finite exponent");
+    if (gx_host) {
+        // d log W_i / d x_ij = -exp(-x_ij) / sum_j exp(-x_ij), formed relative to the step's largest -x
+        for (int i = 0; i < n_interp; ++i) {
+            const double* x = x_host + (size_t)i * n_hit;
+            double amax = -x[0];
+            for (int j = 1; j < n_hit; ++j) amax = fmax(amax, -x[j]);
+            double sw = 0;
+            for (int j = 0; j < n_hit; ++j) sw += exp(-x[j] - amax);
+            for (int j = 0; j < n_hit; ++j) gx_host[(size_t)i * n_hit + j] = -exp(-x[j] - amax) / sw;
+        }
+    }
+    return combine_steps(x_host, n_interp, n_hit, n_f, log_w, step_var_host);
+}
+
 extern "C" int ddwc_det_ratio_estimate(ddwc_ctx* C, double kappa1, double kappa2, int n_interp, int op, int n_f,
                                        const void* eta, int n_hit, double tol, int prec, double* x_host,
                                        double* log_w_gl, double* step_var_host, ddwc_stats* stats, void* stream) {
     auto t0 = std::chrono::steady_clock::now();
     CK(check_common(C, kappa1, n_hit, prec));
+    CK(check_h16_global(C, n_hit, prec));
     if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
     if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
     if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
@@ -1514,6 +1563,7 @@ extern "C" int ddwc_det_ratio_grad(ddwc_ctx* C, double kappa1, double kappa2, in
                                    ddwc_stats* stats, void* stream) {
     auto t0 = std::chrono::steady_clock::now();
     CK(check_common(C, kappa1, n_hit, prec));
+    CK(check_h16_global(C, n_hit, prec));
     if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
     if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
     if (op != DDWC_OP_FULL && op != DDWC_OP_SCHUR) return fail(DDWC_EINVAL, "op must be FULL (0) or SCHUR (1)");
@@ -1727,6 +1777,54 @@ extern "C" int ddwc_block_logdet(ddwc_ctx* C, double kappa, int colour, double* 
     return DDWC_OK;
 }
 
+extern "C" int ddwc_log_w_blocks(ddwc_ctx* C, double kappa1, double kappa2, double* out_host, void* stream) {
+    CK(check_common(C, kappa1, 1, DDWC_FP64));
+    if (!(kappa2 > 0) || !isfinite(kappa2)) return fail(DDWC_EINVAL, "kappa2 must be positive and finite");
+    if (!out_host) return fail(DDWC_EINVAL, "null argument");
+    // 2 sum_k [ln|det D_k(m2)| - ln|det D_k(m1)|] over the blocks of both colours; the sums run per
+    // colour and mass in block order, then in the fixed order (black m2, black m1, white m2, white m1)
+    std::vector<double> la(C->g.NBc);
+    double tot = 0;
+    for (int c = DDWC_BLACK; c <= DDWC_WHITE; ++c)
+        for (int k = 0; k < 2; ++k) {
+            CK(ddwc_block_logdet(C, k == 0 ? kappa2 : kappa1, c, la.data(), nullptr, stream));
+            double s = 0;
+            for (double v : la) s += v;
+            tot += k == 0 ? s : -s;
+        }
+    *out_host = 2.0 * tot;
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_log_w_nested_total(ddwc_ctx* O, ddwc_ctx* I, double kappa1, double kappa2, int n_interp,
+                                       const void* eta_gl, int n_hit_gl, const void* eta_black,
+                                       const void* eta_white, int n_hit_nested, double tol, int prec,
+                                       double* parts_host, ddwc_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!eta_gl || !eta_black || !eta_white || !parts_host) return fail(DDWC_EINVAL, "null argument");
+    if (n_interp < 1 || n_interp > 4096) return fail(DDWC_EINVAL, "n_interp must be in [1, 4096]");
+    if (n_hit_gl < 1 || n_hit_gl > 65535 || n_hit_nested < 1 || n_hit_nested > 65535)
+        return fail(DDWC_EINVAL, "n_hit must be in [1, 65535]");
+    double parts[5] = {0, 0, 0, 0, 0};
+    std::vector<double> x((size_t)n_interp * std::max(n_hit_gl, n_hit_nested));
+    ddwc_stats st;
+    // the nested calls check both contexts (same lattice, links, c_sw, boundary; dividing blocks) first
+    const void* eta_c[2] = {eta_black, eta_white};
+    for (int c = DDWC_BLACK; c <= DDWC_WHITE; ++c)
+        CK(ddwc_det_ratio_nested(O, I, c, kappa1, kappa2, n_interp, 2, eta_c[c], n_hit_nested, tol, prec, x.data(),
+                                 &parts[1 + c], nullptr, nullptr, stream));
+    CK(ddwc_det_ratio_estimate(O, kappa1, kappa2, n_interp, DDWC_OP_SCHUR, 2, eta_gl, n_hit_gl, tol, prec, x.data(),
+                               &parts[0], nullptr, &st, stream));
+    CK(ddwc_log_w_blocks(I, kappa1, kappa2, &parts[3], stream));
+    parts[4] = ((parts[0] + parts[1]) + parts[2]) + parts[3];
+    for (int k = 0; k < 5; ++k) parts_host[k] = parts[k];
+    if (stats) {
+        *stats = st;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return DDWC_OK;
+}
+
 extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
     CK(check_ctx(C));
     switch (option) {
@@ -1756,6 +1854,10 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
             C->opt_blk_lds = value;
             break;
         }
+        case DDWC_OPT_BLOCK_KERNEL:
+            if (value != 0 && value != 1) return fail(DDWC_EINVAL, "block kernel must be 0 or 1");
+            C->opt_blk_kernel = value;
+            break;
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1771,6 +1873,7 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_BLOCK_THREADS: *value = C->opt_blk_threads; break;
         case DDWC_OPT_SOLVER: *value = C->opt_solver; break;
         case DDWC_OPT_BLOCK_LDS: *value = C->opt_blk_lds; break;
+        case DDWC_OPT_BLOCK_KERNEL: *value = C->opt_blk_kernel; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;
@@ -1869,6 +1972,19 @@ extern "C" int ddwc_profile_read(ddwc_ctx* C, int kclass, long long* launches, d
     if (launches) *launches = C->prof.launches[kclass];
     if (total_ms) *total_ms = C->prof.ms[kclass];
     if (bytes) *bytes = C->prof.bytes[kclass];
+    return DDWC_OK;
+}
+
+extern "C" int ddwc_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst) return fail(DDWC_EINVAL, "null buffer");
+    if (bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+        return fail(DDWC_EINVAL, "bytes and both addresses must be multiples of 16");
+    Exec ex;
+    ex.stream = (hipStream_t)stream;
+    ex.prof = nullptr;
+    ex.nbr = nullptr;
+    if (bytes) launch_stream_copy(ex, (const float4*)src, (float4*)dst, bytes / 16);
+    HC(hipGetLastError());
     return DDWC_OK;
 }
 

@@ -399,6 +399,271 @@ __global__ __launch_bounds__(be_inner_max<S>()) void k_blk_inner(Geom g, EoField
     if (threadIdx.x == 0) iters[k.key] += it;
 }
 
+// ------------------------------------------------------------------ LDS-resident inner solver
+// The same BiCGStab on M_k as k_blk_inner, one workgroup per (block, RHS), for block parities of
+// at most BL_MAX sites: one thread per local half index l < hvb owns the even site and the odd
+// site of that index.  The operand of M_k (p, then s; even sites) and the odd intermediate
+// A_oo^-1 H^k_oe (operand) are staged in LDS (2 x hvb x 96 bytes, 124 KB for a 6^4 block), so
+// the in-block neighbour gathers of both passes, and each site's own operand, are LDS reads.
+// r, p, v, rh and the correction e of a thread's own site are global slabs (slots 0, 2, 3, 1,
+// 5), each read or written once or twice per iteration, so that no iterate stays live in
+// registers across the stencil passes (s and t are formed in registers from the LDS operand and
+// the even pass).  Links and clover are read from global
+// memory: the RHS of one block run on one XCD and share them in its L2.  Arithmetic FP32, dot
+// products accumulated in FP64 as in k_blk_inner.
+constexpr int BL_MAX = 768;  // 12 waves: 3 per SIMD at up to 168 VGPRs
+
+__device__ __forceinline__ void lds_load(const float4* __restrict__ L, unsigned HV, unsigned li, cx<float> q[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float4 w = L[k * HV + li];
+        q[2 * k] = mk(w.x, w.y);
+        q[2 * k + 1] = mk(w.z, w.w);
+    }
+}
+__device__ __forceinline__ void lds_store(float4* __restrict__ L, unsigned HV, unsigned li, const cx<float> q[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        L[k * HV + li] = make_float4(q[2 * k].re, q[2 * k].im, q[2 * k + 1].re, q[2 * k + 1].im);
+}
+
+// acc = sum over the hops of half site s that stay inside its block (neighbour t with
+// t - h0 < HV) of (1 -+ g_mu) W q(t), q read from LDS at t - h0; forward links Uf at s, backward
+// links Ub at t (entry-major [4][9][n2]); nbr is the half-field table [8][n2] of s's parity.
+// Software-pipelined: while hop d is applied, the link of hop d + 1 and the table entry of hop
+// d + 2 are in flight (about one global latency per pass instead of one or two per hop).
+__device__ __forceinline__ void lds_hops(unsigned n2, unsigned s, unsigned h0, unsigned HV,
+                                         const float4* __restrict__ L, const cx<float>* __restrict__ Uf,
+                                         const cx<float>* __restrict__ Ub, const int* __restrict__ nbr,
+                                         cx<float> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = mk(0.f, 0.f);
+    int e = at(nbr, s), en = at(nbr + (size_t)n2, s);
+    cx<float> u[9];
+    {
+        const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+        if (t - h0 < HV) hop_link<LK_ENTRY>(Uf, Ub, n2, 0, s, t, u);
+    }
+#pragma unroll 1
+    for (int d = 0; d < 8; ++d) {
+        const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+        int enn = 0;
+        if (d + 2 < 8) enn = at(nbr + (size_t)(d + 2) * n2, s);
+        cx<float> un[9];
+        if (d + 1 < 8) {
+            const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
+            if (tn - h0 < HV) hop_link<LK_ENTRY>(Uf, Ub, n2, d + 1, s, tn, un);
+        }
+        const unsigned li = t - h0;
+        if (li < HV) {
+            cx<float> q[12];
+            lds_load(L, HV, li, q);
+            if (e < 0) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = -q[c];
+            }
+            hop_dispatch<float>(d, u, q, acc);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] = un[k];
+        e = en;
+        en = enn;
+    }
+}
+
+// w = A_oo^-1 H^k_oe q at odd half site j (q: even operand in LDS L).
+__device__ __forceinline__ void odd_lds(const EoFields<float>& F, const float4* __restrict__ Ainv, unsigned j,
+                                        unsigned h0, unsigned HV, const float4* __restrict__ L, cx<float> w[12]) {
+    cx<float> acc[12];
+    lds_hops(F.n2, j, h0, HV, L, F.U[1], F.U[0], F.nbr[1], acc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = mk(0.f, 0.f);
+    apply_diag<float>(Ainv, F.n2, j, 0.f, acc, w, 0.f);
+}
+
+// y = (4 + m + C) q_e - 1/4 H^k_eo q_o at even half site i: q_e the even operand in LDS Le (own
+// site, local index l), q_o the odd intermediate in LDS Lo.
+__device__ __forceinline__ void even_lds(const EoFields<float>& F, float m4, unsigned i, unsigned l, unsigned h0,
+                                         unsigned HV, const float4* __restrict__ Le, const float4* __restrict__ Lo,
+                                         cx<float> y[12]) {
+    lds_hops(F.n2, i, h0, HV, Lo, F.U[0], F.U[1], F.nbr[0], y);
+    cx<float> c[12];
+    lds_load(Le, HV, l, c);
+    apply_diag<float>(F.K[0], F.n2, i, m4, c, y, -0.25f);
+}
+
+__global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, const float4* __restrict__ Ainv,
+                                                    const double2* __restrict__ re, double2* __restrict__ xe,
+                                                    float4* __restrict__ rg, float4* __restrict__ rhg, float4* __restrict__ pg,
+                                                    float4* __restrict__ vg, float4* __restrict__ eg,
+                                                    const double* __restrict__ bb, const double* __restrict__ rr,
+                                                    double mass4, double tol, double inner_floor, int maxit,
+                                                    int* iters, int colour, int nrhs) {
+    extern __shared__ float4 bl_lds[];
+    __shared__ double red_lds[3 * 16];
+    const BlkIdx k = blk_idx(g, colour, nrhs);
+    const double b2 = bb[k.key], r2 = rr[k.key];
+    if (!(b2 > 0) || !(r2 > tol * tol * b2) || !isfinite(r2)) return;  // uniform over the workgroup
+    const unsigned n2 = F.n2, HV = (unsigned)g.hvb, h0 = k.h0;
+    float4* op = bl_lds;          // operand of M_k on the even sites of the block
+    float4* tp = bl_lds + 6 * HV;  // A_oo^-1 H^k_oe (operand) on the odd sites
+    const unsigned l = threadIdx.x;
+    const bool act = l < HV;
+    unsigned i = h0 + (act ? l : 0u);  // half index of this thread's even and odd site
+    const size_t oh = (size_t)k.rhs * 12 * n2, oR = (size_t)k.rhs * 6 * n2;
+    rg += oR;
+    rhg += oR;
+    pg += oR;
+    vg += oR;
+    eg += oR;
+    const float m4 = (float)mass4;
+    const double rn = sqrt(r2), sc = 1.0 / rn;
+    double eps = 0.5 * tol * sqrt(b2) / rn;
+    if (eps < inner_floor) eps = inner_floor;
+    double red[3] = {0, 0, 0};
+    if (act) {
+        cx<double> a[12];
+        load_spinor(re + oh, n2, i, a);
+        cx<float> r[12], z[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            r[c] = mk((float)(sc * a[c].re), (float)(sc * a[c].im));
+            z[c] = mk(0.f, 0.f);
+        }
+        store_spinor(rg, n2, i, r);
+        store_spinor(rhg, n2, i, r);
+        store_spinor(pg, n2, i, r);
+        store_spinor(eg, n2, i, z);
+        lds_store(op, HV, l, r);
+        red[0] = acc_nrm(r);
+    }
+    block_sum<1>(red, red_lds);  // (its barriers also publish the operand)
+    cx<double> rho = mk(red[0], 0.0);
+    const double thr2 = eps * eps * red[0];
+    int it = 0;
+    while (it < maxit) {
+        // an opaque redefinition of the site index: keeps the compiler from hoisting every per-lane
+        // 64-bit address out of the loop (they would not fit the 168 registers and would spill)
+        asm volatile("" : "+v"(i));
+        // v = M_k p, (rh, v)
+        if (act) {
+            cx<float> w[12];
+            odd_lds(F, Ainv, i, h0, HV, op, w);
+            lds_store(tp, HV, l, w);
+        }
+        __syncthreads();
+        red[0] = red[1] = red[2] = 0;
+        if (act) {
+            cx<float> v[12], h[12];
+            even_lds(F, m4, i, l, h0, HV, op, tp, v);
+            store_spinor(vg, n2, i, v);
+            load_spinor(rhg, n2, i, h);
+            acc_dot(h, v, red[0], red[1]);
+        }
+        block_sum<2>(red, red_lds);
+        if (!(red[0] * red[0] + red[1] * red[1] > 0)) break;
+        const cx<float> alpha = cdiv_r<float>(rho, mk(red[0], red[1]));
+        // s = r - alpha v (kept in r), staged as the operand
+        if (act) {
+            cx<float> v[12], r[12];
+            load_spinor(vg, n2, i, v);
+            load_spinor(rg, n2, i, r);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) r[c] = r[c] - alpha * v[c];
+            lds_store(op, HV, l, r);
+        }
+        __syncthreads();
+        // t = M_k s, (t, s), (t, t)
+        if (act) {
+            cx<float> w[12];
+            odd_lds(F, Ainv, i, h0, HV, op, w);
+            lds_store(tp, HV, l, w);
+        }
+        __syncthreads();
+        red[0] = red[1] = red[2] = 0;
+        cx<float> t[12];
+        if (act) {
+            even_lds(F, m4, i, l, h0, HV, op, tp, t);
+            cx<float> r[12];
+            lds_load(op, HV, l, r);
+            acc_dot(t, r, red[0], red[1]);
+            red[2] = acc_nrm(t);
+        }
+        block_sum<3>(red, red_lds);
+        cx<float> omega = mk(0.f, 0.f);
+        if (red[2] > 0) omega = mk((float)(red[0] / red[2]), (float)(red[1] / red[2]));
+        // e += alpha p + omega s ; r = s - omega t ; (rh, r), (r, r)
+        red[0] = red[1] = red[2] = 0;
+        if (act) {
+            cx<float> e[12], pp[12], r[12];
+            lds_load(op, HV, l, r);
+            load_spinor(eg, n2, i, e);
+            load_spinor(pg, n2, i, pp);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                e[c] = e[c] + (alpha * pp[c] + omega * r[c]);
+                r[c] = r[c] - omega * t[c];
+            }
+            store_spinor(eg, n2, i, e);
+            store_spinor(rg, n2, i, r);
+            load_spinor(rhg, n2, i, pp);
+            acc_dot(pp, r, red[0], red[1]);
+            red[2] = acc_nrm(r);
+        }
+        block_sum<3>(red, red_lds);
+        ++it;
+        if (red[2] <= thr2 || !isfinite(red[2])) break;
+        if (omega.re == 0.f && omega.im == 0.f) break;
+        const double d1 = rho.re * rho.re + rho.im * rho.im;
+        if (!(d1 > 0)) break;
+        const cx<double> q = mk((red[0] * rho.re + red[1] * rho.im) / d1, (red[1] * rho.re - red[0] * rho.im) / d1);
+        const double d2 = (double)omega.re * omega.re + (double)omega.im * omega.im;
+        const cx<double> ao = mk(((double)alpha.re * omega.re + (double)alpha.im * omega.im) / d2,
+                                 ((double)alpha.im * omega.re - (double)alpha.re * omega.im) / d2);
+        const cx<float> beta = mk((float)(q.re * ao.re - q.im * ao.im), (float)(q.re * ao.im + q.im * ao.re));
+        rho = mk(red[0], red[1]);
+        // p = r + beta (p - omega v), staged as the next operand
+        if (act) {
+            cx<float> pp[12], v[12], r[12];
+            load_spinor(rg, n2, i, r);
+            load_spinor(pg, n2, i, pp);
+            load_spinor(vg, n2, i, v);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) pp[c] = r[c] + beta * (pp[c] - omega * v[c]);
+            store_spinor(pg, n2, i, pp);
+            lds_store(op, HV, l, pp);
+        }
+        __syncthreads();
+    }
+    // x_e += ||r_e|| e in FP64
+    if (act) {
+        cx<float> e[12];
+        cx<double> x[12];
+        load_spinor(eg, n2, i, e);
+        load_spinor(xe + oh, n2, i, x);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) x[c] = x[c] + mk(rn * (double)e[c].re, rn * (double)e[c].im);
+        store_spinor(xe + oh, n2, i, x);
+    }
+    if (threadIdx.x == 0) iters[k.key] += it;
+}
+
+bool blk_lds_fits(const Geom& g, int lds_max_bytes) {
+    return g.eo && g.hvb <= BL_MAX && (long long)2 * 6 * 16 * g.hvb + 3 * 16 * 8 <= lds_max_bytes;
+}
+
+void launch_blk_lds(Exec& e, const Geom& g, const EoFields<float>& F, const float4* Ainv, const double2* re,
+                    double2* xe, void* const w[7], const double* bb, const double* rr, double mass4, double tol,
+                    int maxit, int* iters, int colour, int nrhs) {
+    Timed t(e, 2, 0);
+    const int threads = ((g.hvb + 63) / 64) * 64;
+    const size_t lds = (size_t)2 * 6 * g.hvb * sizeof(float4);
+    // the inner solve stops at this relative residual at the least (FP32's reach)
+    k_blk_lds<<<g.NBc * nrhs, threads, lds, e.stream>>>(g, F, Ainv, re, xe, (float4*)w[0], (float4*)w[1], (float4*)w[2],
+                                                        (float4*)w[3], (float4*)w[5], bb, rr, mass4, tol, 2e-6,
+                                                        maxit, iters, colour, nrhs);
+}
+
 void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
                      double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs) {
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"

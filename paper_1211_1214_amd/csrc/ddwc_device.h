@@ -323,6 +323,31 @@ DDWC_HD void load_link_l(const cx<L>* __restrict__ U, unsigned V, int mu, unsign
     }
 }
 
+// Link layouts of the hop kernels: LK_ENTRY entry-major [4][9][n] (forward links at s from Uf,
+// backward links at the neighbour t from Ub), LK_SITE site-major [n][4][9] (same roles),
+// LK_OWN own-site records [n][8][9] of Uf: for each site the eight links its hops use, d = 2 mu
+// holding U_mu(x) and d = 2 mu + 1 holding U_mu(x - mu), so that every hop reads its link from
+// the site's own contiguous record (no gather of backward links).
+enum LinkLayout { LK_ENTRY = 0, LK_SITE = 1, LK_OWN = 2 };
+
+template <int LK, class R, class L>
+DDWC_HD void hop_link(const cx<L>* __restrict__ Uf, const cx<L>* __restrict__ Ub, unsigned n, int d, unsigned s,
+                      unsigned t, cx<R> u[9]) {
+    if (LK == LK_OWN) {
+        const cx<L>* p = Uf + ((size_t)s * 8 + d) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const cx<L> w = p[k];
+            u[k] = mk((R)w.re, (R)w.im);
+        }
+        return;
+    }
+    if (d & 1)
+        load_link_l<LK == LK_SITE>(Ub, n, d >> 1, t, u);
+    else
+        load_link_l<LK == LK_SITE>(Uf, n, d >> 1, s, u);
+}
+
 // FP16 spinors: words k = 0..2 hold complex 4k .. 4k + 3; the scale plane follows the three
 // word planes of the field (f is the field base, `stride` its plane length).
 DDWC_HD float* scale_plane(hw16* f, unsigned stride) { return (float*)(f + 3 * (size_t)stride); }
@@ -533,8 +558,8 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 //
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
-// entry-major [4][9][n], or site-major [n][4][9] with SITE_MAJOR.
-template <class R, int HOPS, bool PIPE, bool SITE_MAJOR = false, class W, class L>
+// in the layout LK (LinkLayout; Uf's own-site records with LK_OWN).
+template <class R, int HOPS, bool PIPE, int LK = LK_ENTRY, class W, class L>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
                      const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
                      unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
@@ -553,10 +578,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             if (take) {
                 cx<R> q[12], u[9];
                 load_spinor(in, sstride, t * smul + sadd, q);
-                if (d & 1)
-                    load_link_l<SITE_MAJOR>(Ub, n, d >> 1, t, u);
-                else
-                    load_link_l<SITE_MAJOR>(Uf, n, d >> 1, s, u);
+                hop_link<LK>(Uf, Ub, n, d, s, t, u);
                 if (e < 0) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) q[c] = -q[c];
@@ -573,8 +595,9 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
         cx<R> q[12], u[9];
         {
             const int e = ent[0];
-            load_spinor(in, sstride, (e < 0 ? (unsigned)~e : (unsigned)e) * smul + sadd, q);
-            load_link_l<SITE_MAJOR>(Uf, n, 0, s, u);
+            const unsigned t0 = e < 0 ? (unsigned)~e : (unsigned)e;
+            load_spinor(in, sstride, t0 * smul + sadd, q);
+            hop_link<LK>(Uf, Ub, n, 0, s, t0, u);
         }
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
@@ -591,10 +614,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
                 load_spinor(in, sstride, tn * smul + sadd, qn);
-                if ((d + 1) & 1)
-                    load_link_l<SITE_MAJOR>(Ub, n, (d + 1) >> 1, tn, un);
-                else
-                    load_link_l<SITE_MAJOR>(Uf, n, (d + 1) >> 1, s, un);
+                hop_link<LK>(Uf, Ub, n, d + 1, s, tn, un);
             }
             if (take) {
                 if (e < 0) {

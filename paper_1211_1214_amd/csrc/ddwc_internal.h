@@ -148,6 +148,9 @@ void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typen
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
                      const double* thr_rel2);
 
+// dst = src over n 16-byte words (streaming reference kernel).
+void launch_stream_copy(Exec& e, const float4* src, float4* dst, size_t n);
+
 // n double2 words of reproducible values in [-1/2, 1/2) (autotuner inputs).
 void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed);
 
@@ -200,10 +203,12 @@ struct EoFields {
 
 // FP16 copy of n FP32 complex link entries.
 void launch_links_to_half(Exec& e, size_t n, const cx<float>* src, cx<f16>* dst);
-// Half-field links: entry-major Uh64, Uh32 [2][4][9][V/2], and the site-major FP32 copy Uh32s
-// [2][V/2][4][9] read by the RHS-innermost kernels of the global solver.
+// Half-field links: entry-major Uh64, Uh32 [2][4][9][V/2].
 void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
-                     cx<double>* Uh64, cx<float>* Uh32, cx<float>* Uh32s, double2* Kh64, float4* Kh32, int* nbr_eo);
+                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo);
+// Own-site link records [2][V/2][8][9] (LK_OWN) read by the RHS-innermost kernels of the global
+// solver, from Uh32 and the half-field neighbour tables.
+void launch_eo_links_own(Exec& e, unsigned n2, const cx<float>* Uh32, const int* nbr_eo, cx<float>* Lown);
 void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
 void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs);
 void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);
@@ -232,6 +237,13 @@ template <class S>
 void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
                       const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,
                       double mass4, double tol, int maxit, int* iters, int colour, int nrhs);
+// The LDS-resident FP32 inner solver (both staged block fields in LDS, per-site iterates in
+// registers): whether it takes this geometry with lds_max_bytes of LDS per workgroup, and its
+// launch (slabs w[1], w[3], w[5] hold rh, v and the correction in FP32).
+bool blk_lds_fits(const Geom& g, int lds_max_bytes);
+void launch_blk_lds(Exec& e, const Geom& g, const EoFields<float>& F, const float4* Ainv, const double2* re,
+                    double2* xe, void* const w[7], const double* bb, const double* rr, double mass4, double tol,
+                    int maxit, int* iters, int colour, int nrhs);
 // bytes of one RHS of a block-solver vector in the storage of precision `prec` (n2 = V/2)
 size_t blk_slab_bytes(int prec, unsigned n2);
 

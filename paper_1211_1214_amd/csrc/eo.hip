@@ -8,8 +8,7 @@ namespace ddwc {
 // ------------------------------------------------------------------ setup
 __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const double2* __restrict__ K64,
                            const int* __restrict__ nbr, cx<double>* __restrict__ Uh64, cx<float>* __restrict__ Uh32,
-                           cx<float>* __restrict__ Uh32s, double2* __restrict__ Kh64, float4* __restrict__ Kh32,
-                           int* __restrict__ nbr_eo) {
+                           double2* __restrict__ Kh64, float4* __restrict__ Kh32, int* __restrict__ nbr_eo) {
     const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= (unsigned)g.V) return;
     const size_t V = g.V, V2 = g.V / 2;
@@ -21,7 +20,6 @@ __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const dou
             const size_t o = (((size_t)p * 4 + mu) * 9 + k) * V2 + i;
             Uh64[o] = u;
             Uh32[o] = mk((float)u.re, (float)u.im);
-            Uh32s[(size_t)p * 36 * V2 + ((size_t)i * 4 + mu) * 9 + k] = mk((float)u.re, (float)u.im);
         }
     double a[72];
     for (int k = 0; k < 36; ++k) {
@@ -37,9 +35,38 @@ __global__ void k_eo_setup(Geom g, const cx<double>* __restrict__ U64, const dou
 }
 
 void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double2* K64, const int* nbr,
-                     cx<double>* Uh64, cx<float>* Uh32, cx<float>* Uh32s, double2* Kh64, float4* Kh32, int* nbr_eo) {
+                     cx<double>* Uh64, cx<float>* Uh32, double2* Kh64, float4* Kh32, int* nbr_eo) {
     Timed t(e, 4, 0);
-    k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Uh32s, Kh64, Kh32, nbr_eo);
+    k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Kh64, Kh32, nbr_eo);
+}
+
+// Own-site link records [2][n2][8][9] (LK_OWN) from the entry-major FP32 half-order links: for
+// parity p and half site i, hop d = 2 mu takes U_mu(x) (the site's own forward link) and
+// d = 2 mu + 1 takes U_mu(x - mu), the forward link of its neighbour (parity 1 - p, half index
+// from the table; the time-boundary sign stays with the table entry).
+__global__ void k_eo_links_own(unsigned n2, const cx<float>* __restrict__ Uh32, const int* __restrict__ nbr_eo,
+                               cx<float>* __restrict__ Lown) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * (size_t)n2) return;
+    const int p = idx >= n2;
+    const unsigned i = (unsigned)(idx - (size_t)p * n2);
+    for (int d = 0; d < 8; ++d) {
+        const int mu = d >> 1;
+        int q = p;
+        unsigned src = i;
+        if (d & 1) {
+            const int e = nbr_eo[((size_t)p * 8 + d) * n2 + i];
+            src = e < 0 ? (unsigned)~e : (unsigned)e;
+            q = 1 - p;
+        }
+        for (int k = 0; k < 9; ++k)
+            Lown[(idx * 8 + d) * 9 + k] = Uh32[(((size_t)q * 4 + mu) * 9 + k) * n2 + src];
+    }
+}
+
+void launch_eo_links_own(Exec& e, unsigned n2, const cx<float>* Uh32, const int* nbr_eo, cx<float>* Lown) {
+    Timed t(e, 4, 0);
+    k_eo_links_own<<<(unsigned)((2 * (size_t)n2 + 255) / 256), 256, 0, e.stream>>>(n2, Uh32, nbr_eo, Lown);
 }
 
 // FP16 copy of the FP32 half-order links (setup).
@@ -105,11 +132,12 @@ void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* h
 }
 
 // ------------------------------------------------------------------ operator kernels
-// The RHS-innermost FP32/FP16 kernels (the global solver) read site-major links; FP64 and the
-// RHS-major kernels read entry-major links (EoFields of eo_fields with site_major set alike).
+// The RHS-innermost FP32/FP16 kernels (the global solver) read own-site link records (each half
+// site's eight hop links in one contiguous record); FP64 and the RHS-major kernels read
+// entry-major links (EoFields of eo_fields with site_major set alike).
 template <class S, bool RI>
-constexpr bool site_major_links() {
-    return RI && !std::is_same<S, double>::value;
+constexpr int site_major_links() {
+    return RI && !std::is_same<S, double>::value ? LK_OWN : LK_ENTRY;
 }
 
 // Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the

@@ -8,6 +8,8 @@
 // blocks stay in the same L2.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "ddwc_internal.h"
 #include "clover_build.h"
 #include "vec_items.h"
@@ -449,6 +451,29 @@ void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed) {
     k_fill_hash<<<(unsigned)((n + 255) / 256), 256, 0, e.stream>>>(v, n, seed);
 }
 
+// ------------------------------------------------------------------ streaming reference
+// dst = src over n 16-byte words: the streaming rate the operator kernels are measured against
+// (and a transfer of known size for calibrating memory counters).  Each thread moves four words
+// per round with all four loads issued before the stores; rounds stride over the whole grid.
+__global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+void launch_stream_copy(Exec& e, const float4* src, float4* dst, size_t n) {
+    const size_t want = (n + 1023) / 1024;  // four words per thread and round
+    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), 8192);
+    k_stream_copy<<<grid, 256, 0, e.stream>>>(src, dst, n);
+}
+
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)
 __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
                                                   double* __restrict__ sums, BiState* __restrict__ st, int stage,
@@ -711,7 +736,7 @@ __global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __r
     if (!it.ok) return;
     const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
     cx<float> acc[12], c[12];
-    hop_sum<float, HOPS_ALL, true, true>((unsigned)g.V, it.i, in, Us, Us, nbr, acc, 8, (unsigned)nrhs,
+    hop_sum<float, HOPS_ALL, true, LK_SITE>((unsigned)g.V, it.i, in, Us, Us, nbr, acc, 8, (unsigned)nrhs,
                                          (unsigned)it.r, w.stride);
     load_spinor(in, w.stride, w.idx, c);
     apply_diag<float>(K, (unsigned)g.V, it.i, mass4, c, acc, -0.5f);

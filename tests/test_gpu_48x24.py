@@ -5,7 +5,9 @@ The oracle cannot redo the whole batch in seconds, so the checks are
   * the operator on every site against the C oracle (FP64 one RHS; FP32 on sampled RHS),
   * solve and block-solve residuals measured with the oracle's operator (a property that
     holds at any size),
-  * sampled exponents x_0j against the oracle values stored by tests/golden/make_golden_48x24.py.
+  * every exponent x_0j of the 12-RHS batch, log W_gl (Eq. 8) and the step variance against
+    the oracle values stored by tests/golden/make_golden_48x24.py (all solves to 1e-13),
+    |dx| <= 1e-8 max(|x|, 1) and |d log W| <= 1e-8 max(|log W|, 1).
 """
 import json
 import os
@@ -99,8 +101,16 @@ def test_48x24_exponents_against_oracle(lat48):
     etad = torch.from_numpy(eta).to(dev)
     say("48x24 estimate, mixed, 12 RHS")
     res = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad, op=dd.OP_SCHUR, tol=TOL, prec=dd.MIXED32)
+    assert sorted(map(int, gold["x_schur"])) == list(range(nhit)), "oracle values must cover every noise vector"
     for j, xo in gold["x_schur"].items():
+        say(f"48x24: x[0,{j}] = {res['x'][0, int(j)]!r}, oracle {xo!r}")
         assert abs(res["x"][0, int(j)] - xo) <= 1e-8 * max(abs(xo), 1), (j, res["x"][0, int(j)], xo)
+    lw = gold["log_w_gl"]
+    say(f"48x24: log W_gl = {res['log_w_gl']!r}, oracle {lw!r}")
+    assert abs(res["log_w_gl"] - lw) <= 1e-8 * max(abs(lw), 1)
+    # the relative variance of the weights e^-x moves by at most ~4 max|dx| relative to first order
+    v = gold["step_var"]
+    assert abs(res["step_var"][0] - v) <= 4e-8 * max(abs(res["x"]).max(), 1) * v
     say("48x24 estimate, FP64 single RHS")
     r64 = ctx.det_ratio_estimate(cfg["kappa1"], cfg["kappa2"], etad[:, :1].contiguous(), op=dd.OP_SCHUR, tol=TOL,
                                  prec=dd.FP64)

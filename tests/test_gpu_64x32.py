@@ -111,3 +111,44 @@ def test_64x32_nested():
         assert np.all(np.abs(r16["x"] - r32["x"]) <= 1e-8 * np.maximum(np.abs(r32["x"]), 1.0))
     O.close()
     I.close()
+
+
+@pytest.mark.timeout(600)
+def test_64x32_dslash_largest_rhs_batches():
+    """FP32 Dslash at 64x32^3 (V = 2^21) with 128 RHS (the largest RHS-innermost batch whose
+    component planes stay within 32-bit byte offsets) and 129 RHS (RHS-major fields).  RHS r is
+    (1 + r) times base spinor r mod 3, so a wrong plane or RHS offset changes the scale; RHS 0, 1,
+    2, 64, the last two and the last are checked on every site against the C oracle's operator."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import cref, dirac
+    cfg = inputs.WORKLOADS["64x32^3"]
+    lat, blk = cfg["lat"], cfg["blk"]
+    say("64x32 dslash: inputs")
+    U = inputs.make_links(lat, cfg["eps"], cfg["seed"])
+    dev = torch.device("cuda:0")
+    ctx = dd.Context(torch.from_numpy(U).to(dev), lat, blk, -1, cfg["csw"])
+    R = cref.CRef(U, lat, blk, cfg["csw"], -1)
+    del U
+    m = dirac.mass(cfg["kappa2"])
+    base = [inputs.make_spinor(lat, 140 + k) for k in range(3)]
+    want = [R.dslash(m, b) for b in base]
+    R.close()
+    based = [torch.from_numpy(b).to(dev) for b in base]
+    V = based[0].shape[0]
+    for nrhs in (128, 129):
+        say(f"64x32 dslash: {nrhs} RHS")
+        inp = torch.empty((nrhs, V, 4, 3), dtype=torch.complex128, device=dev)
+        for r in range(nrhs):
+            inp[r] = based[r % 3] * (1.0 + r)
+        out = ctx.dslash_apply(cfg["kappa2"], inp, prec=dd.MIXED32)
+        del inp
+        for r in (0, 1, 2, 64, nrhs - 2, nrhs - 1):
+            got = out[r].cpu().numpy() / (1.0 + r)
+            w = want[r % 3]
+            err = float(np.abs(got - w).max() / np.abs(w).max())
+            say(f"64x32 dslash: {nrhs} RHS, rhs {r}: rel err {err:.2e}")
+            assert err <= 2e-6
+        del out
+        torch.cuda.empty_cache()
+    ctx.close()

@@ -108,3 +108,53 @@ def test_empty_batch(env):
             call()
     status = binding.lib().ddwc_solve(ctx._h, 0.121, e.data_ptr(), e.data_ptr(), 0, 1e-12, 10, dd.FP64, None, None)
     assert status == binding.EINVAL
+
+
+def test_log_w_combine_through_the_abi(env):
+    """ddwc_log_w_combine (host arithmetic of the library) against the oracle's Eq. (8) combination,
+    its pinned step variance and the oracle's d log W_gl / dx; the undefined one-flavour case."""
+    from oracle import derivative, estimator
+    say("log_w_combine")
+    rng = np.random.default_rng(97)
+    x = rng.standard_normal((3, 7)) * 40 + 900.0
+    r = binding.log_w_combine(x, n_f=2, grad=True)
+    want = estimator.log_w_gl(x)
+    assert abs(r["log_w"] - want) <= 1e-13 * abs(want)
+    assert np.allclose(r["step_var"], estimator.step_variance(x), rtol=1e-12, atol=0)
+    assert np.allclose(r["gx"], derivative.log_w_weights(x), rtol=1e-12, atol=1e-300)
+    x1 = x + 1j * rng.standard_normal(x.shape)
+    r1 = binding.log_w_combine(x1, n_f=1)
+    want1 = estimator.log_w_one_flavour(x1)
+    assert abs(r1["log_w"] - want1) <= 1e-13 * abs(want1)
+    assert np.allclose(r1["step_var"], estimator.step_variance_one_flavour(x1), rtol=1e-12, atol=0)
+    neg = np.array([[1.0 + np.pi * 1j, 1.5 + 0.9 * np.pi * 1j]])
+    r2 = binding.log_w_combine(neg, n_f=1, allow=(binding.EUNDEF,))
+    assert r2["status"] == binding.EUNDEF and np.isnan(r2["log_w"])
+    for bad in (lambda: binding.log_w_combine(x1, n_f=1, grad=True),
+                lambda: binding.log_w_combine(np.array([[np.nan, 1.0]]))):
+        with pytest.raises(dd.DDWCError) as e:
+            bad()
+        assert e.value.code == binding.EINVAL
+
+
+@pytest.mark.parametrize("op,j", [(dd.OP_FULL, 0), (dd.OP_SCHUR, 2)])
+def test_one_flavour_undefined_estimate(env, op, j):
+    """One flavour on a 4^4 lattice with a large mass step (kappa 0.100 -> 0.125): for the chosen noise
+    vector the oracle's exponent has cos(Im x) < 0, so the real part of the step mean is negative
+    (Sec. 3: Eq. (11) then has no logarithm).  The estimate returns EUNDEF and a NaN log W, with
+    the exponent itself still equal to the oracle's."""
+    from oracle import estimator
+    dev = env[0]
+    say("one-flavour undefined", op, j)
+    U = inputs.make_links(LAT, 0.3, 1)
+    S = Schwarz(U, LAT, BLK, 1.0)
+    eta = inputs.make_noise_batch(LAT, 60, 1, 8)[:, [j]]
+    want = estimator.exponents(S, dirac.mass(0.100), dirac.mass(0.125), eta,
+                               "full" if op == dd.OP_FULL else "schur", "diff", n_f=1)
+    assert np.cos(want[0, 0].imag) < 0
+    ctx = dd.Context(T(U, dev), LAT, BLK, -1, 1.0)
+    r = ctx.det_ratio_estimate(0.100, 0.125, T(eta, dev), op=op, tol=1e-12, prec=dd.MIXED32, n_f=1,
+                               allow=(binding.EUNDEF,))
+    ctx.close()
+    assert r["status"] == binding.EUNDEF and np.isnan(r["log_w_gl"])
+    assert abs(r["x"][0, 0] - want[0, 0]) <= 1e-8 * max(abs(want[0, 0]), 1.0)

@@ -76,8 +76,6 @@ def _oracle_x(case, colour, n_f):
 @pytest.mark.parametrize("case", ["small", "even"])
 def test_nested_exponents(dev, case, prec, n_f):
     lat, outer, inner = SMALL if case == "small" else EVEN
-    if prec == dd.MIXED16 and case == "small":
-        pytest.skip("FP16 storage needs even block extents")
     say("nested", case, prec, n_f)
     U = inputs.make_links(lat, 0.3, 31)
     O = dd.Context(T(U, dev), lat, outer, -1, 1.0)
@@ -85,6 +83,10 @@ def test_nested_exponents(dev, case, prec, n_f):
     for colour in (0, 1):
         eta = inputs.make_noise_batch(lat, 31 + colour, 2, NHIT)
         r = O.det_ratio_nested(I, colour, K1, K2, T(eta, dev), tol=1e-12, prec=prec, n_f=n_f)
+        if prec == dd.MIXED16 and case == "small":
+            # an odd inner block extent: FP16 storage is documented to run as MIXED32, bit for bit
+            r32 = O.det_ratio_nested(I, colour, K1, K2, T(eta, dev), tol=1e-12, prec=dd.MIXED32, n_f=n_f)
+            assert np.array_equal(r["x"], r32["x"]) and r["log_w"] == r32["log_w"]
         want = _oracle_x(case, colour, n_f)
         scale = max(np.abs(want).max(), 1.0)
         assert np.abs(r["x"] - want).max() <= 1e-8 * scale, (colour, r["x"], want)

@@ -263,6 +263,9 @@ int ddwc_log_w_nested_total(ddwc_ctx *outer, ddwc_ctx *inner, double kappa1, dou
  *                          DDWC_MIXED16: 0 (default) the LDS-resident FP32 kernel wherever a block
  *                          parity has at most 768 sites and its two staged fields fit the LDS (both
  *                          precisions then run it, FP32 storage); 1 the global-memory kernel.
+ *   DDWC_OPT_INNER_FLOOR   the FP32 inner BiCGStab of the even-odd global solver (DDWC_MIXED32) stops
+ *                          at a relative residual of at least value x 1e-8 before the FP64 defect
+ *                          correction restarts it, in [1, 100000]; default 200 (2e-6).
  * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
@@ -272,7 +275,8 @@ typedef enum {
     DDWC_OPT_BLOCK_THREADS = 2,
     DDWC_OPT_SOLVER = 3,
     DDWC_OPT_BLOCK_LDS = 4,
-    DDWC_OPT_BLOCK_KERNEL = 5
+    DDWC_OPT_BLOCK_KERNEL = 5,
+    DDWC_OPT_INNER_FLOOR = 6
 } ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);

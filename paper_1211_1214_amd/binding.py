@@ -19,7 +19,7 @@ FP64, MIXED32, MIXED16 = 0, 1, 2
 BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER, K_EOHOP = range(6)
-OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS, OPT_BLOCK_KERNEL = range(6)
+OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS, OPT_BLOCK_KERNEL, OPT_INNER_FLOOR = range(7)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.

@@ -128,6 +128,8 @@ struct ddwc_ctx {
     // schedule options (ddwc_set_option, ddwc_autotune)
     int opt_graphs = 1;       // replay the global solver's iteration chunks from captured graphs
     int opt_poll = 2;         // BiCGStab iterations between host convergence checks
+    int opt_inner_floor = 200;  // FP32 inner solves of the even-odd global solver stop at a relative
+                                // residual of at least opt_inner_floor x 1e-8
     int opt_blk_threads = 0;  // block-solver workgroup size (0: default rule)
     int opt_solver = 0;       // global solver: 0 even-odd BiCGStab, 1 SAP-preconditioned GCR
     int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
@@ -684,7 +686,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     HC(hipStreamSynchronize(sm));
     for (int k = 0; k < nrhs; ++k) rr[k] = h_sums[k * NPART + 2];
     // the inner solve stops at this relative residual at the least (the storage's reach)
-    const double floor_eps = fp64 ? 0.0 : h16 ? 1e-3 : 2e-6;
+    const double floor_eps = fp64 ? 0.0 : h16 ? 1e-3 : 1e-8 * C->opt_inner_floor;
     const int poll = C->opt_poll;
     int total = 0, nout = 0;
     bool converged = false;
@@ -1858,6 +1860,10 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
             if (value != 0 && value != 1) return fail(DDWC_EINVAL, "block kernel must be 0 or 1");
             C->opt_blk_kernel = value;
             break;
+        case DDWC_OPT_INNER_FLOOR:
+            if (value < 1 || value > 100000) return fail(DDWC_EINVAL, "inner floor must be in [1, 100000] (x 1e-8)");
+            C->opt_inner_floor = value;
+            break;
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1874,6 +1880,7 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_SOLVER: *value = C->opt_solver; break;
         case DDWC_OPT_BLOCK_LDS: *value = C->opt_blk_lds; break;
         case DDWC_OPT_BLOCK_KERNEL: *value = C->opt_blk_kernel; break;
+        case DDWC_OPT_INNER_FLOOR: *value = C->opt_inner_floor; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;

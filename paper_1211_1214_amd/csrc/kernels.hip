@@ -453,25 +453,27 @@ void launch_fill_hash(Exec& e, double2* v, size_t n, uint64_t seed) {
 
 // ------------------------------------------------------------------ streaming reference
 // dst = src over n 16-byte words: the streaming rate the operator kernels are measured against
-// (and a transfer of known size for calibrating memory counters).  Each thread moves four words
-// per round with all four loads issued before the stores; rounds stride over the whole grid.
-__global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst,
-                                                     size_t n) {
+// (and a transfer of known size for calibrating memory counters).  Each thread moves eight words
+// per round, all eight loads issued before the stores (non-temporal: the data is not reused);
+// rounds stride over the whole grid.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const v4f* __restrict__ src, v4f* __restrict__ dst, size_t n) {
+    constexpr int U = 8;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        v4f w[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) w[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < U; ++k) __builtin_nontemporal_store(w[k], dst + i + k * stride);
     }
     for (; i < n; i += stride) dst[i] = src[i];
 }
 void launch_stream_copy(Exec& e, const float4* src, float4* dst, size_t n) {
-    const size_t want = (n + 1023) / 1024;  // four words per thread and round
+    const size_t want = (n + 2047) / 2048;  // eight words per thread and round
     const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), 8192);
-    k_stream_copy<<<grid, 256, 0, e.stream>>>(src, dst, n);
+    k_stream_copy<<<grid, 256, 0, e.stream>>>((const v4f*)src, (v4f*)dst, n);
 }
 
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)

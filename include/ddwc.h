@@ -95,6 +95,20 @@ int ddwc_destroy(ddwc_ctx *ctx);
 int ddwc_dslash_apply(ddwc_ctx *ctx, double kappa, const void *in, void *out, int nrhs, int prec, void *stream);
 
 /*
+ * ddwc_dslash_apply for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same operator and result, bit for
+ * bit, with the internal-layout fields in a static device array of the library (256 MiB per GPU,
+ * held until the process ends) instead of the context's workspace.  The call allocates nothing
+ * and creates no events.  EINVAL (nothing launched) when the two fields need more than 256 MiB:
+ * 2 x nrhs x V x 192 bytes for DDWC_FP64, 2 x nrhs x V x 96 bytes otherwise (at 48x24^3: one FP64
+ * RHS, two FP32 RHS).  Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other threads, other contexts)
+ * race and must be serialised by the caller.  Asynchronous on `stream`.
+ */
+int ddwc_dslash_apply_noalloc(ddwc_ctx *ctx, double kappa, const void *in, void *out, int nrhs, int prec,
+                              void *stream);
+
+/*
  * sol = D_cc(m)^-1 rhs for all Schwarz blocks of one colour (D_bb or D_ww: the
  * Dirichlet block operators on the diagonal, Sec. 1).  Only sites of that colour
  * are read; the other colour of sol is set to zero.  One persistent launch: one

@@ -40,6 +40,7 @@ SIGNATURES = {
     "ddwc_create": (_I, [ctypes.POINTER(_P), _P, _P, _I, _D, _P, _P]),
     "ddwc_destroy": (_I, [_P]),
     "ddwc_dslash_apply": (_I, [_P, _D, _P, _P, _I, _I, _P]),
+    "ddwc_dslash_apply_noalloc": (_I, [_P, _D, _P, _P, _I, _I, _P]),
     "ddwc_block_solve": (_I, [_P, _I, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),
     "ddwc_schur_apply": (_I, [_P, _D, _I, _P, _P, _I, _D, _I, _PS, _P]),
     "ddwc_solve": (_I, [_P, _D, _P, _P, _I, _D, _I, _I, _PS, _P]),

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -87,6 +88,35 @@ Profiler::~Profiler() {
 }
 }  // namespace ddwc
 
+// ------------------------------------------------------------------ static device scratch
+// Scratch of ddwc_dslash_apply_noalloc, for callers that cannot allocate device memory: the
+// internal-layout input and output fields of one call.  Each GPU the library runs on holds its
+// own copy for the life of the process; host code never uses the array's name as a device
+// address, only the per-device address that hipGetSymbolAddress returns (scratch_address).
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;  // device -> its copy of `scratch`
+
+// Address of `scratch` on `device`, which must be the current device (looked up once per device).
+static int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return DDWC_OK;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(DDWC_EHIP, std::string("address of the static device scratch: ") + hipGetErrorString(e));
+    }
+    g_scratch_addr[device] = p;
+    *out = p;
+    return DDWC_OK;
+}
+
 // ------------------------------------------------------------------ context
 struct ddwc_ctx {
     Geom g;
@@ -135,6 +165,7 @@ struct ddwc_ctx {
     int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
     int opt_blk_kernel = 0;   // block inner solver: 0 LDS-resident where it fits (FP32/FP16), 1 global-memory
     int lds_max = 0;          // LDS bytes per workgroup of the device
+    void* scratch = nullptr;  // this device's copy of the static scratch (ddwc_dslash_apply_noalloc)
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
     struct Graph {
         std::vector<uintptr_t> key;
@@ -253,6 +284,10 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     C->csw = c_sw;
     hipError_t e0 = hipGetDevice(&C->device);
     if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&C->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device);
+    if (e0 == hipSuccess && scratch_address(C->device, &C->scratch) != DDWC_OK) {
+        delete C;
+        return DDWC_EHIP;
+    }
     size_t n = (size_t)4 * 9 * g.V;
     if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
         hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
@@ -990,41 +1025,62 @@ static void fill_stats(ddwc_stats* s, int outer, int inner, double rel, std::chr
     s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// out = D(m) in through internal-layout fields a and b (each dslash_field_bytes long): from the
+// context's workspace, or from the static scratch for the no-allocation entry point.
+static size_t dslash_field_bytes(const ddwc_ctx* C, int nrhs, int prec) {
+    return vec_words(C, nrhs, prec == DDWC_FP64) * 16;
+}
+static int dslash_apply_with(ddwc_ctx* C, Exec& ex, double kappa, const void* in, void* out, int nrhs, int prec,
+                             void* a, void* b) {
+    const Geom& g = C->g;
+    const double mass4 = 4.0 + mass_of(kappa);
+    if (prec == DDWC_FP64) {
+        launch_import<double>(ex, g, in, (double2*)a, nrhs, MASK_ALL);
+        launch_dslash<double>(ex, g, C->U64, C->K64, mass4, (const double2*)a, (double2*)b, nrhs, DDWC_K_DSLASH64,
+                              ddwc_dslash_bytes(C, nrhs, DDWC_FP64));
+        launch_export<double>(ex, g, (const double2*)b, out, nrhs, MASK_ALL);
+    } else if (nrhs > 1 && nrhs <= WG && ri_fits((unsigned)g.V, nrhs)) {
+        // several RHS: RHS-innermost fields, the RHS of a site share its links and clover
+        launch_import_ri32(ex, g, in, (float4*)a, nrhs);
+        launch_dslash_ri32(ex, g, C->U32s, C->K32, mass4, (const float4*)a, (float4*)b, nrhs, DDWC_K_DSLASH32,
+                           ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
+        launch_export_ri32(ex, g, (const float4*)b, out, nrhs);
+    } else {
+        launch_import<float>(ex, g, in, (float4*)a, nrhs, MASK_ALL);
+        launch_dslash<float>(ex, g, C->U32, C->K32, mass4, (const float4*)a, (float4*)b, nrhs, DDWC_K_DSLASH32,
+                             ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
+        launch_export<float>(ex, g, (const float4*)b, out, nrhs, MASK_ALL);
+    }
+    HC(hipGetLastError());
+    return DDWC_OK;
+}
+
 extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void* out, int nrhs, int prec,
                                  void* stream) {
     CK(check_common(C, kappa, nrhs, prec));
     if (!in || !out) return fail(DDWC_EINVAL, "null vector");
     Exec ex = make_exec(C, stream);
-    const Geom& g = C->g;
-    const double mass4 = 4.0 + mass_of(kappa);
-    if (prec == DDWC_FP64) {
-        double2 *a, *b;
-        CK(ws_t(C, "d_in64", vec_words(C, nrhs, true), &a));
-        CK(ws_t(C, "d_out64", vec_words(C, nrhs, true), &b));
-        launch_import<double>(ex, g, in, a, nrhs, MASK_ALL);
-        launch_dslash<double>(ex, g, C->U64, C->K64, mass4, a, b, nrhs, DDWC_K_DSLASH64,
-                              ddwc_dslash_bytes(C, nrhs, DDWC_FP64));
-        launch_export<double>(ex, g, b, out, nrhs, MASK_ALL);
-    } else if (nrhs > 1 && nrhs <= WG && ri_fits((unsigned)g.V, nrhs)) {
-        // several RHS: RHS-innermost fields, the RHS of a site share its links and clover
-        float4 *a, *b;
-        CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));
-        CK(ws_t(C, "d_out32", vec_words(C, nrhs, false), &b));
-        launch_import_ri32(ex, g, in, a, nrhs);
-        launch_dslash_ri32(ex, g, C->U32s, C->K32, mass4, a, b, nrhs, DDWC_K_DSLASH32,
-                           ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
-        launch_export_ri32(ex, g, b, out, nrhs);
-    } else {
-        float4 *a, *b;
-        CK(ws_t(C, "d_in32", vec_words(C, nrhs, false), &a));
-        CK(ws_t(C, "d_out32", vec_words(C, nrhs, false), &b));
-        launch_import<float>(ex, g, in, a, nrhs, MASK_ALL);
-        launch_dslash<float>(ex, g, C->U32, C->K32, mass4, a, b, nrhs, DDWC_K_DSLASH32,
-                             ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
-        launch_export<float>(ex, g, b, out, nrhs, MASK_ALL);
-    }
-    HC(hipGetLastError());
-    return DDWC_OK;
+    const bool fp64 = prec == DDWC_FP64;
+    void *a, *b;
+    CK(ws_get(C, fp64 ? "d_in64" : "d_in32", dslash_field_bytes(C, nrhs, prec), &a));
+    CK(ws_get(C, fp64 ? "d_out64" : "d_out32", dslash_field_bytes(C, nrhs, prec), &b));
+    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, a, b);
+}
+
+extern "C" int ddwc_dslash_apply_noalloc(ddwc_ctx* C, double kappa, const void* in, void* out, int nrhs, int prec,
+                                         void* stream) {
+    CK(check_common(C, kappa, nrhs, prec));
+    if (!in || !out) return fail(DDWC_EINVAL, "null vector");
+    const size_t fb = (dslash_field_bytes(C, nrhs, prec) + 255) / 256 * 256;
+    if (2 * fb > NOALLOC_SCRATCH_BYTES)
+        return fail(DDWC_EINVAL, "ddwc_dslash_apply_noalloc: the two internal fields need " + std::to_string(2 * fb) +
+                                     " bytes, more than the static scratch of " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
+    if (!C->scratch) return fail(DDWC_EHIP, "no static scratch on this context's device");
+    Exec ex = make_exec(C, stream);
+    ex.prof = nullptr;  // no event pairs: nothing is created during the call
+    char* base = (char*)C->scratch;
+    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, base, base + fb);
 }
 
 extern "C" int ddwc_block_solve(ddwc_ctx* C, int colour, double kappa, const void* rhs, void* sol, int nrhs,

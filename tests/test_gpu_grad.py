@@ -6,6 +6,8 @@ random directions, for L = sum_ij g_ij x_ij with random g, against the derivativ
 The 32x16^3 workload (4^4 blocks, N_hit = 8): the gradient of log W_gl against central
 differences of the GPU estimate itself (a property at any size), relative error <= 1e-6.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -18,6 +20,7 @@ from oracle import derivative, estimator  # noqa: E402
 from paper_1211_1214_amd import autograd, inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+GOLDEN_32X16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_32x16.json")
 GEOMS = {
     "4x4^3/2^4": ((4, 4, 4, 4), (2, 2, 2, 2)),     # even-odd block solver
     "4x4x2x2/2x2x1x1": ((4, 4, 2, 2), (2, 2, 1, 1)),  # lexicographic block solver
@@ -127,8 +130,9 @@ def test_autograd_matches_abi(dev):
 
 
 def test_c5_gradient_vs_finite_differences(dev):
-    """32x16^3, 4^4 blocks, N_hit = 8, kappa 0.1200 -> 0.1205: d log W_gl / d kappa2 and along
-    one random link direction, against extrapolated central differences of the GPU estimate."""
+    """32x16^3, 4^4 blocks, N_hit = 8, kappa 0.1200 -> 0.1205: the forward exponents and log W_gl
+    against the stored oracle values, then d log W_gl / d kappa2 and along one random link
+    direction against extrapolated central differences of the GPU estimate."""
     cfg = inputs.WORKLOADS["32x16^3"]
     lat, blk = cfg["lat"], cfg["blk"]
     say("c5: inputs")
@@ -144,6 +148,12 @@ def test_c5_gradient_vs_finite_differences(dev):
         return res["log_w_gl"], res["x"]
 
     lw, x = logw(U, k2)
+    # the forward exponents and log W_gl against the oracle values stored by
+    # tests/golden/make_golden_32x16.py (all solves to 1e-13)
+    gold = json.load(open(GOLDEN_32X16))
+    for j, xo in gold["x_schur"].items():
+        assert abs(x[0, int(j)] - xo) <= 1e-8 * max(abs(xo), 1.0), (j, x[0, int(j)], xo)
+    assert abs(lw - gold["log_w_gl"]) <= 1e-8 * max(abs(gold["log_w_gl"]), 1.0)
     ctx = dd.Context(T(U, dev), lat, blk, -1, cfg["csw"])
     say("c5: gradient")
     r = ctx.det_ratio_grad(k1, k2, eta, derivative.log_w_weights(x), op=dd.OP_SCHUR, tol=1e-12, prec=dd.MIXED32)

@@ -559,11 +559,14 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
 // in the layout LK (LinkLayout; Uf's own-site records with LK_OWN).
+// With LK_OWN the records may be a staged copy (in LDS) that starts at site `l0`: the record of
+// s is then record s - l0 of Uf.
 template <class R, int HOPS, bool PIPE, int LK = LK_ENTRY, class W, class L>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
                      const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
-                     unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0) {
+                     unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0, unsigned l0 = 0) {
     if (sstride == 0) sstride = n;
+    const unsigned sl = s - l0;  // record index of s (LK_OWN)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));
     if (HOPS == HOPS_NONE) return;
@@ -578,7 +581,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             if (take) {
                 cx<R> q[12], u[9];
                 load_spinor(in, sstride, t * smul + sadd, q);
-                hop_link<LK>(Uf, Ub, n, d, s, t, u);
+                hop_link<LK>(Uf, Ub, n, d, LK == LK_OWN ? sl : s, t, u);
                 if (e < 0) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) q[c] = -q[c];
@@ -597,7 +600,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             const int e = ent[0];
             const unsigned t0 = e < 0 ? (unsigned)~e : (unsigned)e;
             load_spinor(in, sstride, t0 * smul + sadd, q);
-            hop_link<LK>(Uf, Ub, n, 0, s, t0, u);
+            hop_link<LK>(Uf, Ub, n, 0, LK == LK_OWN ? sl : s, t0, u);
         }
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
@@ -614,7 +617,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
                 load_spinor(in, sstride, tn * smul + sadd, qn);
-                hop_link<LK>(Uf, Ub, n, d + 1, s, tn, un);
+                hop_link<LK>(Uf, Ub, n, d + 1, LK == LK_OWN ? sl : s, tn, un);
             }
             if (take) {
                 if (e < 0) {

@@ -143,9 +143,67 @@ constexpr int site_major_links() {
 // Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the
 // RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
+// Staging of what the lanes of one site share (RHS-innermost kernels with at least STG_MIN_RHS
+// RHS): the own-site link records and the clover words of the sites a workgroup covers are copied
+// into LDS with coalesced 16-byte loads before the hop loop, which then reads them there: one
+// copy per site instead of one vector-memory load per (site, RHS) lane.
+constexpr int STG_MIN_RHS = 8;
+constexpr int STG_SITES = WG / STG_MIN_RHS + 2;  // sites that WG consecutive (site, RHS) pairs can touch
+
+template <class S>
+constexpr unsigned record_words() {  // 16-byte words of one own-site link record
+    return 8 * 9 * sizeof(cx<typename Traits<S>::link>) / 16;
+}
+template <class S>
+constexpr size_t stage_bytes() {
+    return (size_t)STG_SITES * (record_words<S>() + Traits<S>::NKW) * 16;
+}
+
+// Staging applies to the RHS-innermost low-precision kernels (own-site link records) with enough
+// RHS per site.
+template <class S>
+inline bool stage_ok(int nrhs) {
+    return !std::is_same<S, double>::value && nrhs >= STG_MIN_RHS;
+}
+
+template <class S>
+struct Staged {
+    const cx<typename Traits<S>::link>* U;  // link records of sites l0, l0 + 1, ...
+    const typename Traits<S>::kword* K;     // clover words [NKW][STG_SITES] of the same sites
+    unsigned l0;
+};
+
+// Copies the records and clover words of the sites of the workgroup's pairs; every thread of the
+// workgroup must call it (it ends with a barrier).
+template <class S>
+__device__ __forceinline__ Staged<S> stage_site_data(const VItem& it, unsigned n2, int nrhs,
+                                                     const cx<typename Traits<S>::link>* __restrict__ Up,
+                                                     const typename Traits<S>::kword* __restrict__ K) {
+    typedef typename Traits<S>::kword KW;
+    extern __shared__ float4 stg[];
+    constexpr unsigned RW = record_words<S>();
+    const unsigned l0 = it.g0 / (unsigned)nrhs;
+    unsigned l1 = (it.g0 + WG - 1) / (unsigned)nrhs + 1;
+    if (l1 > n2) l1 = n2;
+    const unsigned ns = l1 - l0;  // <= STG_SITES for nrhs >= STG_MIN_RHS
+    const float4* src = (const float4*)Up + (size_t)l0 * RW;
+    for (unsigned k = threadIdx.x; k < ns * RW; k += WG) stg[k] = src[k];
+    KW* ck = (KW*)(stg + STG_SITES * RW);
+    for (unsigned k = threadIdx.x; k < Traits<S>::NKW * ns; k += WG) {
+        const unsigned w = k / ns, j = k - w * ns;
+        ck[w * STG_SITES + j] = K[(size_t)w * n2 + l0 + j];
+    }
+    __syncthreads();
+    Staged<S> st;
+    st.U = (const cx<typename Traits<S>::link>*)stg;
+    st.K = ck;
+    st.l0 = l0;
+    return st;
+}
+
 // y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
 // alpha = 0 skips the hops.  S is the storage (double, float or H16), arithmetic in its real.
-template <class S, bool RI>
+template <class S, bool RI, bool STG>
 __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<S>::word* __restrict__ x,
                                                   const typename Traits<S>::word* __restrict__ c,
                                                   typename Traits<S>::real alpha,
@@ -156,12 +214,22 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
                                                   typename Traits<S>::word* __restrict__ y, int nrhs, int ntiles) {
     typedef typename Traits<S>::real R;
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
+    const cx<typename Traits<S>::link>* Uf = Up;
+    const typename Traits<S>::kword* Ak = Ainv;
+    unsigned kst = n2, l0 = 0;
+    if (STG) {
+        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Ainv);
+        Uf = sd.U;
+        Ak = sd.K;
+        kst = STG_SITES;
+        l0 = sd.l0;
+    }
     if (!it.ok) return;
     const VView<RI, S> w(n2, nrhs, it.i, it.r);
     cx<R> acc[12], out[12];
     if (alpha != R(0))
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Up, Uq, nbrp, acc, 8,
-                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Uf, Uq, nbrp, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0);
     else
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = mk(R(0), R(0));
@@ -176,7 +244,7 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) out[k] = mk(R(0), R(0));
-    apply_diag<R>(Ainv, n2, it.i, R(0), acc, out, R(0));
+    apply_diag<R>(Ak, kst, it.i - l0, R(0), acc, out, R(0));
     store_spinor(y + w.base, w.stride, w.idx, out);
 }
 
@@ -185,7 +253,7 @@ enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
 // y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
 // Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
 // RESID: y = aux - y and partial ||y||^2.
-template <class S, int EPI, bool USE_A, bool RI>
+template <class S, int EPI, bool USE_A, bool RI, bool STG>
 __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<S>::word* __restrict__ c,
                                                    const typename Traits<S>::word* __restrict__ t,
                                                    typename Traits<S>::real beta,
@@ -199,15 +267,25 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
                                                    int ntiles) {
     typedef typename Traits<S>::real R;
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
+    const cx<typename Traits<S>::link>* Uf = Up;
+    const typename Traits<S>::kword* Kk = Kp;
+    unsigned kst = n2, l0 = 0;
+    if (STG) {
+        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Kp);
+        Uf = sd.U;
+        Kk = sd.K;
+        kst = STG_SITES;
+        l0 = sd.l0;
+    }
     double v[3] = {0, 0, 0};
     if (it.ok) {
         const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Up, Uq, nbrp, acc, 8,
-                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Uf, Uq, nbrp, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0);
         load_spinor(c + w.base, w.stride, w.idx, cc);
         if (USE_A) {
-            apply_diag<R>(Kp, n2, it.i, mass4, cc, acc, beta);
+            apply_diag<R>(Kk, kst, it.i - l0, mass4, cc, acc, beta);
         } else {
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = cc[k] + beta * acc[k];
@@ -242,12 +320,15 @@ void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typen
     typedef typename Traits<S>::real R;
     Timed t(e, kclass, bytes);
     const int nt = vector_tiles(F.n2, nrhs, ri);
-    if (ri)
-        k_eo_hopinv<S, true><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y,
-                                                      nrhs, nt);
+    if (ri && stage_ok<S>(nrhs))
+        k_eo_hopinv<S, true, true><<<nt, WG, stage_bytes<S>(), e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
+                                                                          F.nbr[p], Ainv, y, nrhs, nt);
+    else if (ri)
+        k_eo_hopinv<S, true, false><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
+                                                             Ainv, y, nrhs, nt);
     else
-        k_eo_hopinv<S, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
-                                                              Ainv, y, nrhs, nt);
+        k_eo_hopinv<S, false, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
+                                                                     F.nbr[p], Ainv, y, nrhs, nt);
 }
 
 template <class S>
@@ -259,9 +340,15 @@ void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, b
     Timed tm(e, kclass, bytes);
     const int nt = vector_tiles(F.n2, nrhs, ri);
     const int ng = ri ? nt : nt * nrhs;
+    const bool stg = ri && stage_ok<S>(nrhs);
 #define EOL(EP, UA, RIV)                                                                                            \
-    k_eo_diaghop<S, EP, UA, RIV><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p],       \
-                                                          F.K[p], (R)mass4, aux, y, part, nrhs, nt)
+    if (stg)                                                                                                        \
+        k_eo_diaghop<S, EP, UA, RIV, true><<<ng, WG, stage_bytes<S>(), e.stream>>>(                                 \
+            F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);          \
+    else                                                                                                            \
+        k_eo_diaghop<S, EP, UA, RIV, false><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p],      \
+                                                                     F.nbr[p], F.K[p], (R)mass4, aux, y, part,      \
+                                                                     nrhs, nt)
 #define EOSW(RIV)                                            \
     if (use_a) {                                             \
         switch (epi) {                                       \

@@ -126,7 +126,7 @@ struct ddwc_ctx {
     double links_fp = 0;  // fingerprint of the canonical links (equal links give equal values)
     cx<double>* U64 = nullptr;
     cx<float>* U32 = nullptr;
-    cx<float>* U32s = nullptr;  // site-major FP32 links [V][4][9] (RHS-innermost full Dslash)
+    cx<float>* U32s = nullptr;  // own-site FP32 link records [V][8][9] (RHS-innermost full Dslash)
     double2* K64 = nullptr;
     float4* K32 = nullptr;
     int* nbr = nullptr;  // neighbour table [8][V]
@@ -291,7 +291,7 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     size_t n = (size_t)4 * 9 * g.V;
     if (e0 != hipSuccess || hipMalloc(&C->U64, n * sizeof(cx<double>)) != hipSuccess ||
         hipMalloc(&C->U32, n * sizeof(cx<float>)) != hipSuccess ||
-        hipMalloc(&C->U32s, n * sizeof(cx<float>)) != hipSuccess ||
+        hipMalloc(&C->U32s, 2 * n * sizeof(cx<float>)) != hipSuccess ||
         hipMalloc(&C->K64, (size_t)36 * g.V * sizeof(double2)) != hipSuccess ||
         hipMalloc(&C->K32, (size_t)18 * g.V * sizeof(float4)) != hipSuccess ||
         hipMalloc(&C->nbr, (size_t)8 * g.V * sizeof(int)) != hipSuccess) {
@@ -300,7 +300,8 @@ extern "C" int ddwc_create(ddwc_ctx** out, const int lat[4], const int blk[4], i
     }
     Exec ex = make_exec(C, stream);
     launch_nbr_build(ex, g, C->nbr);
-    launch_links_import(ex, g, links_dev, C->U64, C->U32, C->U32s);
+    launch_links_import(ex, g, links_dev, C->U64, C->U32);
+    launch_links_own(ex, (unsigned)g.V, C->U32, C->U32, C->nbr, C->U32s);
     launch_clover_build(ex, g, C->U64, c_sw, C->K64, C->K32);
     if (g.eo) {
         const size_t n2 = g.V / 2;

@@ -560,13 +560,16 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
 // in the layout LK (LinkLayout; Uf's own-site records with LK_OWN).
 // With LK_OWN the records may be a staged copy (in LDS) that starts at site `l0`: the record of
-// s is then record s - l0 of Uf.
+// s is then record s - l0 of Uf.  With nstr > 0 the neighbour table is a staged copy too,
+// [8][nstr] entries starting at site l0.
 template <class R, int HOPS, bool PIPE, int LK = LK_ENTRY, class W, class L>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
                      const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
-                     unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0, unsigned l0 = 0) {
+                     unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0, unsigned l0 = 0,
+                     unsigned nstr = 0) {
     if (sstride == 0) sstride = n;
     const unsigned sl = s - l0;  // record index of s (LK_OWN)
+    const unsigned ns = nstr ? nstr : n, sn = nstr ? sl : s;  // table stride and index of s
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));
     if (HOPS == HOPS_NONE) return;
@@ -574,7 +577,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
     if (!PIPE) {
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
-            const int e = at(nbr + (size_t)d * n, s);
+            const int e = at(nbr + (size_t)d * ns, sn);
             const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
             const bool inside = (t < n / 2) == s_black;
             const bool take = HOPS == HOPS_ALL || (HOPS == HOPS_INSIDE && inside) || (HOPS == HOPS_CROSSING && !inside);
@@ -594,7 +597,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
         // neighbour spinor and link of direction d + 1 are in flight while d is computed
         int ent[8];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * n, s);
+        for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * ns, sn);
         cx<R> q[12], u[9];
         {
             const int e = ent[0];

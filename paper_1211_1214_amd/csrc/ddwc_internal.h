@@ -70,10 +70,14 @@ constexpr int NPART = 4; // doubles per partial-sum slot
 
 inline int tiles_of(int n) { return (n + WG - 1) / WG; }
 
-// Links to the internal layouts: U64, U32 entry-major [4][9][V], U32s site-major [V][4][9].
-void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32,
-                         cx<float>* U32s);
-// Full-lattice FP32 Dslash on RHS-innermost fields [6][V][nrhs] (canonical FP64 in and out).
+// Links to the internal layouts: U64, U32 entry-major [4][9][V].
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32);
+// Own-site link records [n][8][9] (LK_OWN) of n sites from entry-major forward links Uf ([4][9][n])
+// and Ub (the neighbours', [4][9][n]) and the table nbr [8][n].
+void launch_links_own(Exec& e, unsigned n, const cx<float>* Uf, const cx<float>* Ub, const int* nbr,
+                      cx<float>* Lown);
+// Full-lattice FP32 Dslash on RHS-innermost fields [6][V][nrhs] (canonical FP64 in and out), with
+// the own-site link records Us [V][8][9].
 void launch_import_ri32(Exec& e, const Geom& g, const void* canon, float4* out, int nrhs);
 void launch_export_ri32(Exec& e, const Geom& g, const float4* in, void* canon, int nrhs);
 void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float4* K, double mass4, const float4* in,

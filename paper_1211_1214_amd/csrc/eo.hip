@@ -40,33 +40,11 @@ void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double
     k_eo_setup<<<tiles_of(g.V), WG, 0, e.stream>>>(g, U64, K64, nbr, Uh64, Uh32, Kh64, Kh32, nbr_eo);
 }
 
-// Own-site link records [2][n2][8][9] (LK_OWN) from the entry-major FP32 half-order links: for
-// parity p and half site i, hop d = 2 mu takes U_mu(x) (the site's own forward link) and
-// d = 2 mu + 1 takes U_mu(x - mu), the forward link of its neighbour (parity 1 - p, half index
-// from the table; the time-boundary sign stays with the table entry).
-__global__ void k_eo_links_own(unsigned n2, const cx<float>* __restrict__ Uh32, const int* __restrict__ nbr_eo,
-                               cx<float>* __restrict__ Lown) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 2 * (size_t)n2) return;
-    const int p = idx >= n2;
-    const unsigned i = (unsigned)(idx - (size_t)p * n2);
-    for (int d = 0; d < 8; ++d) {
-        const int mu = d >> 1;
-        int q = p;
-        unsigned src = i;
-        if (d & 1) {
-            const int e = nbr_eo[((size_t)p * 8 + d) * n2 + i];
-            src = e < 0 ? (unsigned)~e : (unsigned)e;
-            q = 1 - p;
-        }
-        for (int k = 0; k < 9; ++k)
-            Lown[(idx * 8 + d) * 9 + k] = Uh32[(((size_t)q * 4 + mu) * 9 + k) * n2 + src];
-    }
-}
-
 void launch_eo_links_own(Exec& e, unsigned n2, const cx<float>* Uh32, const int* nbr_eo, cx<float>* Lown) {
-    Timed t(e, 4, 0);
-    k_eo_links_own<<<(unsigned)((2 * (size_t)n2 + 255) / 256), 256, 0, e.stream>>>(n2, Uh32, nbr_eo, Lown);
+    // parity p: forward links of the parity-p sites, backward links from the other parity's
+    for (int p = 0; p < 2; ++p)
+        launch_links_own(e, n2, Uh32 + (size_t)p * 36 * n2, Uh32 + (size_t)(1 - p) * 36 * n2, nbr_eo + (size_t)p * 8 * n2,
+                         Lown + (size_t)p * 72 * n2);
 }
 
 // FP16 copy of the FP32 half-order links (setup).
@@ -143,64 +121,6 @@ constexpr int site_major_links() {
 // Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the
 // RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
-// Staging of what the lanes of one site share (RHS-innermost kernels with at least STG_MIN_RHS
-// RHS): the own-site link records and the clover words of the sites a workgroup covers are copied
-// into LDS with coalesced 16-byte loads before the hop loop, which then reads them there: one
-// copy per site instead of one vector-memory load per (site, RHS) lane.
-constexpr int STG_MIN_RHS = 8;
-constexpr int STG_SITES = WG / STG_MIN_RHS + 2;  // sites that WG consecutive (site, RHS) pairs can touch
-
-template <class S>
-constexpr unsigned record_words() {  // 16-byte words of one own-site link record
-    return 8 * 9 * sizeof(cx<typename Traits<S>::link>) / 16;
-}
-template <class S>
-constexpr size_t stage_bytes() {
-    return (size_t)STG_SITES * (record_words<S>() + Traits<S>::NKW) * 16;
-}
-
-// Staging applies to the RHS-innermost low-precision kernels (own-site link records) with enough
-// RHS per site.
-template <class S>
-inline bool stage_ok(int nrhs) {
-    return !std::is_same<S, double>::value && nrhs >= STG_MIN_RHS;
-}
-
-template <class S>
-struct Staged {
-    const cx<typename Traits<S>::link>* U;  // link records of sites l0, l0 + 1, ...
-    const typename Traits<S>::kword* K;     // clover words [NKW][STG_SITES] of the same sites
-    unsigned l0;
-};
-
-// Copies the records and clover words of the sites of the workgroup's pairs; every thread of the
-// workgroup must call it (it ends with a barrier).
-template <class S>
-__device__ __forceinline__ Staged<S> stage_site_data(const VItem& it, unsigned n2, int nrhs,
-                                                     const cx<typename Traits<S>::link>* __restrict__ Up,
-                                                     const typename Traits<S>::kword* __restrict__ K) {
-    typedef typename Traits<S>::kword KW;
-    extern __shared__ float4 stg[];
-    constexpr unsigned RW = record_words<S>();
-    const unsigned l0 = it.g0 / (unsigned)nrhs;
-    unsigned l1 = (it.g0 + WG - 1) / (unsigned)nrhs + 1;
-    if (l1 > n2) l1 = n2;
-    const unsigned ns = l1 - l0;  // <= STG_SITES for nrhs >= STG_MIN_RHS
-    const float4* src = (const float4*)Up + (size_t)l0 * RW;
-    for (unsigned k = threadIdx.x; k < ns * RW; k += WG) stg[k] = src[k];
-    KW* ck = (KW*)(stg + STG_SITES * RW);
-    for (unsigned k = threadIdx.x; k < Traits<S>::NKW * ns; k += WG) {
-        const unsigned w = k / ns, j = k - w * ns;
-        ck[w * STG_SITES + j] = K[(size_t)w * n2 + l0 + j];
-    }
-    __syncthreads();
-    Staged<S> st;
-    st.U = (const cx<typename Traits<S>::link>*)stg;
-    st.K = ck;
-    st.l0 = l0;
-    return st;
-}
-
 // y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
 // alpha = 0 skips the hops.  S is the storage (double, float or H16), arithmetic in its real.
 template <class S, bool RI, bool STG>
@@ -216,20 +136,22 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Ak = Ainv;
-    unsigned kst = n2, l0 = 0;
+    const int* nb = nbrp;
+    unsigned kst = n2, l0 = 0, nstr = 0;
     if (STG) {
-        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Ainv);
+        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Ainv, nbrp);
         Uf = sd.U;
         Ak = sd.K;
-        kst = STG_SITES;
+        nb = sd.nbr;
+        kst = nstr = STG_SITES;
         l0 = sd.l0;
     }
     if (!it.ok) return;
     const VView<RI, S> w(n2, nrhs, it.i, it.r);
     cx<R> acc[12], out[12];
     if (alpha != R(0))
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Uf, Uq, nbrp, acc, 8,
-                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Uf, Uq, nb, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0, nstr);
     else
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = mk(R(0), R(0));
@@ -269,20 +191,22 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
     const VItem it = vitem<RI>(n2, nrhs, ntiles);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Kk = Kp;
-    unsigned kst = n2, l0 = 0;
+    const int* nb = nbrp;
+    unsigned kst = n2, l0 = 0, nstr = 0;
     if (STG) {
-        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Kp);
+        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Kp, nbrp);
         Uf = sd.U;
         Kk = sd.K;
-        kst = STG_SITES;
+        nb = sd.nbr;
+        kst = nstr = STG_SITES;
         l0 = sd.l0;
     }
     double v[3] = {0, 0, 0};
     if (it.ok) {
         const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Uf, Uq, nbrp, acc, 8,
-                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0);
+        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Uf, Uq, nb, acc, 8,
+                                                              RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0, nstr);
         load_spinor(c + w.base, w.stride, w.idx, cc);
         if (USE_A) {
             apply_diag<R>(Kk, kst, it.i - l0, mass4, cc, acc, beta);

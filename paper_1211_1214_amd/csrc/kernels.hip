@@ -21,7 +21,7 @@ namespace ddwc {
 
 // ------------------------------------------------------------------ conversions
 __global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<double>* __restrict__ U64,
-                               cx<float>* __restrict__ U32, cx<float>* __restrict__ U32s) {
+                               cx<float>* __restrict__ U32) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     int mu = blockIdx.y;
     if (s >= g.V) return;
@@ -33,15 +33,39 @@ __global__ void k_links_import(Geom g, const double2* __restrict__ can, cx<doubl
         size_t o = ((size_t)mu * 9 + k) * g.V + s;
         U64[o] = mk(w.x, w.y);
         U32[o] = mk((float)w.x, (float)w.y);
-        U32s[((size_t)s * 4 + mu) * 9 + k] = mk((float)w.x, (float)w.y);
     }
 }
 
-void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32,
-                         cx<float>* U32s) {
+void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* U64, cx<float>* U32) {
     Timed t(e, 4, 0);
     dim3 grid(tiles_of(g.V), 4);
-    k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32, U32s);
+    k_links_import<<<grid, WG, 0, e.stream>>>(g, (const double2*)canon, U64, U32);
+}
+
+// Own-site link records [n][8][9] (LK_OWN) of n sites: hop d = 2 mu takes U_mu(x), the site's own
+// forward link from Uf ([4][9][n]); d = 2 mu + 1 takes U_mu(x - mu), the forward link of the
+// neighbour from Ub ([4][9][*], index from the table nbr [8][n]; the time-boundary sign stays with
+// the table entry).  Full lattice: Uf = Ub, one table; even-odd: the two parities' half fields.
+__global__ void k_links_own(unsigned n, const cx<float>* __restrict__ Uf, const cx<float>* __restrict__ Ub,
+                            unsigned nb, const int* __restrict__ nbr, cx<float>* __restrict__ Lown) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < 8; ++d) {
+        const int mu = d >> 1;
+        if (d & 1) {
+            const int e = nbr[(size_t)d * n + i];
+            const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
+            for (int k = 0; k < 9; ++k) Lown[(i * 8 + d) * 9 + k] = Ub[((size_t)mu * 9 + k) * nb + t];
+        } else {
+            for (int k = 0; k < 9; ++k) Lown[(i * 8 + d) * 9 + k] = Uf[((size_t)mu * 9 + k) * n + i];
+        }
+    }
+}
+
+void launch_links_own(Exec& e, unsigned n, const cx<float>* Uf, const cx<float>* Ub, const int* nbr,
+                      cx<float>* Lown) {
+    Timed t(e, 4, 0);
+    k_links_own<<<(unsigned)((n + 255) / 256), 256, 0, e.stream>>>(n, Uf, Ub, n, nbr, Lown);
 }
 
 // Neighbour table [8][V] (setup, once per geometry).
@@ -730,18 +754,31 @@ __global__ __launch_bounds__(WG) void k_export_ri32(Geom g, const float4* __rest
     for (int c = 0; c < 12; ++c) dst[c] = make_double2((double)q[c].re, (double)q[c].im);
 }
 
-__global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __restrict__ Us,
+template <bool STG>
+__global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __restrict__ Lown,
                                                     const float4* __restrict__ K, float mass4,
                                                     const float4* __restrict__ in, float4* __restrict__ out,
                                                     const int* __restrict__ nbr, int nrhs, int ntiles) {
     const VItem it = vitem<true>((unsigned)g.V, nrhs, ntiles);
+    const cx<float>* Uf = Lown;
+    const float4* Kk = K;
+    const int* nb = nbr;
+    unsigned kst = (unsigned)g.V, l0 = 0, nstr = 0;
+    if (STG) {
+        const Staged<float> sd = stage_site_data<float>(it, (unsigned)g.V, nrhs, Lown, K, nbr);
+        Uf = sd.U;
+        Kk = sd.K;
+        nb = sd.nbr;
+        kst = nstr = STG_SITES;
+        l0 = sd.l0;
+    }
     if (!it.ok) return;
     const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
     cx<float> acc[12], c[12];
-    hop_sum<float, HOPS_ALL, true, LK_SITE>((unsigned)g.V, it.i, in, Us, Us, nbr, acc, 8, (unsigned)nrhs,
-                                         (unsigned)it.r, w.stride);
+    hop_sum<float, HOPS_ALL, true, LK_OWN>((unsigned)g.V, it.i, in, Uf, Uf, nb, acc, 8, (unsigned)nrhs,
+                                           (unsigned)it.r, w.stride, l0, nstr);
     load_spinor(in, w.stride, w.idx, c);
-    apply_diag<float>(K, (unsigned)g.V, it.i, mass4, c, acc, -0.5f);
+    apply_diag<float>(Kk, kst, it.i - l0, mass4, c, acc, -0.5f);
     store_spinor(out, w.stride, w.idx, acc);
 }
 
@@ -759,7 +796,11 @@ void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float
                         float4* out, int nrhs, int kclass, double bytes) {
     Timed t(e, kclass, bytes);
     const int nt = tiles_of(g.V * nrhs);
-    k_dslash_ri32<<<nt, WG, 0, e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs, nt);
+    if (stage_ok<float>(nrhs))
+        k_dslash_ri32<true><<<nt, WG, stage_bytes<float>(), e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs,
+                                                                        nt);
+    else
+        k_dslash_ri32<false><<<nt, WG, 0, e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs, nt);
 }
 
 // ------------------------------------------------------------------ instantiations

@@ -4,6 +4,8 @@
 // (which receive workgroups round-robin) sweeps one contiguous range: the RHS of a tile
 // share its links and clover in that XCD's L2, and neighbouring tiles stay in one L2.
 #pragma once
+#include <type_traits>
+
 #include "ddwc_internal.h"
 
 namespace ddwc {
@@ -97,6 +99,72 @@ __device__ __forceinline__ void vpartials(double v[NV], double* part, int ntiles
         tr.rhs = it.r;
         write_partials<NV>(v, part, ntiles, tr);
     }
+}
+
+// Staging of what the lanes of one site share (RHS-innermost kernels with at least STG_MIN_RHS
+// RHS): the own-site link records, the clover words and the neighbour-table entries of the sites
+// a workgroup covers are copied into LDS with coalesced loads before the hop loop, which then
+// reads them there: one copy per site instead of one vector-memory load per (site, RHS) lane.
+constexpr int STG_MIN_RHS = 8;
+constexpr int STG_SITES = WG / STG_MIN_RHS + 2;  // sites that WG consecutive (site, RHS) pairs can touch
+
+template <class S>
+constexpr unsigned record_words() {  // 16-byte words of one own-site link record
+    return 8 * 9 * sizeof(cx<typename Traits<S>::link>) / 16;
+}
+template <class S>
+constexpr size_t stage_bytes() {
+    return (size_t)STG_SITES * ((record_words<S>() + Traits<S>::NKW) * 16 + 8 * sizeof(int));
+}
+
+// Staging applies to the RHS-innermost low-precision kernels (own-site link records) with enough
+// RHS per site.
+template <class S>
+inline bool stage_ok(int nrhs) {
+    return !std::is_same<S, double>::value && nrhs >= STG_MIN_RHS;
+}
+
+template <class S>
+struct Staged {
+    const cx<typename Traits<S>::link>* U;  // link records of sites l0, l0 + 1, ...
+    const typename Traits<S>::kword* K;     // clover words [NKW][STG_SITES] of the same sites
+    const int* nbr;                         // neighbour-table entries [8][STG_SITES] of the same sites
+    unsigned l0;
+};
+
+// Copies the records, clover words and table entries of the sites of the workgroup's pairs;
+// every thread of the workgroup must call it (it ends with a barrier).
+template <class S>
+__device__ __forceinline__ Staged<S> stage_site_data(const VItem& it, unsigned n2, int nrhs,
+                                                     const cx<typename Traits<S>::link>* __restrict__ Up,
+                                                     const typename Traits<S>::kword* __restrict__ K,
+                                                     const int* __restrict__ nbr) {
+    typedef typename Traits<S>::kword KW;
+    extern __shared__ float4 stg[];
+    constexpr unsigned RW = record_words<S>();
+    const unsigned l0 = it.g0 / (unsigned)nrhs;
+    unsigned l1 = (it.g0 + WG - 1) / (unsigned)nrhs + 1;
+    if (l1 > n2) l1 = n2;
+    const unsigned ns = l1 - l0;  // <= STG_SITES for nrhs >= STG_MIN_RHS
+    const float4* src = (const float4*)Up + (size_t)l0 * RW;
+    for (unsigned k = threadIdx.x; k < ns * RW; k += WG) stg[k] = src[k];
+    KW* ck = (KW*)(stg + STG_SITES * RW);
+    for (unsigned k = threadIdx.x; k < Traits<S>::NKW * ns; k += WG) {
+        const unsigned w = k / ns, j = k - w * ns;
+        ck[w * STG_SITES + j] = K[(size_t)w * n2 + l0 + j];
+    }
+    int* cn = (int*)(ck + Traits<S>::NKW * STG_SITES);
+    for (unsigned k = threadIdx.x; k < 8 * ns; k += WG) {
+        const unsigned d = k / ns, j = k - d * ns;
+        cn[d * STG_SITES + j] = nbr[(size_t)d * n2 + l0 + j];
+    }
+    __syncthreads();
+    Staged<S> st;
+    st.U = (const cx<typename Traits<S>::link>*)stg;
+    st.K = ck;
+    st.nbr = cn;
+    st.l0 = l0;
+    return st;
 }
 
 }  // namespace ddwc

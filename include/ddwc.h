@@ -280,6 +280,9 @@ int ddwc_log_w_nested_total(ddwc_ctx *outer, ddwc_ctx *inner, double kappa1, dou
  *   DDWC_OPT_INNER_FLOOR   the FP32 inner BiCGStab of the even-odd global solver (DDWC_MIXED32) stops
  *                          at a relative residual of at least value x 1e-8 before the FP64 defect
  *                          correction restarts it, in [1, 100000]; default 200 (2e-6).
+ *   DDWC_OPT_OP_THREADS    workgroup size of the even-odd global solver's RHS-innermost operator
+ *                          kernels (more than one RHS): 128, 256 (default) or 512; a value below
+ *                          the RHS count runs 256.
  * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
@@ -290,18 +293,20 @@ typedef enum {
     DDWC_OPT_SOLVER = 3,
     DDWC_OPT_BLOCK_LDS = 4,
     DDWC_OPT_BLOCK_KERNEL = 5,
-    DDWC_OPT_INNER_FLOOR = 6
+    DDWC_OPT_INNER_FLOOR = 6,
+    DDWC_OPT_OP_THREADS = 7
 } ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
 
 /*
  * Autotuner: times the schedule options on this lattice with nrhs reproducible right-hand
- * sides at the given kappa and precision (a block sweep of one colour for each workgroup
- * size, without and with the LDS reservations that leave room for 2 or 4 block-solver
- * workgroups per CU; a global solve for each poll interval with and without graphs,
- * tolerance 1e-8) and
- * sets the fastest.  *seconds_host (may be null) receives the tuning time.  Synchronises.
+ * sides at the given kappa and precision, tolerance 1e-8, and sets the fastest of each group in
+ * turn: the block inner solver on a block sweep of one colour (DDWC_OPT_BLOCK_KERNEL 0 where it
+ * applies; kernel 1 at each DDWC_OPT_BLOCK_THREADS in {0, 128, 256, 512} without and with the
+ * LDS reservations that leave room for 2 or 4 block-solver workgroups per CU); then, on a global
+ * solve, DDWC_OPT_OP_THREADS in {128, 256, 512}; then each poll interval in {2, 4, 8} with and
+ * without graphs.  *seconds_host (may be null) receives the tuning time.  Synchronises.
  */
 int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *seconds_host, void *stream);
 

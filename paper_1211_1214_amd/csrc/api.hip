@@ -164,6 +164,7 @@ struct ddwc_ctx {
     int opt_solver = 0;       // global solver: 0 even-odd BiCGStab, 1 SAP-preconditioned GCR
     int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
     int opt_blk_kernel = 0;   // block inner solver: 0 LDS-resident where it fits (FP32/FP16), 1 global-memory
+    int opt_op_threads = WG;  // workgroup size of the global solver's RHS-innermost operator kernels
     int lds_max = 0;          // LDS bytes per workgroup of the device
     void* scratch = nullptr;  // this device's copy of the static scratch (ddwc_dslash_apply_noalloc)
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
@@ -513,6 +514,7 @@ template <>
 EoFields<double> eo_fields<double>(const ddwc_ctx* C, bool) {
     EoFields<double> F;
     F.n2 = C->g.V / 2;
+    F.op_threads = C->opt_op_threads;
     for (int p = 0; p < 2; ++p) {
         F.U[p] = C->Uh64 + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh64 + (size_t)p * 36 * F.n2;
@@ -524,6 +526,7 @@ template <>
 EoFields<float> eo_fields<float>(const ddwc_ctx* C, bool site_major) {
     EoFields<float> F;
     F.n2 = C->g.V / 2;
+    F.op_threads = C->opt_op_threads;
     for (int p = 0; p < 2; ++p) {
         F.U[p] = site_major ? C->Uh32s + (size_t)p * 72 * F.n2 : C->Uh32 + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
@@ -536,6 +539,7 @@ template <>
 EoFields<H16> eo_fields<H16>(const ddwc_ctx* C, bool site_major) {
     EoFields<H16> F;
     F.n2 = C->g.V / 2;
+    F.op_threads = C->opt_op_threads;
     for (int p = 0; p < 2; ++p) {
         F.U[p] = site_major ? C->Uh16s + (size_t)p * 72 * F.n2 : C->Uh16 + (size_t)p * 36 * F.n2;
         F.K[p] = C->Kh32 + (size_t)p * 18 * F.n2;
@@ -647,6 +651,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     const bool ri = h16 || (nrhs > 1 && nrhs <= WG && ri_fits(n2, nrhs));
     const EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read own-site link records
     const int ntR = vector_tiles(n2, nrhs, ri);
+    const int ntM = eo_op_tiles(FR, nrhs, ri);  // tiles of the operator kernels' partial sums
     const double mass4 = 4.0 + mass;
     const double2* A64;
     const float4* A32;
@@ -686,7 +691,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         CK(ws_get(C, pre + "x", bytesX, &q));
         xR = (XW*)q;
     }
-    CK(ws_t(C, "g_part", (size_t)(ntf > ntR ? ntf : ntR) * nrhs * NPART, &part));
+    CK(ws_t(C, "g_part", (size_t)std::max(ntf, std::max(ntR, ntM)) * nrhs * NPART, &part));
     CK(ws_t(C, "g_sums", (size_t)nrhs * NPART, &sums));
     CK(ws_t(C, "g_scale", (size_t)nrhs, &scale));
     CK(ws_t(C, "g_thr", (size_t)nrhs, &thr));
@@ -735,10 +740,10 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         };
         for (int k = 0; k < iters; ++k) {
             apply_M(p, v, 1, rh);
-            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_ALPHA, nullptr);
+            launch_finalize(ee, part, ntM, nrhs, nullptr, st, ST_ALPHA, nullptr);
             launch_bicg_s<S>(ee, n2, ri, st, r, v, s, nrhs);
             apply_M(s, t, 2, nullptr);
-            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_OMEGA, nullptr);
+            launch_finalize(ee, part, ntM, nrhs, nullptr, st, ST_OMEGA, nullptr);
             launch_bicg_xr<S>(ee, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
             launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
             launch_bicg_p<S>(ee, n2, ri, st, r, v, p, nrhs);
@@ -755,7 +760,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
                                       (uintptr_t)n2, (uintptr_t)poll, (uintptr_t)mb, (uintptr_t)r, (uintptr_t)rh,
                                       (uintptr_t)p, (uintptr_t)v, (uintptr_t)s, (uintptr_t)t, (uintptr_t)tmp,
                                       (uintptr_t)xR, (uintptr_t)part, (uintptr_t)st, (uintptr_t)AR,
-                                      (uintptr_t)FR.U[0], (uintptr_t)FR.K[0]};
+                                      (uintptr_t)FR.U[0], (uintptr_t)FR.K[0], (uintptr_t)FR.op_threads};
         gx = graph_for(C, key, [&](Exec& ee) { chunk(ee, poll); });
     }
     while (true) {
@@ -1921,6 +1926,11 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
             if (value < 1 || value > 100000) return fail(DDWC_EINVAL, "inner floor must be in [1, 100000] (x 1e-8)");
             C->opt_inner_floor = value;
             break;
+        case DDWC_OPT_OP_THREADS:
+            if (value != 128 && value != 256 && value != 512)
+                return fail(DDWC_EINVAL, "operator threads must be 128, 256 or 512");
+            C->opt_op_threads = value;
+            break;
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1938,15 +1948,17 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_BLOCK_LDS: *value = C->opt_blk_lds; break;
         case DDWC_OPT_BLOCK_KERNEL: *value = C->opt_blk_kernel; break;
         case DDWC_OPT_INNER_FLOOR: *value = C->opt_inner_floor; break;
+        case DDWC_OPT_OP_THREADS: *value = C->opt_op_threads; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;
 }
 
 // Times the schedule choices on this context's lattice with nrhs reproducible right-hand
-// sides and keeps the fastest: the block-solver workgroup size (one colour's block sweep),
-// then the poll interval and graph replay of the global solve.  Each candidate runs once to
-// warm up and once timed.
+// sides and keeps the fastest, one group after the other: the block inner solver (the
+// LDS-resident kernel where it applies; the global-memory kernel at each workgroup size and
+// residency) on one colour's block sweep, then the operator workgroup size of the global solve,
+// then its poll interval and graph replay.  Each candidate runs once to warm up and once timed.
 extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, double* seconds_host, void* stream) {
     CK(check_common(C, kappa, nrhs, prec));
     auto t0 = std::chrono::steady_clock::now();
@@ -1970,44 +1982,70 @@ extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, doub
         }
         return best;
     };
-    // block solver: workgroup size x residency (no LDS reservation, or one that leaves room for
-    // 2 or 4 persistent workgroups per CU)
+    // one schedule: the values of the options it sets
+    struct Sched {
+        int kernel, threads, lds;
+    };
+    const Sched saved = {C->opt_blk_kernel, C->opt_blk_threads, C->opt_blk_lds};
+    auto set = [&](const Sched& q) {
+        C->opt_blk_kernel = q.kernel;
+        C->opt_blk_threads = q.threads;
+        C->opt_blk_lds = q.lds;
+    };
+    // block solver: the LDS-resident kernel (its workgroup holds one block parity), and the
+    // global-memory kernel at each workgroup size x residency (no LDS reservation, or one that
+    // leaves room for 2 or 4 persistent workgroups per CU)
     int maxlds = 0;
     HC(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, C->device));
     auto per_cu = [&](int k) { return std::max(0, (maxlds / k - 2048) >> 10); };
-    const int saved_threads = C->opt_blk_threads, saved_lds = C->opt_blk_lds;
-    double best = 1e300;
-    int pick = saved_threads, pick_lds = saved_lds;
+    std::vector<Sched> cands;
+    if (C->g.eo && prec != DDWC_FP64 && blk_lds_fits(C->g, C->lds_max)) cands.push_back({0, 0, 0});
     for (int T : {0, 128, 256, 512})
-        for (int L : {0, per_cu(2), per_cu(4)}) {
-            C->opt_blk_threads = T;
-            C->opt_blk_lds = L;
-            const double t = timed([&]() {
-                Exec ex = make_exec(C, stream);
-                BlockInfo bi;
-                return block_internal(C, ex, 0, mass, b, x, nrhs, 1e-8, 5000, prec, &bi);
-            });
-            if (t < 0) {
-                C->opt_blk_threads = saved_threads;
-                C->opt_blk_lds = saved_lds;
-                return fail(DDWC_ENOCONV, "autotune: block solve failed");
-            }
-            if (t < best) best = t, pick = T, pick_lds = L;
+        for (int L : {0, per_cu(2), per_cu(4)}) cands.push_back({1, T, L});
+    double best = 1e300;
+    Sched pick = saved;
+    for (const Sched& q : cands) {
+        set(q);
+        const double t = timed([&]() {
+            Exec ex = make_exec(C, stream);
+            BlockInfo bi;
+            return block_internal(C, ex, 0, mass, b, x, nrhs, 1e-8, 5000, prec, &bi);
+        });
+        if (t < 0) {
+            set(saved);
+            return fail(DDWC_ENOCONV, "autotune: block solve failed");
         }
-    C->opt_blk_threads = pick;
-    C->opt_blk_lds = pick_lds;
-    const int saved_poll = C->opt_poll, saved_graphs = C->opt_graphs;
+        if (t < best) best = t, pick = q;
+    }
+    set(pick);
+    // global solve: operator workgroup size, then poll interval x graph replay
+    auto solve_time = [&]() {
+        return timed([&]() {
+            Exec ex = make_exec(C, stream);
+            SolveInfo si;
+            return solve_internal(C, ex, mass, b, x, nrhs, 1e-8, 5000, prec, &si);
+        });
+    };
+    const int saved_op = C->opt_op_threads, saved_poll = C->opt_poll, saved_graphs = C->opt_graphs;
+    best = 1e300;
+    int po = saved_op;
+    for (int nt : {128, 256, 512}) {
+        C->opt_op_threads = nt;
+        const double t = solve_time();
+        if (t < 0) {
+            C->opt_op_threads = saved_op;
+            return fail(DDWC_ENOCONV, "autotune: global solve failed");
+        }
+        if (t < best) best = t, po = nt;
+    }
+    C->opt_op_threads = po;
     best = 1e300;
     int pp = saved_poll, pg = saved_graphs;
     for (int poll : {2, 4, 8})
         for (int graphs : {0, 1}) {
             C->opt_poll = poll;
             C->opt_graphs = graphs;
-            const double t = timed([&]() {
-                Exec ex = make_exec(C, stream);
-                SolveInfo si;
-                return solve_internal(C, ex, mass, b, x, nrhs, 1e-8, 5000, prec, &si);
-            });
+            const double t = solve_time();
             if (t < 0) {
                 C->opt_poll = saved_poll;
                 C->opt_graphs = saved_graphs;

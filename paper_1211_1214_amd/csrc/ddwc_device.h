@@ -553,8 +553,10 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // forward links are read from Uf at s, backward links from Ub at the neighbour.  Both
 // index spaces are colour-major, so a neighbour lies in the same Schwarz block exactly
 // when it lies in the same half.  `ndir` is 8; it is a run-time value so that the
-// direction loop stays a loop and only one neighbour spinor and link are live at a time
-// (PIPE: the next direction's loads are issued before the current one is computed).
+// direction loop stays a loop and only one neighbour spinor and link are live at a time.
+// PIPE 1: the next direction's spinor and link loads are issued before the current one is
+// computed; PIPE 2: the next spinor only (links read where they are used: staged in LDS, their
+// latency is short, and the registers go to more waves in flight).
 //
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
@@ -562,7 +564,7 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // With LK_OWN the records may be a staged copy (in LDS) that starts at site `l0`: the record of
 // s is then record s - l0 of Uf.  With nstr > 0 the neighbour table is a staged copy too,
 // [8][nstr] entries starting at site l0.
-template <class R, int HOPS, bool PIPE, int LK = LK_ENTRY, class W, class L>
+template <class R, int HOPS, int PIPE, int LK = LK_ENTRY, class W, class L>
 DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<L>* __restrict__ Uf,
                      const cx<L>* __restrict__ Ub, const int* __restrict__ nbr, cx<R> acc[12], int ndir,
                      unsigned smul = 1, unsigned sadd = 0, unsigned sstride = 0, unsigned l0 = 0,
@@ -594,7 +596,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
         }
     } else {
         // all eight table entries first, then a software-pipelined direction loop: the
-        // neighbour spinor and link of direction d + 1 are in flight while d is computed
+        // neighbour spinor (and, PIPE 1, link) of direction d + 1 are in flight while d is computed
         int ent[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * ns, sn);
@@ -603,7 +605,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             const int e = ent[0];
             const unsigned t0 = e < 0 ? (unsigned)~e : (unsigned)e;
             load_spinor(in, sstride, t0 * smul + sadd, q);
-            hop_link<LK>(Uf, Ub, n, 0, LK == LK_OWN ? sl : s, t0, u);
+            if (PIPE == 1) hop_link<LK>(Uf, Ub, n, 0, LK == LK_OWN ? sl : s, t0, u);
         }
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
@@ -620,9 +622,10 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
                 load_spinor(in, sstride, tn * smul + sadd, qn);
-                hop_link<LK>(Uf, Ub, n, d + 1, LK == LK_OWN ? sl : s, tn, un);
+                if (PIPE == 1) hop_link<LK>(Uf, Ub, n, d + 1, LK == LK_OWN ? sl : s, tn, un);
             }
             if (take) {
+                if (PIPE != 1) hop_link<LK>(Uf, Ub, n, d, LK == LK_OWN ? sl : s, t, u);
                 if (e < 0) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) q[c] = -q[c];
@@ -631,8 +634,10 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             }
 #pragma unroll
             for (int c = 0; c < 12; ++c) q[c] = qn[c];
+            if (PIPE == 1) {
 #pragma unroll
-            for (int c = 0; c < 9; ++c) u[c] = un[c];
+                for (int c = 0; c < 9; ++c) u[c] = un[c];
+            }
         }
     }
 }
@@ -683,11 +688,11 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
 
 // Per-RHS partial sums of a workgroup whose thread j holds values of RHS (g0 + j) mod nrhs
 // (RHS-innermost work items): thread r < nrhs sums its RHS in a fixed order and writes
-// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= 256.
-template <int NV>
+// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= NT.
+template <int NV, int NT = 256>
 __device__ __forceinline__ void seg_partials(const double v[NV], double* part, int ntiles, int tile, unsigned g0,
                                              int nrhs, int stride) {
-    __shared__ double lds[NV][256];
+    __shared__ double lds[NV][NT];
 #pragma unroll
     for (int k = 0; k < NV; ++k) lds[k][threadIdx.x] = v[k];
     __syncthreads();

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "ddwc_device.h"
@@ -203,7 +204,22 @@ struct EoFields {
     const cx<typename Traits<R>::link>* U[2];           // [4][9][n2] links of the sites of parity p
     const typename Traits<R>::kword* K[2];              // clover of the sites of parity p
     const int* nbr[2];                                  // [8][n2] neighbour half indices (other parity)
+    int op_threads = WG;                                // workgroup size of the RHS-innermost operator kernels
 };
+
+// Workgroup size and tile count of the operator kernels (launch_eo_hopinv / launch_eo_diaghop) on
+// nrhs RHS: the RHS-innermost FP32 and FP16 kernels take op_threads (WG where it is below nrhs: a
+// workgroup's partial sums need every RHS in it), the others WG (RHS-major: per tile of sites).
+template <class R>
+inline int eo_op_threads(const EoFields<R>& F, int nrhs, bool ri) {
+    return ri && !std::is_same<R, double>::value && nrhs <= F.op_threads ? F.op_threads : WG;
+}
+template <class R>
+inline int eo_op_tiles(const EoFields<R>& F, int nrhs, bool ri) {
+    const long long n = ri ? (long long)F.n2 * nrhs : (long long)F.n2;
+    const int t = eo_op_threads(F, nrhs, ri);
+    return (int)((n + t - 1) / t);
+}
 
 // FP16 copy of n FP32 complex link entries.
 void launch_links_to_half(Exec& e, size_t n, const cx<float>* src, cx<f16>* dst);

@@ -118,13 +118,21 @@ constexpr int site_major_links() {
     return RI && !std::is_same<S, double>::value ? LK_OWN : LK_ENTRY;
 }
 
+// Pipelining of the hop loop (hop_sum): with the links, clover and table staged in LDS the
+// unpipelined loop's fewer registers (about 100 against 146) buy a fourth and fifth wave per
+// SIMD, which hides the neighbour-spinor latency better than loading one direction ahead.
+template <bool STG>
+constexpr int hop_pipe() {
+    return STG ? 0 : 1;
+}
+
 // Work items as for the vector kernels (vec_items.h): RHS-major fields or, with RI, the
 // RHS-innermost layout in which the lanes of a site share its links, clover and table.
 
 // y_p = A_pp^-1 (c_p + alpha H_{p,1-p} x), over the n2 sites of parity p.  c may be null,
 // alpha = 0 skips the hops.  S is the storage (double, float or H16), arithmetic in its real.
-template <class S, bool RI, bool STG>
-__global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Traits<S>::word* __restrict__ x,
+template <class S, bool RI, bool STG, int NT>
+__global__ __launch_bounds__(NT) void k_eo_hopinv(unsigned n2, const typename Traits<S>::word* __restrict__ x,
                                                   const typename Traits<S>::word* __restrict__ c,
                                                   typename Traits<S>::real alpha,
                                                   const cx<typename Traits<S>::link>* __restrict__ Up,
@@ -133,24 +141,24 @@ __global__ __launch_bounds__(WG) void k_eo_hopinv(unsigned n2, const typename Tr
                                                   const typename Traits<S>::kword* __restrict__ Ainv,
                                                   typename Traits<S>::word* __restrict__ y, int nrhs, int ntiles) {
     typedef typename Traits<S>::real R;
-    const VItem it = vitem<RI>(n2, nrhs, ntiles);
+    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Ak = Ainv;
     const int* nb = nbrp;
     unsigned kst = n2, l0 = 0, nstr = 0;
     if (STG) {
-        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Ainv, nbrp);
+        const Staged<S> sd = stage_site_data<S, NT>(it, n2, nrhs, Up, Ainv, nbrp);
         Uf = sd.U;
         Ak = sd.K;
         nb = sd.nbr;
-        kst = nstr = STG_SITES;
+        kst = nstr = stg_sites<NT>();
         l0 = sd.l0;
     }
     if (!it.ok) return;
     const VView<RI, S> w(n2, nrhs, it.i, it.r);
     cx<R> acc[12], out[12];
     if (alpha != R(0))
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, x + w.base, Uf, Uq, nb, acc, 8,
+        hop_sum<R, HOPS_ALL, hop_pipe<STG>(), site_major_links<S, RI>()>(n2, it.i, x + w.base, Uf, Uq, nb, acc, 8,
                                                               RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0, nstr);
     else
 #pragma unroll
@@ -175,8 +183,8 @@ enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
 // y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
 // Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
 // RESID: y = aux - y and partial ||y||^2.
-template <class S, int EPI, bool USE_A, bool RI, bool STG>
-__global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename Traits<S>::word* __restrict__ c,
+template <class S, int EPI, bool USE_A, bool RI, bool STG, int NT>
+__global__ __launch_bounds__(NT) void k_eo_diaghop(unsigned n2, const typename Traits<S>::word* __restrict__ c,
                                                    const typename Traits<S>::word* __restrict__ t,
                                                    typename Traits<S>::real beta,
                                                    const cx<typename Traits<S>::link>* __restrict__ Up,
@@ -188,24 +196,24 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
                                                    typename Traits<S>::word* __restrict__ y, double* part, int nrhs,
                                                    int ntiles) {
     typedef typename Traits<S>::real R;
-    const VItem it = vitem<RI>(n2, nrhs, ntiles);
+    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Kk = Kp;
     const int* nb = nbrp;
     unsigned kst = n2, l0 = 0, nstr = 0;
     if (STG) {
-        const Staged<S> sd = stage_site_data<S>(it, n2, nrhs, Up, Kp, nbrp);
+        const Staged<S> sd = stage_site_data<S, NT>(it, n2, nrhs, Up, Kp, nbrp);
         Uf = sd.U;
         Kk = sd.K;
         nb = sd.nbr;
-        kst = nstr = STG_SITES;
+        kst = nstr = stg_sites<NT>();
         l0 = sd.l0;
     }
     double v[3] = {0, 0, 0};
     if (it.ok) {
         const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
-        hop_sum<R, HOPS_ALL, true, site_major_links<S, RI>()>(n2, it.i, t + w.base, Uf, Uq, nb, acc, 8,
+        hop_sum<R, HOPS_ALL, hop_pipe<STG>(), site_major_links<S, RI>()>(n2, it.i, t + w.base, Uf, Uq, nb, acc, 8,
                                                               RI ? nrhs : 1, RI ? it.r : 0, w.stride, l0, nstr);
         load_spinor(c + w.base, w.stride, w.idx, cc);
         if (USE_A) {
@@ -232,9 +240,22 @@ __global__ __launch_bounds__(WG) void k_eo_diaghop(unsigned n2, const typename T
             v[2] = acc_nrm(acc);
         }
     }
-    if (EPI == EOE_DOT) vpartials<2, RI>(v, part, ntiles, it, nrhs);
-    if (EPI == EOE_DOT2) vpartials<3, RI>(v, part, ntiles, it, nrhs);
-    if (EPI == EOE_RESID) vpartials<1, RI>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_DOT) vpartials<2, RI, NT>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_DOT2) vpartials<3, RI, NT>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_RESID) vpartials<1, RI, NT>(v, part, ntiles, it, nrhs);
+}
+
+// Calls f(std::integral_constant<int, NT>) for the RHS-innermost workgroup size nt (FP64: WG only).
+template <class S, class Fn>
+static void with_op_threads(int nt, Fn&& f) {
+    if constexpr (!std::is_same<S, double>::value) {
+        switch (nt) {
+            case 128: f(std::integral_constant<int, 128>()); return;
+            case 512: f(std::integral_constant<int, 512>()); return;
+            default: break;
+        }
+    }
+    f(std::integral_constant<int, WG>());
 }
 
 template <class S>
@@ -243,16 +264,22 @@ void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typen
                       typename Traits<S>::word* y, int nrhs, int kclass, double bytes) {
     typedef typename Traits<S>::real R;
     Timed t(e, kclass, bytes);
-    const int nt = vector_tiles(F.n2, nrhs, ri);
-    if (ri && stage_ok<S>(nrhs))
-        k_eo_hopinv<S, true, true><<<nt, WG, stage_bytes<S>(), e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
-                                                                          F.nbr[p], Ainv, y, nrhs, nt);
-    else if (ri)
-        k_eo_hopinv<S, true, false><<<nt, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p],
-                                                             Ainv, y, nrhs, nt);
-    else
-        k_eo_hopinv<S, false, false><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
+    const int nt = eo_op_tiles(F, nrhs, ri);
+    if (!ri) {
+        k_eo_hopinv<S, false, false, WG><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
+                                                                         F.nbr[p], Ainv, y, nrhs, nt);
+        return;
+    }
+    const bool stg = stage_ok<S>(nrhs);
+    with_op_threads<S>(eo_op_threads(F, nrhs, ri), [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        if (stg)
+            k_eo_hopinv<S, true, true, NT><<<nt, NT, stage_bytes<S, NT>(), e.stream>>>(
+                F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y, nrhs, nt);
+        else
+            k_eo_hopinv<S, true, false, NT><<<nt, NT, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
                                                                      F.nbr[p], Ainv, y, nrhs, nt);
+    });
 }
 
 template <class S>
@@ -262,35 +289,37 @@ void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, b
                        int nrhs, int kclass, double bytes) {
     typedef typename Traits<S>::real R;
     Timed tm(e, kclass, bytes);
-    const int nt = vector_tiles(F.n2, nrhs, ri);
-    const int ng = ri ? nt : nt * nrhs;
+    const int nt = eo_op_tiles(F, nrhs, ri);
     const bool stg = ri && stage_ok<S>(nrhs);
-#define EOL(EP, UA, RIV)                                                                                            \
-    if (stg)                                                                                                        \
-        k_eo_diaghop<S, EP, UA, RIV, true><<<ng, WG, stage_bytes<S>(), e.stream>>>(                                 \
-            F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);          \
-    else                                                                                                            \
-        k_eo_diaghop<S, EP, UA, RIV, false><<<ng, WG, 0, e.stream>>>(F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p],      \
-                                                                     F.nbr[p], F.K[p], (R)mass4, aux, y, part,      \
-                                                                     nrhs, nt)
-#define EOSW(RIV)                                            \
-    if (use_a) {                                             \
-        switch (epi) {                                       \
-            case EOE_DOT: EOL(EOE_DOT, true, RIV); break;    \
-            case EOE_DOT2: EOL(EOE_DOT2, true, RIV); break;  \
-            case EOE_RESID: EOL(EOE_RESID, true, RIV); break; \
-            default: EOL(EOE_NONE, true, RIV); break;        \
-        }                                                    \
-    } else {                                                 \
-        EOL(EOE_NONE, false, RIV);                           \
-    }
-    if (ri) {
-        EOSW(true)
-    } else {
-        EOSW(false)
-    }
-#undef EOSW
-#undef EOL
+    auto launch = [&](auto epc, auto uac, auto ric, auto ntc) {
+        constexpr int EP = decltype(epc)::value, NT = decltype(ntc)::value;
+        constexpr bool UA = decltype(uac)::value, RIV = decltype(ric)::value;
+        const int ng = RIV ? nt : nt * nrhs;
+        if (RIV && stg)
+            k_eo_diaghop<S, EP, UA, RIV, RIV, NT><<<ng, NT, stage_bytes<S, NT>(), e.stream>>>(
+                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);
+        else
+            k_eo_diaghop<S, EP, UA, RIV, false, NT><<<ng, NT, 0, e.stream>>>(
+                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);
+    };
+    typedef std::integral_constant<bool, true> T_;
+    typedef std::integral_constant<bool, false> F_;
+    auto epilogue = [&](auto ric, auto ntc) {
+        if (!use_a) {
+            launch(std::integral_constant<int, EOE_NONE>(), F_(), ric, ntc);
+            return;
+        }
+        switch (epi) {
+            case EOE_DOT: launch(std::integral_constant<int, EOE_DOT>(), T_(), ric, ntc); break;
+            case EOE_DOT2: launch(std::integral_constant<int, EOE_DOT2>(), T_(), ric, ntc); break;
+            case EOE_RESID: launch(std::integral_constant<int, EOE_RESID>(), T_(), ric, ntc); break;
+            default: launch(std::integral_constant<int, EOE_NONE>(), T_(), ric, ntc); break;
+        }
+    };
+    if (ri)
+        with_op_threads<S>(eo_op_threads(F, nrhs, ri), [&](auto ntc) { epilogue(T_(), ntc); });
+    else
+        epilogue(F_(), std::integral_constant<int, WG>());
 }
 
 #define EO_INST(S)                                                                                                 \

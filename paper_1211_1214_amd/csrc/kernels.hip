@@ -769,14 +769,14 @@ __global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __r
         Uf = sd.U;
         Kk = sd.K;
         nb = sd.nbr;
-        kst = nstr = STG_SITES;
+        kst = nstr = stg_sites<WG>();
         l0 = sd.l0;
     }
     if (!it.ok) return;
     const VView<true, float> w((unsigned)g.V, nrhs, it.i, it.r);
     cx<float> acc[12], c[12];
-    hop_sum<float, HOPS_ALL, true, LK_OWN>((unsigned)g.V, it.i, in, Uf, Uf, nb, acc, 8, (unsigned)nrhs,
-                                           (unsigned)it.r, w.stride, l0, nstr);
+    hop_sum<float, HOPS_ALL, STG ? 0 : 1, LK_OWN>((unsigned)g.V, it.i, in, Uf, Uf, nb, acc, 8, (unsigned)nrhs,
+                                                  (unsigned)it.r, w.stride, l0, nstr);
     load_spinor(in, w.stride, w.idx, c);
     apply_diag<float>(Kk, kst, it.i - l0, mass4, c, acc, -0.5f);
     store_spinor(out, w.stride, w.idx, acc);

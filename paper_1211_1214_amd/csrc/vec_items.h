@@ -50,7 +50,8 @@ struct VItem {
     unsigned g0;  // first pair of the workgroup (RI)
 };
 
-template <bool RI>
+// NT: threads per workgroup of an RHS-innermost kernel (the RHS-major path always uses WG).
+template <bool RI, int NT = WG>
 __device__ __forceinline__ VItem vitem(unsigned n, int nrhs, int ntiles) {
     VItem it;
     if (!RI) {
@@ -62,7 +63,7 @@ __device__ __forceinline__ VItem vitem(unsigned n, int nrhs, int ntiles) {
         it.g0 = 0;
     } else {
         it.tile = xcd_remap(blockIdx.x, ntiles);
-        it.g0 = (unsigned)it.tile * WG;
+        it.g0 = (unsigned)it.tile * NT;
         const unsigned gi = it.g0 + threadIdx.x;
         it.ok = gi < n * (unsigned)nrhs;
         it.i = gi / (unsigned)nrhs;
@@ -89,10 +90,10 @@ struct VView {
     }
 };
 
-template <int NV, bool RI>
+template <int NV, bool RI, int NT = WG>
 __device__ __forceinline__ void vpartials(double v[NV], double* part, int ntiles, const VItem& it, int nrhs) {
     if (RI) {
-        seg_partials<NV>(v, part, ntiles, it.tile, it.g0, nrhs, NPART);
+        seg_partials<NV, NT>(v, part, ntiles, it.tile, it.g0, nrhs, NPART);
     } else {
         TileRhs tr;
         tr.tile = it.tile;
@@ -106,15 +107,18 @@ __device__ __forceinline__ void vpartials(double v[NV], double* part, int ntiles
 // a workgroup covers are copied into LDS with coalesced loads before the hop loop, which then
 // reads them there: one copy per site instead of one vector-memory load per (site, RHS) lane.
 constexpr int STG_MIN_RHS = 8;
-constexpr int STG_SITES = WG / STG_MIN_RHS + 2;  // sites that WG consecutive (site, RHS) pairs can touch
+template <int NT = WG>
+constexpr int stg_sites() {  // sites that NT consecutive (site, RHS) pairs can touch
+    return NT / STG_MIN_RHS + 2;
+}
 
 template <class S>
 constexpr unsigned record_words() {  // 16-byte words of one own-site link record
     return 8 * 9 * sizeof(cx<typename Traits<S>::link>) / 16;
 }
-template <class S>
+template <class S, int NT = WG>
 constexpr size_t stage_bytes() {
-    return (size_t)STG_SITES * ((record_words<S>() + Traits<S>::NKW) * 16 + 8 * sizeof(int));
+    return (size_t)stg_sites<NT>() * ((record_words<S>() + Traits<S>::NKW) * 16 + 8 * sizeof(int));
 }
 
 // Staging applies to the RHS-innermost low-precision kernels (own-site link records) with enough
@@ -127,36 +131,36 @@ inline bool stage_ok(int nrhs) {
 template <class S>
 struct Staged {
     const cx<typename Traits<S>::link>* U;  // link records of sites l0, l0 + 1, ...
-    const typename Traits<S>::kword* K;     // clover words [NKW][STG_SITES] of the same sites
-    const int* nbr;                         // neighbour-table entries [8][STG_SITES] of the same sites
+    const typename Traits<S>::kword* K;     // clover words [NKW][stg_sites] of the same sites
+    const int* nbr;                         // neighbour-table entries [8][stg_sites] of the same sites
     unsigned l0;
 };
 
 // Copies the records, clover words and table entries of the sites of the workgroup's pairs;
 // every thread of the workgroup must call it (it ends with a barrier).
-template <class S>
+template <class S, int NT = WG>
 __device__ __forceinline__ Staged<S> stage_site_data(const VItem& it, unsigned n2, int nrhs,
                                                      const cx<typename Traits<S>::link>* __restrict__ Up,
                                                      const typename Traits<S>::kword* __restrict__ K,
                                                      const int* __restrict__ nbr) {
     typedef typename Traits<S>::kword KW;
     extern __shared__ float4 stg[];
-    constexpr unsigned RW = record_words<S>();
+    constexpr unsigned RW = record_words<S>(), NS = stg_sites<NT>();
     const unsigned l0 = it.g0 / (unsigned)nrhs;
-    unsigned l1 = (it.g0 + WG - 1) / (unsigned)nrhs + 1;
+    unsigned l1 = (it.g0 + NT - 1) / (unsigned)nrhs + 1;
     if (l1 > n2) l1 = n2;
-    const unsigned ns = l1 - l0;  // <= STG_SITES for nrhs >= STG_MIN_RHS
+    const unsigned ns = l1 - l0;  // <= NS for nrhs >= STG_MIN_RHS
     const float4* src = (const float4*)Up + (size_t)l0 * RW;
-    for (unsigned k = threadIdx.x; k < ns * RW; k += WG) stg[k] = src[k];
-    KW* ck = (KW*)(stg + STG_SITES * RW);
-    for (unsigned k = threadIdx.x; k < Traits<S>::NKW * ns; k += WG) {
+    for (unsigned k = threadIdx.x; k < ns * RW; k += NT) stg[k] = src[k];
+    KW* ck = (KW*)(stg + NS * RW);
+    for (unsigned k = threadIdx.x; k < Traits<S>::NKW * ns; k += NT) {
         const unsigned w = k / ns, j = k - w * ns;
-        ck[w * STG_SITES + j] = K[(size_t)w * n2 + l0 + j];
+        ck[w * NS + j] = K[(size_t)w * n2 + l0 + j];
     }
-    int* cn = (int*)(ck + Traits<S>::NKW * STG_SITES);
-    for (unsigned k = threadIdx.x; k < 8 * ns; k += WG) {
+    int* cn = (int*)(ck + Traits<S>::NKW * NS);
+    for (unsigned k = threadIdx.x; k < 8 * ns; k += NT) {
         const unsigned d = k / ns, j = k - d * ns;
-        cn[d * STG_SITES + j] = nbr[(size_t)d * n2 + l0 + j];
+        cn[d * NS + j] = nbr[(size_t)d * n2 + l0 + j];
     }
     __syncthreads();
     Staged<S> st;

@@ -468,11 +468,10 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
                 launch_dslash_dot<R>(ex, g, U, K, mass4, p, v, rh, part, nrhs, kcl, dbytes + rb);
                 launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_ALPHA, nullptr);
                 launch_bicg_s<R>(ex, g.V, false, st, r, v, s, nrhs);
-                launch_dslash_dot2<R>(ex, g, U, K, mass4, s, t, part, nrhs, kcl, dbytes);
+                launch_dslash_dot4<R>(ex, g, U, K, mass4, s, t, rh, part, nrhs, kcl, dbytes + rb);
                 launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_OMEGA, nullptr);
-                launch_bicg_xr<R>(ex, g.V, false, st, xR, p, s, t, rh, r, part, nrhs);
-                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_BETA, nullptr);
-                launch_bicg_p<R>(ex, g.V, false, st, r, v, p, nrhs);
+                launch_bicg_xrp<R>(ex, g.V, false, st, xR, p, s, t, v, r, part, nrhs);
+                launch_finalize(ex, part, nt, nrhs, nullptr, st, ST_RR, nullptr);
             }
             HC(hipGetLastError());
             HC(hipMemcpyAsync(h_st, st, sizeof(BiState) * nrhs, hipMemcpyDeviceToHost, sm));
@@ -736,17 +735,18 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         auto apply_M = [&](const W* in, W* out, int epi, const W* aux) {
             launch_eo_hopinv<S>(ee, FR, 1, ri, in, nullptr, 1.0, AR, tmp, nrhs, fp64 ? kcl : DDWC_K_EOHOP, hbytes);
             launch_eo_diaghop<S>(ee, FR, 0, ri, epi, true, in, tmp, -0.25, mass4, aux, out, part, nrhs, kcl,
-                                 hbytes + (epi == 1 ? (double)nrhs * n2 * rs : 0.0));
+                                 hbytes + (double)nrhs * n2 * rs);
         };
+        // BiCGStab (van der Vorst) with the next rho taken from the dot products of t = M s, so
+        // that x, r and p are updated in one pass
         for (int k = 0; k < iters; ++k) {
             apply_M(p, v, 1, rh);
             launch_finalize(ee, part, ntM, nrhs, nullptr, st, ST_ALPHA, nullptr);
             launch_bicg_s<S>(ee, n2, ri, st, r, v, s, nrhs);
-            apply_M(s, t, 2, nullptr);
+            apply_M(s, t, 2, rh);
             launch_finalize(ee, part, ntM, nrhs, nullptr, st, ST_OMEGA, nullptr);
-            launch_bicg_xr<S>(ee, n2, ri, st, xR, p, s, t, rh, r, part, nrhs);
-            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_BETA, nullptr);
-            launch_bicg_p<S>(ee, n2, ri, st, r, v, p, nrhs);
+            launch_bicg_xrp<S>(ee, n2, ri, st, xR, p, s, t, v, r, part, nrhs);
+            launch_finalize(ee, part, ntR, nrhs, nullptr, st, ST_RR, nullptr);
         }
     };
     // a chunk of `poll` iterations replayed from a graph (every argument of its launches is in

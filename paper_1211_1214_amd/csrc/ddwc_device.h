@@ -688,13 +688,14 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
 
 // Per-RHS partial sums of a workgroup whose thread j holds values of RHS (g0 + j) mod nrhs
 // (RHS-innermost work items): thread r < nrhs sums its RHS in a fixed order and writes
-// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= NT.
-template <int NV, int NT = 256>
+// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= NT.  The values pass
+// through LDS as T (float where every value is an FP32 sum converted to double: exact).
+template <int NV, int NT = 256, class T = double>
 __device__ __forceinline__ void seg_partials(const double v[NV], double* part, int ntiles, int tile, unsigned g0,
                                              int nrhs, int stride) {
-    __shared__ double lds[NV][NT];
+    __shared__ T lds[NV][NT];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds[k][threadIdx.x] = v[k];
+    for (int k = 0; k < NV; ++k) lds[k][threadIdx.x] = (T)v[k];
     __syncthreads();
     if ((int)threadIdx.x < nrhs) {
         const int r = threadIdx.x;
@@ -704,7 +705,7 @@ __device__ __forceinline__ void seg_partials(const double v[NV], double* part, i
         for (int k = 0; k < NV; ++k) acc[k] = 0;
         for (int j = j0; j < (int)blockDim.x; j += nrhs)
 #pragma unroll
-            for (int k = 0; k < NV; ++k) acc[k] += lds[k][j];
+            for (int k = 0; k < NV; ++k) acc[k] += (double)lds[k][j];
         double* p = part + ((size_t)r * ntiles + tile) * stride;
 #pragma unroll
         for (int k = 0; k < NV; ++k) p[k] = acc[k];

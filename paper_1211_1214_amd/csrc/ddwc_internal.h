@@ -18,7 +18,10 @@ struct BiState {
     int broken;   // breakdown (zero denominator) detected
 };
 
-enum Stage { ST_SUM = 0, ST_INIT = 1, ST_ALPHA = 2, ST_OMEGA = 3, ST_BETA = 4 };
+// Stages of the global BiCGStab's finalize (k_finalize): ST_OMEGA takes (t, s), (t, t), (rh, s) and
+// (rh, t) and sets omega, the next rho = (rh, s) - omega (rh, t) = (rh, r_new) and beta, so that one
+// kernel updates x, r and p; ST_RR takes ||r_new||^2 and decides convergence.
+enum Stage { ST_SUM = 0, ST_INIT = 1, ST_ALPHA = 2, ST_OMEGA = 3, ST_RR = 4 };
 
 // Spinor masks for import / combination kernels.
 enum Mask { MASK_ALL = 0, MASK_P = 1, MASK_BLACK = 2, MASK_WHITE = 3 };
@@ -67,7 +70,7 @@ struct Timed {
 
 // ------------------------------------------------------------------ launchers (kernels.hip)
 constexpr int WG = 256;  // sites per workgroup of the site-parallel kernels
-constexpr int NPART = 4; // doubles per partial-sum slot
+constexpr int NPART = 8; // doubles per partial-sum slot
 
 inline int tiles_of(int n) { return (n + WG - 1) / WG; }
 
@@ -101,11 +104,11 @@ template <class R>
 void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
                        const typename Traits<R>::word* in, typename Traits<R>::word* out,
                        const typename Traits<R>::word* w, double* part, int nrhs, int kclass, double bytes);
-// out = D(m) in, partials (out, in) complex and (out, out).
+// out = D(m) in, partials (out, in) complex, (out, out), (rh, in) and (rh, out) complex.
 template <class R>
-void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
-                        const typename Traits<R>::word* in, typename Traits<R>::word* out, double* part, int nrhs,
-                        int kclass, double bytes);
+void launch_dslash_dot4(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                        const typename Traits<R>::word* in, typename Traits<R>::word* out,
+                        const typename Traits<R>::word* rh, double* part, int nrhs, int kclass, double bytes);
 // r = b - D(m) x, partial ||r||^2.
 template <class R>
 void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
@@ -136,14 +139,11 @@ void launch_bicg_init(Exec& e, unsigned n, bool ri, const double2* r64, const do
 template <class S>
 void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
                    const typename Traits<S>::word* v, typename Traits<S>::word* s, int nrhs);
+// x += alpha p + omega s; r = s - omega t; p = r + beta (p - omega v); partial ||r||^2.
 template <class S>
-void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
-                    const typename Traits<S>::word* p, const typename Traits<S>::word* s,
-                    const typename Traits<S>::word* t, const typename Traits<S>::word* rh,
-                    typename Traits<S>::word* r, double* part, int nrhs);
-template <class S>
-void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
-                   const typename Traits<S>::word* v, typename Traits<S>::word* p, int nrhs);
+void launch_bicg_xrp(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
+                     typename Traits<S>::word* p, const typename Traits<S>::word* s, const typename Traits<S>::word* t,
+                     const typename Traits<S>::word* v, typename Traits<S>::word* r, double* part, int nrhs);
 // x64 += (1/scale) * x per RHS (RHS with scale 0 untouched); x in Traits<S>::xs.
 template <class S>
 void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typename Traits<S>::xs>::word* x,

@@ -178,11 +178,11 @@ __global__ __launch_bounds__(NT) void k_eo_hopinv(unsigned n2, const typename Tr
     store_spinor(y + w.base, w.stride, w.idx, out);
 }
 
-enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT2 = 2, EOE_RESID = 3 };
+enum EoEpi { EOE_NONE = 0, EOE_DOT = 1, EOE_DOT4 = 2, EOE_RESID = 3 };
 
 // y_p = [A_pp] c_p + beta H_{p,1-p} t (USE_A: clover + mass on c, else c itself).
-// Epilogues as for the full operator: DOT partial (aux, y); DOT2 partials (y, c), (y, y);
-// RESID: y = aux - y and partial ||y||^2.
+// Epilogues as for the full operator: DOT partial (aux, y); DOT4 partials (y, c), (y, y),
+// (aux, c), (aux, y); RESID: y = aux - y and partial ||y||^2.
 template <class S, int EPI, bool USE_A, bool RI, bool STG, int NT>
 __global__ __launch_bounds__(NT) void k_eo_diaghop(unsigned n2, const typename Traits<S>::word* __restrict__ c,
                                                    const typename Traits<S>::word* __restrict__ t,
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_eo_diaghop(unsigned n2, const typename T
         kst = nstr = stg_sites<NT>();
         l0 = sd.l0;
     }
-    double v[3] = {0, 0, 0};
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (it.ok) {
         const VView<RI, S> w(n2, nrhs, it.i, it.r);
         cx<R> acc[12], cc[12];
@@ -235,14 +235,18 @@ __global__ __launch_bounds__(NT) void k_eo_diaghop(unsigned n2, const typename T
             load_spinor(aux + w.base, w.stride, w.idx, q);
             acc_dot(q, acc, v[0], v[1]);
         }
-        if (EPI == EOE_DOT2) {
+        if (EPI == EOE_DOT4) {
             acc_dot(acc, cc, v[0], v[1]);
             v[2] = acc_nrm(acc);
+            cx<R> q[12];
+            load_spinor(aux + w.base, w.stride, w.idx, q);
+            acc_dot(q, cc, v[3], v[4]);
+            acc_dot(q, acc, v[5], v[6]);
         }
     }
-    if (EPI == EOE_DOT) vpartials<2, RI, NT>(v, part, ntiles, it, nrhs);
-    if (EPI == EOE_DOT2) vpartials<3, RI, NT>(v, part, ntiles, it, nrhs);
-    if (EPI == EOE_RESID) vpartials<1, RI, NT>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_DOT) vpartials<2, RI, NT, R>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_DOT4) vpartials<7, RI, NT, R>(v, part, ntiles, it, nrhs);
+    if (EPI == EOE_RESID) vpartials<1, RI, NT, R>(v, part, ntiles, it, nrhs);
 }
 
 // Calls f(std::integral_constant<int, NT>) for the RHS-innermost workgroup size nt (FP64: WG only).
@@ -311,7 +315,7 @@ void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, b
         }
         switch (epi) {
             case EOE_DOT: launch(std::integral_constant<int, EOE_DOT>(), T_(), ric, ntc); break;
-            case EOE_DOT2: launch(std::integral_constant<int, EOE_DOT2>(), T_(), ric, ntc); break;
+            case EOE_DOT4: launch(std::integral_constant<int, EOE_DOT4>(), T_(), ric, ntc); break;
             case EOE_RESID: launch(std::integral_constant<int, EOE_RESID>(), T_(), ric, ntc); break;
             default: launch(std::integral_constant<int, EOE_NONE>(), T_(), ric, ntc); break;
         }

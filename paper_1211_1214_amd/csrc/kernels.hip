@@ -153,7 +153,9 @@ void launch_export(Exec& e, const Geom& g, const typename Traits<R>::word* in, v
 }
 
 // ------------------------------------------------------------------ operator kernels
-enum Epi { EPI_NONE = 0, EPI_DOT = 1, EPI_DOT2 = 2, EPI_RESID = 3 };
+// Epilogues: DOT partial (aux, y); DOT4 partials (y, in), (y, y), (aux, in), (aux, y) (the global
+// BiCGStab's t = M s with aux = rh); RESID: y = aux - y and partial ||y||^2.
+enum Epi { EPI_NONE = 0, EPI_DOT = 1, EPI_DOT4 = 2, EPI_RESID = 3 };
 
 template <class R, int EPI>
 __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __restrict__ U,
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
     TileRhs tr = tile_rhs(ntiles, nrhs);
     const int s = tr.tile * WG + threadIdx.x;
     const size_t off = (size_t)tr.rhs * Traits<R>::NCW * g.V;
-    double v[3] = {0, 0, 0};
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (s < g.V) {
         cx<R> y[12];
         site_operator<R, true, HOPS_ALL, true>(g, s, in + off, U, K, nbr, mass4, y, ndir);
@@ -183,15 +185,18 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
             load_spinor(aux + off, g.V, s, w);
             acc_dot(w, y, v[0], v[1]);
         }
-        if (EPI == EPI_DOT2) {
-            cx<R> c[12];
+        if (EPI == EPI_DOT4) {
+            cx<R> c[12], w[12];
             load_spinor(in + off, g.V, s, c);
             acc_dot(y, c, v[0], v[1]);  // (t, s)
             v[2] = acc_nrm(y);          // (t, t)
+            load_spinor(aux + off, g.V, s, w);
+            acc_dot(w, c, v[3], v[4]);  // (rh, s)
+            acc_dot(w, y, v[5], v[6]);  // (rh, t)
         }
     }
     if (EPI == EPI_DOT) write_partials<2>(v, part, ntiles, tr);
-    if (EPI == EPI_DOT2) write_partials<3>(v, part, ntiles, tr);
+    if (EPI == EPI_DOT4) write_partials<7>(v, part, ntiles, tr);
     if (EPI == EPI_RESID) write_partials<1>(v, part, ntiles, tr);
 }
 
@@ -212,12 +217,12 @@ void launch_dslash_dot(Exec& e, const Geom& g, const cx<R>* U, const typename Tr
     k_dslash<R, EPI_DOT><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, w, part, nrhs, nt, e.nbr, 8);
 }
 template <class R>
-void launch_dslash_dot2(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
-                        const typename Traits<R>::word* in, typename Traits<R>::word* out, double* part, int nrhs,
-                        int kclass, double bytes) {
+void launch_dslash_dot4(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
+                        const typename Traits<R>::word* in, typename Traits<R>::word* out,
+                        const typename Traits<R>::word* rh, double* part, int nrhs, int kclass, double bytes) {
     Timed t(e, kclass, bytes);
     int nt = tiles_of(g.V);
-    k_dslash<R, EPI_DOT2><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, nullptr, part, nrhs, nt, e.nbr, 8);
+    k_dslash<R, EPI_DOT4><<<nt * nrhs, WG, 0, e.stream>>>(g, U, K, (R)mass4, in, out, rh, part, nrhs, nt, e.nbr, 8);
 }
 template <class R>
 void launch_residual(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* K, double mass4,
@@ -328,22 +333,24 @@ __global__ __launch_bounds__(WG) void k_bicg_s(unsigned n, const BiState* __rest
     store_spinor(s_out + w.base, w.stride, w.idx, a);
 }
 
+// x += alpha p + omega s; r = s - omega t; p = r + beta (p - omega v); partial ||r||^2.  beta was
+// set from the dot products of t = M s (ST_OMEGA), so the three updates share one pass.
 template <class S, bool RI>
-__global__ __launch_bounds__(WG) void k_bicg_xr(unsigned n, const BiState* __restrict__ st,
-                                                typename Traits<typename Traits<S>::xs>::word* __restrict__ x,
-                                                const typename Traits<S>::word* __restrict__ p,
-                                                const typename Traits<S>::word* __restrict__ sv,
-                                                const typename Traits<S>::word* __restrict__ t,
-                                                const typename Traits<S>::word* __restrict__ rh,
-                                                typename Traits<S>::word* __restrict__ r, double* part, int nrhs,
-                                                int ntiles) {
+__global__ __launch_bounds__(WG) void k_bicg_xrp(unsigned n, const BiState* __restrict__ st,
+                                                 typename Traits<typename Traits<S>::xs>::word* __restrict__ x,
+                                                 typename Traits<S>::word* __restrict__ p,
+                                                 const typename Traits<S>::word* __restrict__ sv,
+                                                 const typename Traits<S>::word* __restrict__ t,
+                                                 const typename Traits<S>::word* __restrict__ v,
+                                                 typename Traits<S>::word* __restrict__ r, double* part, int nrhs,
+                                                 int ntiles) {
     VTYPES(S);
     const VItem it = vitem<RI>(n, nrhs, ntiles);
-    double v[3] = {0, 0, 0};
+    double q[1] = {0};
     if (it.ok) {
         const VView<RI, S> w(n, nrhs, it.i, it.r);
         const VView<RI, XS> wx(n, nrhs, it.i, it.r);
-        const cx<R> al = cxs<R>(st[it.r].alpha), om = cxs<R>(st[it.r].omega);
+        const cx<R> al = cxs<R>(st[it.r].alpha), om = cxs<R>(st[it.r].omega), be = cxs<R>(st[it.r].beta);
         cx<XS> xx[12];
         cx<R> pp[12], ss[12], tt[12];
         load_spinor(x + wx.base, wx.stride, wx.idx, xx);
@@ -359,30 +366,13 @@ __global__ __launch_bounds__(WG) void k_bicg_xr(unsigned n, const BiState* __res
         store_spinor(x + wx.base, wx.stride, wx.idx, xx);
         store_spinor(r + w.base, w.stride, w.idx, ss);
         if (std::is_same<S, H16>::value) load_spinor(r + w.base, w.stride, w.idx, ss);  // r as stored
-        load_spinor(rh + w.base, w.stride, w.idx, pp);
-        acc_dot(pp, ss, v[0], v[1]);
-        v[2] = acc_nrm(ss);
-    }
-    vpartials<3, RI>(v, part, ntiles, it, nrhs);
-}
-
-template <class S, bool RI>
-__global__ __launch_bounds__(WG) void k_bicg_p(unsigned n, const BiState* __restrict__ st,
-                                               const typename Traits<S>::word* __restrict__ r,
-                                               const typename Traits<S>::word* __restrict__ v,
-                                               typename Traits<S>::word* __restrict__ p, int nrhs, int ntiles) {
-    VTYPES(S);
-    const VItem it = vitem<RI>(n, nrhs, ntiles);
-    if (!it.ok) return;
-    const VView<RI, S> w(n, nrhs, it.i, it.r);
-    const cx<R> be = cxs<R>(st[it.r].beta), om = cxs<R>(st[it.r].omega);
-    cx<R> rr[12], pp[12], vv[12];
-    load_spinor(r + w.base, w.stride, w.idx, rr);
-    load_spinor(p + w.base, w.stride, w.idx, pp);
-    load_spinor(v + w.base, w.stride, w.idx, vv);
+        q[0] = acc_nrm(ss);
+        load_spinor(v + w.base, w.stride, w.idx, tt);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) pp[k] = rr[k] + be * (pp[k] - om * vv[k]);
-    store_spinor(p + w.base, w.stride, w.idx, pp);
+        for (int k = 0; k < 12; ++k) pp[k] = ss[k] + be * (pp[k] - om * tt[k]);
+        store_spinor(p + w.base, w.stride, w.idx, pp);
+    }
+    vpartials<1, RI>(q, part, ntiles, it, nrhs);
 }
 
 template <class S, bool RI>
@@ -434,18 +424,11 @@ void launch_bicg_s(Exec& e, unsigned n, bool ri, const BiState* st, const typena
     VDISPATCH(k_bicg_s, S, st, r, v, s);
 }
 template <class S>
-void launch_bicg_xr(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
-                    const typename Traits<S>::word* p, const typename Traits<S>::word* s,
-                    const typename Traits<S>::word* t, const typename Traits<S>::word* rh,
-                    typename Traits<S>::word* r, double* part, int nrhs) {
+void launch_bicg_xrp(Exec& e, unsigned n, bool ri, const BiState* st, typename Traits<typename Traits<S>::xs>::word* x,
+                     typename Traits<S>::word* p, const typename Traits<S>::word* s, const typename Traits<S>::word* t,
+                     const typename Traits<S>::word* v, typename Traits<S>::word* r, double* part, int nrhs) {
     Timed tm(e, 3, 0);
-    VDISPATCH(k_bicg_xr, S, st, x, p, s, t, rh, r, part);
-}
-template <class S>
-void launch_bicg_p(Exec& e, unsigned n, bool ri, const BiState* st, const typename Traits<S>::word* r,
-                   const typename Traits<S>::word* v, typename Traits<S>::word* p, int nrhs) {
-    Timed t(e, 3, 0);
-    VDISPATCH(k_bicg_p, S, st, r, v, p);
+    VDISPATCH(k_bicg_xrp, S, st, x, p, s, t, v, r, part);
 }
 template <class S>
 void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typename Traits<S>::xs>::word* x,
@@ -505,7 +488,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
                                                   double* __restrict__ sums, BiState* __restrict__ st, int stage,
                                                   const double* __restrict__ thr_rel2) {
     const int rhs = blockIdx.x;
-    double v[NPART] = {0, 0, 0, 0};
+    double v[NPART] = {};
     for (int w = threadIdx.x; w < ntiles; w += blockDim.x) {
         const double* p = part + ((size_t)rhs * ntiles + w) * NPART;
 #pragma unroll
@@ -538,38 +521,44 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
             S.alpha[0] = S.alpha[1] = 0;
         }
     } else if (stage == ST_OMEGA) {
+        // v: (t, s), (t, t), (rh, s), (rh, t).  omega = (t, s) / (t, t); the next rho is
+        // (rh, s - omega t) = (rh, s) - omega (rh, t); beta = (rho_next / rho) (alpha / omega).
+        S.beta[0] = S.beta[1] = 0;
         if (S.active && v[2] > 0 && isfinite(v[2])) {
             S.omega[0] = v[0] / v[2];
             S.omega[1] = v[1] / v[2];
+            const double nr = v[3] - (S.omega[0] * v[5] - S.omega[1] * v[6]);
+            const double ni = v[4] - (S.omega[0] * v[6] + S.omega[1] * v[5]);
+            const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
+            const double rh2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+            if (om2 > 0 && rh2 > 0) {
+                const double qr = (nr * S.rho[0] + ni * S.rho[1]) / rh2;
+                const double qi = (ni * S.rho[0] - nr * S.rho[1]) / rh2;
+                const double ar = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
+                const double ai = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
+                S.beta[0] = qr * ar - qi * ai;
+                S.beta[1] = qr * ai + qi * ar;
+            }
+            S.rho[0] = nr;
+            S.rho[1] = ni;
         } else {
-            // t = 0 means s = 0: x += alpha p is exact, stop here
+            // t = 0 means s = 0: x += alpha p is exact, and ST_RR stops here
             S.omega[0] = S.omega[1] = 0;
             if (S.active && !(v[2] >= 0)) S.broken = 1;
         }
-    } else if (stage == ST_BETA) {
+    } else if (stage == ST_RR) {
         if (S.active) {
-            S.rr = v[2];
-            double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
-            double rh2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
-            if (!isfinite(v[2])) {
+            S.rr = v[0];
+            const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
+            const double rh2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+            if (!isfinite(v[0])) {
                 S.broken = 1;
                 S.active = 0;
-            } else if (v[2] <= S.thr2) {
+            } else if (v[0] <= S.thr2) {
                 S.active = 0;
             } else if (om2 == 0 || rh2 == 0) {
                 S.broken = 1;
                 S.active = 0;
-            }
-            if (S.active) {
-                // beta = (rho_new / rho) (alpha / omega)
-                double qr = (v[0] * S.rho[0] + v[1] * S.rho[1]) / rh2;
-                double qi = (v[1] * S.rho[0] - v[0] * S.rho[1]) / rh2;
-                double ar = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
-                double ai = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
-                S.beta[0] = qr * ar - qi * ai;
-                S.beta[1] = qr * ai + qi * ar;
-                S.rho[0] = v[0];
-                S.rho[1] = v[1];
             }
         }
         if (!S.active) {
@@ -812,8 +801,9 @@ void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float
     template void launch_dslash_dot<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,          \
                                        const Traits<R>::word*, Traits<R>::word*, const Traits<R>::word*, double*, \
                                        int, int, double);                                                         \
-    template void launch_dslash_dot2<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,         \
-                                        const Traits<R>::word*, Traits<R>::word*, double*, int, int, double);     \
+    template void launch_dslash_dot4<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,         \
+                                        const Traits<R>::word*, Traits<R>::word*, const Traits<R>::word*,         \
+                                        double*, int, int, double);                                               \
     template void launch_residual<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, double,            \
                                      const Traits<R>::word*, const Traits<R>::word*, Traits<R>::word*, double*,   \
                                      int, int, double);                                                           \
@@ -823,11 +813,9 @@ void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float
                                       Traits<R>::word*, Traits<R>::word*, Traits<R>::word*, double*, int);        \
     template void launch_bicg_s<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \
                                    const Traits<R>::word*, Traits<R>::word*, int);                                \
-    template void launch_bicg_xr<R>(Exec&, unsigned, bool, const BiState*, Traits<R>::word*,                      \
-                                    const Traits<R>::word*, const Traits<R>::word*, const Traits<R>::word*,       \
-                                    const Traits<R>::word*, Traits<R>::word*, double*, int);                      \
-    template void launch_bicg_p<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \
-                                   const Traits<R>::word*, Traits<R>::word*, int);                                \
+    template void launch_bicg_xrp<R>(Exec&, unsigned, bool, const BiState*, Traits<R>::word*, Traits<R>::word*,   \
+                                     const Traits<R>::word*, const Traits<R>::word*, const Traits<R>::word*,      \
+                                     Traits<R>::word*, double*, int);                                             \
     template void launch_accumulate<R>(Exec&, unsigned, bool, const Traits<R>::word*, const double*, double2*, int);
 
 INST(double)
@@ -836,9 +824,8 @@ INST(float)
 template void launch_bicg_init<H16>(Exec&, unsigned, bool, const double2*, const double*, hw16*, hw16*, hw16*, float4*,
                                     double*, int);
 template void launch_bicg_s<H16>(Exec&, unsigned, bool, const BiState*, const hw16*, const hw16*, hw16*, int);
-template void launch_bicg_xr<H16>(Exec&, unsigned, bool, const BiState*, float4*, const hw16*, const hw16*,
-                                  const hw16*, const hw16*, hw16*, double*, int);
-template void launch_bicg_p<H16>(Exec&, unsigned, bool, const BiState*, const hw16*, const hw16*, hw16*, int);
+template void launch_bicg_xrp<H16>(Exec&, unsigned, bool, const BiState*, float4*, hw16*, const hw16*, const hw16*,
+                                   const hw16*, hw16*, double*, int);
 template void launch_accumulate<H16>(Exec&, unsigned, bool, const float4*, const double*, double2*, int);
 
 }  // namespace ddwc

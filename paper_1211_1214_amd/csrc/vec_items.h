@@ -90,10 +90,10 @@ struct VView {
     }
 };
 
-template <int NV, bool RI, int NT = WG>
+template <int NV, bool RI, int NT = WG, class T = double>
 __device__ __forceinline__ void vpartials(double v[NV], double* part, int ntiles, const VItem& it, int nrhs) {
     if (RI) {
-        seg_partials<NV, NT>(v, part, ntiles, it.tile, it.g0, nrhs, NPART);
+        seg_partials<NV, NT, T>(v, part, ntiles, it.tile, it.g0, nrhs, NPART);
     } else {
         TileRhs tr;
         tr.tile = it.tile;

@@ -483,7 +483,7 @@ static int global_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, 
         launch_accumulate<R>(ex, g.V, false, xR, scale, x64, nrhs);
         launch_residual<double>(ex, g, C->U64, C->K64, mass4, x64, b64, r64, part, nrhs, DDWC_K_DSLASH64,
                                 ddwc_dslash_bytes(C, nrhs, DDWC_FP64) + (double)nrhs * g.V * 192.0);
-        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr, 1);
         HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
         HC(hipStreamSynchronize(sm));
         for (int k = 0; k < nrhs; ++k) {
@@ -802,7 +802,7 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
         // r_e = b'_e - Mee x_e in FP64
         launch_eo_hopinv<double>(ex, F64, 1, false, xe, nullptr, 1.0, A64, to, nrhs, DDWC_K_DSLASH64, 0);
         launch_eo_diaghop<double>(ex, F64, 0, false, 3, true, xe, to, -0.25, mass4, bpe, re, part, nrhs, DDWC_K_DSLASH64, 0);
-        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr);
+        launch_finalize(ex, part, nt, nrhs, sums, nullptr, ST_SUM, nullptr, 1);
         HC(hipMemcpyAsync(h_sums, sums, sizeof(double) * nrhs * NPART, hipMemcpyDeviceToHost, sm));
         HC(hipStreamSynchronize(sm));
         for (int k = 0; k < nrhs; ++k) {

@@ -66,6 +66,13 @@ __host__ __device__ __forceinline__ size_t slab_words(unsigned n2) {
     return (size_t)Traits<S>::NCW * n2 + (std::is_same<S, H16>::value ? n2 / 4 : 0);
 }
 
+// Direction loop of the in-block hops (hop_sum): unrolled for FP64 and FP32 storage, rolled for
+// FP16 (unrolled it spills).
+template <class S>
+constexpr int blk_hop_mode() {
+    return std::is_same<S, H16>::value ? 0 : 2;
+}
+
 template <class S>
 __device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename Traits<S>::word* x,
                                          const typename Traits<S>::word* c, typename Traits<S>::real alpha,
@@ -73,7 +80,7 @@ __device__ __forceinline__ void odd_pass(unsigned n2, unsigned j, const typename
                                          cx<typename Traits<S>::real> w[12]) {
     typedef typename Traits<S>::real R;
     cx<R> acc[12];
-    hop_sum<R, HOPS_INSIDE, false>(n2, j, x, F.U[1], F.U[0], F.nbr[1], acc, 8);
+    hop_sum<R, HOPS_INSIDE, blk_hop_mode<S>()>(n2, j, x, F.U[1], F.U[0], F.nbr[1], acc, 8);
     if (c) {
         cx<R> cc[12];
         load_spinor(c, n2, j, cc);
@@ -96,7 +103,7 @@ __device__ __forceinline__ void even_pass(unsigned n2, unsigned i, const typenam
                                           cx<typename Traits<S>::real> y[12]) {
     typedef typename Traits<S>::real R;
     cx<R> cc[12];
-    hop_sum<R, HOPS_INSIDE, false>(n2, i, t, F.U[0], F.U[1], F.nbr[0], y, 8);
+    hop_sum<R, HOPS_INSIDE, blk_hop_mode<S>()>(n2, i, t, F.U[0], F.U[1], F.nbr[0], y, 8);
     load_spinor(c, n2, i, cc);
     if (USE_A) {
         apply_diag<R>(F.K[0], n2, i, mass4, cc, y, beta);
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_prep(Geom g, EoFields<do
         cx<double> be[12], y[12], z[12];
         load_spinor(b + of, g.V, s, be);
         red[0] += acc_nrm(be);
-        hop_sum<double, HOPS_INSIDE, false>(n2, i, to + oh, F.U[0], F.U[1], F.nbr[0], y, 8);
+        hop_sum<double, HOPS_INSIDE, 2>(n2, i, to + oh, F.U[0], F.U[1], F.nbr[0], y, 8);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             y[c] = be[c] + 0.5 * y[c];
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, EoFields<d
         // x_o = A_oo^-1 (b_o + 1/2 H^k x_e)
         load_spinor(b + of, g.V, full_index(g, j, 1), bo);
         cx<double> acc[12];
-        hop_sum<double, HOPS_INSIDE, false>(n2, j, xe + oh, F.U[1], F.U[0], F.nbr[1], acc, 8);
+        hop_sum<double, HOPS_INSIDE, 2>(n2, j, xe + oh, F.U[1], F.U[0], F.nbr[1], acc, 8);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             acc[c] = bo[c] + 0.5 * acc[c];
@@ -431,7 +438,10 @@ __device__ __forceinline__ void lds_store(float4* __restrict__ L, unsigned HV, u
 // t - h0 < HV) of (1 -+ g_mu) W q(t), q read from LDS at t - h0; forward links Uf at s, backward
 // links Ub at t (entry-major [4][9][n2]); nbr is the half-field table [8][n2] of s's parity.
 // Software-pipelined: while hop d is applied, the link of hop d + 1 and the table entry of hop
-// d + 2 are in flight (about one global latency per pass instead of one or two per hop).
+// d + 2 are in flight (about one global latency per pass instead of one or two per hop).  The
+// direction loop is unrolled: with a run-time direction the spin algebra sat behind a switch
+// whose merge copied the accumulator and the prefetched link (42 moves per hop against 108
+// arithmetic instructions); unrolled, the block kernel is 6.7% faster with identical results.
 __device__ __forceinline__ void lds_hops(unsigned n2, unsigned s, unsigned h0, unsigned HV,
                                          const float4* __restrict__ L, const cx<float>* __restrict__ Uf,
                                          const cx<float>* __restrict__ Ub, const int* __restrict__ nbr,
@@ -444,7 +454,7 @@ __device__ __forceinline__ void lds_hops(unsigned n2, unsigned s, unsigned h0, u
         const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
         if (t - h0 < HV) hop_link<LK_ENTRY>(Uf, Ub, n2, 0, s, t, u);
     }
-#pragma unroll 1
+#pragma unroll
     for (int d = 0; d < 8; ++d) {
         const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
         int enn = 0;

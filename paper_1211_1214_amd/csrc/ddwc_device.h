@@ -555,8 +555,11 @@ enum HopSet { HOPS_NONE = 0, HOPS_ALL = 1, HOPS_INSIDE = 2, HOPS_CROSSING = 3 };
 // when it lies in the same half.  `ndir` is 8; it is a run-time value so that the
 // direction loop stays a loop and only one neighbour spinor and link are live at a time.
 // PIPE 1: the next direction's spinor and link loads are issued before the current one is
-// computed; PIPE 2: the next spinor only (links read where they are used: staged in LDS, their
-// latency is short, and the registers go to more waves in flight).
+// computed.  PIPE 2: the direction loop is unrolled (no pipelining): the spin algebra of each
+// direction is then straight-line code instead of a switch whose merge copies the accumulator
+// (24 moves per hop); for hop sets with a per-hop condition (inside / crossing), whose branches
+// keep the scheduler from hoisting every direction's loads.  (With HOPS_ALL the unrolled loop
+// hoists them all: 256 VGPRs.)
 //
 // Spinors may be stored RHS-innermost: the spinor of site t is element t * smul + sadd of
 // component arrays sstride apart (RHS-major: smul = 1, sadd = 0, sstride = n).  Links are
@@ -576,9 +579,9 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
     for (int c = 0; c < 12; ++c) acc[c] = mk(R(0), R(0));
     if (HOPS == HOPS_NONE) return;
     const bool s_black = s < n / 2;
-    if (!PIPE) {
-#pragma unroll 1
-        for (int d = 0; d < ndir; ++d) {
+    if (PIPE == 0 || PIPE == 2) {
+#pragma unroll(PIPE == 2 ? 8 : 1)
+        for (int d = 0; d < (PIPE == 2 ? 8 : ndir); ++d) {
             const int e = at(nbr + (size_t)d * ns, sn);
             const unsigned t = e < 0 ? (unsigned)~e : (unsigned)e;
             const bool inside = (t < n / 2) == s_black;
@@ -596,7 +599,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
         }
     } else {
         // all eight table entries first, then a software-pipelined direction loop: the
-        // neighbour spinor (and, PIPE 1, link) of direction d + 1 are in flight while d is computed
+        // neighbour spinor and link of direction d + 1 are in flight while d is computed
         int ent[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d) ent[d] = at(nbr + (size_t)d * ns, sn);
@@ -605,7 +608,7 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             const int e = ent[0];
             const unsigned t0 = e < 0 ? (unsigned)~e : (unsigned)e;
             load_spinor(in, sstride, t0 * smul + sadd, q);
-            if (PIPE == 1) hop_link<LK>(Uf, Ub, n, 0, LK == LK_OWN ? sl : s, t0, u);
+            hop_link<LK>(Uf, Ub, n, 0, LK == LK_OWN ? sl : s, t0, u);
         }
 #pragma unroll 1
         for (int d = 0; d < ndir; ++d) {
@@ -622,10 +625,9 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
                 for (int k = 2; k < 8; ++k) en = d + 1 == k ? ent[k] : en;
                 const unsigned tn = en < 0 ? (unsigned)~en : (unsigned)en;
                 load_spinor(in, sstride, tn * smul + sadd, qn);
-                if (PIPE == 1) hop_link<LK>(Uf, Ub, n, d + 1, LK == LK_OWN ? sl : s, tn, un);
+                hop_link<LK>(Uf, Ub, n, d + 1, LK == LK_OWN ? sl : s, tn, un);
             }
             if (take) {
-                if (PIPE != 1) hop_link<LK>(Uf, Ub, n, d, LK == LK_OWN ? sl : s, t, u);
                 if (e < 0) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) q[c] = -q[c];
@@ -634,17 +636,15 @@ DDWC_HD void hop_sum(unsigned n, unsigned s, const W* __restrict__ in, const cx<
             }
 #pragma unroll
             for (int c = 0; c < 12; ++c) q[c] = qn[c];
-            if (PIPE == 1) {
 #pragma unroll
-                for (int c = 0; c < 9; ++c) u[c] = un[c];
-            }
+            for (int c = 0; c < 9; ++c) u[c] = un[c];
         }
     }
 }
 
 // y = [diag] (4+m+C) psi(s) - 1/2 sum over the selected hops, on full fields.  `in`
 // points at one RHS, nbr is the neighbour table [8][V].
-template <class R, bool DIAG, int HOPS, bool PIPE = false>
+template <class R, bool DIAG, int HOPS, int PIPE = 0>
 DDWC_HD void site_operator(const Geom& g, unsigned s, const typename Traits<R>::word* __restrict__ in,
                            const cx<R>* __restrict__ U, const typename Traits<R>::word* __restrict__ K,
                            const int* __restrict__ nbr, R mass4, cx<R> y[12], int ndir) {
@@ -688,11 +688,11 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
 
 // Per-RHS partial sums of a workgroup whose thread j holds values of RHS (g0 + j) mod nrhs
 // (RHS-innermost work items): thread r < nrhs sums its RHS in a fixed order and writes
-// part[(r * ntiles + tile) * stride + k].  Needs nrhs <= blockDim.x <= NT.  The values pass
+// part[(k * nrhs + r) * ntiles + tile].  Needs nrhs <= blockDim.x <= NT.  The values pass
 // through LDS as T (float where every value is an FP32 sum converted to double: exact).
 template <int NV, int NT = 256, class T = double>
 __device__ __forceinline__ void seg_partials(const double v[NV], double* part, int ntiles, int tile, unsigned g0,
-                                             int nrhs, int stride) {
+                                             int nrhs) {
     __shared__ T lds[NV][NT];
 #pragma unroll
     for (int k = 0; k < NV; ++k) lds[k][threadIdx.x] = (T)v[k];
@@ -706,9 +706,8 @@ __device__ __forceinline__ void seg_partials(const double v[NV], double* part, i
         for (int j = j0; j < (int)blockDim.x; j += nrhs)
 #pragma unroll
             for (int k = 0; k < NV; ++k) acc[k] += (double)lds[k][j];
-        double* p = part + ((size_t)r * ntiles + tile) * stride;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) p[k] = acc[k];
+        for (int k = 0; k < NV; ++k) part[((size_t)k * nrhs + r) * ntiles + tile] = acc[k];
     }
 }
 

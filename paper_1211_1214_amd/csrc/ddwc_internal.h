@@ -151,7 +151,7 @@ void launch_accumulate(Exec& e, unsigned n, bool ri, const typename Traits<typen
 
 // Sums partials per RHS in a fixed order and applies the BiCGStab stage update.
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
-                     const double* thr_rel2);
+                     const double* thr_rel2, int nv = -1);
 
 // dst = src over n 16-byte words (streaming reference kernel).
 void launch_stream_copy(Exec& e, const float4* src, float4* dst, size_t n);

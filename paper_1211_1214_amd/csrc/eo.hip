@@ -120,7 +120,9 @@ constexpr int site_major_links() {
 
 // Pipelining of the hop loop (hop_sum): with the links, clover and table staged in LDS the
 // unpipelined loop's fewer registers (about 100 against 146) buy a fourth and fifth wave per
-// SIMD, which hides the neighbour-spinor latency better than loading one direction ahead.
+// SIMD, which hides the neighbour-spinor latency better than loading one direction ahead.  (In
+// FP64 the pipelined loop needs 254 VGPRs, one wave per SIMD, and is still as fast as the
+// unpipelined one at two waves.)
 template <bool STG>
 constexpr int hop_pipe() {
     return STG ? 0 : 1;

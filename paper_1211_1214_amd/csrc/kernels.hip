@@ -171,7 +171,7 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (s < g.V) {
         cx<R> y[12];
-        site_operator<R, true, HOPS_ALL, true>(g, s, in + off, U, K, nbr, mass4, y, ndir);
+        site_operator<R, true, HOPS_ALL, 1>(g, s, in + off, U, K, nbr, mass4, y, ndir);
         if (EPI == EPI_RESID) {
             cx<R> b[12];
             load_spinor((const W*)aux + off, g.V, s, b);
@@ -195,9 +195,9 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_dslash(Geom g, const cx<R>* __r
             acc_dot(w, y, v[5], v[6]);  // (rh, t)
         }
     }
-    if (EPI == EPI_DOT) write_partials<2>(v, part, ntiles, tr);
-    if (EPI == EPI_DOT4) write_partials<7>(v, part, ntiles, tr);
-    if (EPI == EPI_RESID) write_partials<1>(v, part, ntiles, tr);
+    if (EPI == EPI_DOT) write_partials<2>(v, part, ntiles, nrhs, tr);
+    if (EPI == EPI_DOT4) write_partials<7>(v, part, ntiles, nrhs, tr);
+    if (EPI == EPI_RESID) write_partials<1>(v, part, ntiles, nrhs, tr);
 }
 
 template <class R>
@@ -252,7 +252,8 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __rest
         keep = (sum & 1) == cut_colour;
     }
     if (keep) {
-        site_operator<R, false, HOPS_CROSSING, true>(g, s, in + off, U, nullptr, nbr, R(0), y, ndir);
+        // unrolled: 138 VGPRs in FP64 against 256 and AGPRs for the pipelined loop
+        site_operator<R, false, HOPS_CROSSING, 2>(g, s, in + off, U, nullptr, nbr, R(0), y, ndir);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) y[k] = mk(R(0), R(0));
@@ -484,21 +485,37 @@ void launch_stream_copy(Exec& e, const float4* src, float4* dst, size_t n) {
 }
 
 // ------------------------------------------------------------------ finalize (one workgroup per RHS)
+// Sums the first NV partial components of each RHS over the tiles (fixed order), then applies
+// the BiCGStab stage.  v has NPART entries so that every stage can name its components.
+template <int NV>
 __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ part, int ntiles, int nrhs,
                                                   double* __restrict__ sums, BiState* __restrict__ st, int stage,
                                                   const double* __restrict__ thr_rel2) {
     const int rhs = blockIdx.x;
     double v[NPART] = {};
-    for (int w = threadIdx.x; w < ntiles; w += blockDim.x) {
-        const double* p = part + ((size_t)rhs * ntiles + w) * NPART;
+    // four strides in flight per thread (independent sums, combined in a fixed order): a single
+    // workgroup per RHS is otherwise bound by the latency of one load round per stride
+    constexpr int U = 4;
+    double a[U][NV] = {};
+    const unsigned B = blockDim.x;
+    unsigned w = threadIdx.x;
+    for (; w + (U - 1) * B < (unsigned)ntiles; w += U * B) {
 #pragma unroll
-        for (int k = 0; k < NPART; ++k) v[k] += p[k];
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) a[u][k] += part[((size_t)k * nrhs + rhs) * ntiles + w + u * B];
     }
-    __shared__ double lds[NPART * 16];
-    block_sum<NPART>(v, lds);
+    for (; w < (unsigned)ntiles; w += B) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a[0][k] += part[((size_t)k * nrhs + rhs) * ntiles + w];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = (a[0][k] + a[1][k]) + (a[2][k] + a[3][k]);
+    __shared__ double lds[NV * 16];
+    block_sum<NV>(v, lds);
     if (threadIdx.x != 0) return;
     if (sums)
-        for (int k = 0; k < NPART; ++k) sums[rhs * NPART + k] = v[k];
+        for (int k = 0; k < NV; ++k) sums[rhs * NPART + k] = v[k];
     if (!st) return;
     BiState S = st[rhs];
     if (stage == ST_INIT) {
@@ -569,10 +586,18 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
 }
 
 void launch_finalize(Exec& e, const double* part, int ntiles, int nrhs, double* sums, BiState* st, int stage,
-                     const double* thr_rel2) {
+                     const double* thr_rel2, int nv) {
     Timed t(e, 3, 0);
+    if (nv < 0) nv = stage == ST_ALPHA ? 2 : stage == ST_OMEGA ? 7 : stage == ST_SUM ? 3 : 1;
     // one workgroup of 16 waves per RHS: the partial sums of up to ~10^4 tiles in a few strides
-    k_finalize<<<nrhs, 1024, 0, e.stream>>>(part, ntiles, nrhs, sums, st, stage, thr_rel2);
+#define FIN(N) k_finalize<N><<<nrhs, 1024, 0, e.stream>>>(part, ntiles, nrhs, sums, st, stage, thr_rel2)
+    switch (nv) {
+        case 1: FIN(1); break;
+        case 2: FIN(2); break;
+        case 3: FIN(3); break;
+        default: FIN(7); break;
+    }
+#undef FIN
 }
 
 // ------------------------------------------------------------------ FP64 helpers
@@ -704,7 +729,7 @@ __global__ __launch_bounds__(WG) void k_dots(Geom g, const double2* __restrict__
         acc_dot(a, b, v[0], v[1]);
         v[2] = acc_nrm(b);
     }
-    write_partials<3>(v, part, ntiles, tr);
+    write_partials<3>(v, part, ntiles, nrhs, tr);
 }
 
 void launch_dots(Exec& e, const Geom& g, const double2* x, const double2* y, double* part, int nrhs) {

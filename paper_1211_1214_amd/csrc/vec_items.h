@@ -27,14 +27,16 @@ __device__ __forceinline__ TileRhs tile_rhs(int ntiles, int nrhs) {
     return t;
 }
 
+// Partial sums are stored component-major: value k of (RHS r, tile w) at
+// part[(k * nrhs + r) * ntiles + w], so that a reduction over the tiles reads each component it
+// needs as one contiguous run.
 template <int NV>
-__device__ __forceinline__ void write_partials(double v[NV], double* part, int ntiles, TileRhs tr) {
+__device__ __forceinline__ void write_partials(double v[NV], double* part, int ntiles, int nrhs, TileRhs tr) {
     __shared__ double lds[NV * 16];
     block_sum<NV>(v, lds);
     if (threadIdx.x == 0) {
-        double* p = part + ((size_t)tr.rhs * ntiles + tr.tile) * NPART;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) p[k] = v[k];
+        for (int k = 0; k < NV; ++k) part[((size_t)k * nrhs + tr.rhs) * ntiles + tr.tile] = v[k];
     }
 }
 
@@ -93,12 +95,12 @@ struct VView {
 template <int NV, bool RI, int NT = WG, class T = double>
 __device__ __forceinline__ void vpartials(double v[NV], double* part, int ntiles, const VItem& it, int nrhs) {
     if (RI) {
-        seg_partials<NV, NT, T>(v, part, ntiles, it.tile, it.g0, nrhs, NPART);
+        seg_partials<NV, NT, T>(v, part, ntiles, it.tile, it.g0, nrhs);
     } else {
         TileRhs tr;
         tr.tile = it.tile;
         tr.rhs = it.r;
-        write_partials<NV>(v, part, ntiles, tr);
+        write_partials<NV>(v, part, ntiles, nrhs, tr);
     }
 }
 

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
                                                     double mass4, double tol, double inner_floor, int maxit,
                                                     int* iters, int colour, int nrhs) {
     extern __shared__ float4 bl_lds[];
-    __shared__ double red_lds[3 * 16];
+    __shared__ double red_lds[2][8 * 16];  // alternating slots of the workgroup reductions
     const BlkIdx k = blk_idx(g, colour, nrhs);
     const double b2 = bb[k.key], r2 = rr[k.key];
     if (!(b2 > 0) || !(r2 > tol * tol * b2) || !isfinite(r2)) return;  // uniform over the workgroup
@@ -530,7 +530,8 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
     const double rn = sqrt(r2), sc = 1.0 / rn;
     double eps = 0.5 * tol * sqrt(b2) / rn;
     if (eps < inner_floor) eps = inner_floor;
-    double red[3] = {0, 0, 0};
+    int phase = 0;  // reduction slot
+    double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (act) {
         cx<double> a[12];
         load_spinor(re + oh, n2, i, a);
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
         lds_store(op, HV, l, r);
         red[0] = acc_nrm(r);
     }
-    block_sum<1>(red, red_lds);  // (its barriers also publish the operand)
+    block_sum1<1>(red, red_lds[phase ^= 1]);  // (its barrier also publishes the operand)
     cx<double> rho = mk(red[0], 0.0);
     const double thr2 = eps * eps * red[0];
     int it = 0;
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
             lds_store(tp, HV, l, w);
         }
         __syncthreads();
-        red[0] = red[1] = red[2] = 0;
+        red[0] = red[1] = 0;
         if (act) {
             cx<float> v[12], h[12];
             even_lds(F, m4, i, l, h0, HV, op, tp, v);
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
             load_spinor(rhg, n2, i, h);
             acc_dot(h, v, red[0], red[1]);
         }
-        block_sum<2>(red, red_lds);
+        block_sum1<2>(red, red_lds[phase ^= 1]);
         if (!(red[0] * red[0] + red[1] * red[1] > 0)) break;
         const cx<float> alpha = cdiv_r<float>(rho, mk(red[0], red[1]));
         // s = r - alpha v (kept in r), staged as the operand
@@ -583,27 +584,49 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
             lds_store(op, HV, l, r);
         }
         __syncthreads();
-        // t = M_k s, (t, s), (t, t)
+        // t = M_k s, (t, s), (t, t), (rh, s), (rh, t), (s, s)
         if (act) {
             cx<float> w[12];
             odd_lds(F, Ainv, i, h0, HV, op, w);
             lds_store(tp, HV, l, w);
         }
         __syncthreads();
-        red[0] = red[1] = red[2] = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) red[c] = 0;
         cx<float> t[12];
         if (act) {
             even_lds(F, m4, i, l, h0, HV, op, tp, t);
-            cx<float> r[12];
-            lds_load(op, HV, l, r);
-            acc_dot(t, r, red[0], red[1]);
+            cx<float> sv[12], h[12];
+            lds_load(op, HV, l, sv);
+            acc_dot(t, sv, red[0], red[1]);
             red[2] = acc_nrm(t);
+            load_spinor(rhg, n2, i, h);
+            acc_dot(h, sv, red[3], red[4]);
+            acc_dot(h, t, red[5], red[6]);
+            red[7] = acc_nrm(sv);
         }
-        block_sum<3>(red, red_lds);
+        block_sum1<8>(red, red_lds[phase ^= 1]);
+        ++it;
         cx<float> omega = mk(0.f, 0.f);
         if (red[2] > 0) omega = mk((float)(red[0] / red[2]), (float)(red[1] / red[2]));
-        // e += alpha p + omega s ; r = s - omega t ; (rh, r), (r, r)
-        red[0] = red[1] = red[2] = 0;
+        // r = s - omega t is orthogonal to t, so ||r||^2 = (s, s) - |(t, s)|^2 / (t, t); the next
+        // rho = (rh, r) = (rh, s) - omega (rh, t): one reduction serves omega, the stopping test and
+        // beta, and x, r and p are updated in one pass
+        const double r2n = red[2] > 0 ? red[7] - (red[0] * red[0] + red[1] * red[1]) / red[2] : red[7];
+        const cx<double> rn_ = mk(red[3] - ((double)omega.re * red[5] - (double)omega.im * red[6]),
+                                  red[4] - ((double)omega.re * red[6] + (double)omega.im * red[5]));
+        const double d1 = rho.re * rho.re + rho.im * rho.im;
+        const double d2 = (double)omega.re * omega.re + (double)omega.im * omega.im;
+        const bool stop = r2n <= thr2 || !isfinite(r2n) || !(d2 > 0) || !(d1 > 0);
+        cx<float> beta = mk(0.f, 0.f);
+        if (!stop) {
+            const cx<double> q = mk((rn_.re * rho.re + rn_.im * rho.im) / d1, (rn_.im * rho.re - rn_.re * rho.im) / d1);
+            const cx<double> ao = mk(((double)alpha.re * omega.re + (double)alpha.im * omega.im) / d2,
+                                     ((double)alpha.im * omega.re - (double)alpha.re * omega.im) / d2);
+            beta = mk((float)(q.re * ao.re - q.im * ao.im), (float)(q.re * ao.im + q.im * ao.re));
+        }
+        rho = rn_;
+        // e += alpha p + omega s ; r = s - omega t ; p = r + beta (p - omega v), staged as the next operand
         if (act) {
             cx<float> e[12], pp[12], r[12];
             lds_load(op, HV, l, r);
@@ -615,34 +638,18 @@ __global__ __launch_bounds__(BL_MAX) void k_blk_lds(Geom g, EoFields<float> F, c
                 r[c] = r[c] - omega * t[c];
             }
             store_spinor(eg, n2, i, e);
-            store_spinor(rg, n2, i, r);
-            load_spinor(rhg, n2, i, pp);
-            acc_dot(pp, r, red[0], red[1]);
-            red[2] = acc_nrm(r);
-        }
-        block_sum<3>(red, red_lds);
-        ++it;
-        if (red[2] <= thr2 || !isfinite(red[2])) break;
-        if (omega.re == 0.f && omega.im == 0.f) break;
-        const double d1 = rho.re * rho.re + rho.im * rho.im;
-        if (!(d1 > 0)) break;
-        const cx<double> q = mk((red[0] * rho.re + red[1] * rho.im) / d1, (red[1] * rho.re - red[0] * rho.im) / d1);
-        const double d2 = (double)omega.re * omega.re + (double)omega.im * omega.im;
-        const cx<double> ao = mk(((double)alpha.re * omega.re + (double)alpha.im * omega.im) / d2,
-                                 ((double)alpha.im * omega.re - (double)alpha.re * omega.im) / d2);
-        const cx<float> beta = mk((float)(q.re * ao.re - q.im * ao.im), (float)(q.re * ao.im + q.im * ao.re));
-        rho = mk(red[0], red[1]);
-        // p = r + beta (p - omega v), staged as the next operand
-        if (act) {
-            cx<float> pp[12], v[12], r[12];
-            load_spinor(rg, n2, i, r);
-            load_spinor(pg, n2, i, pp);
-            load_spinor(vg, n2, i, v);
+            if (!stop) {
+                cx<float> v[12];
+                store_spinor(rg, n2, i, r);
+                load_spinor(vg, n2, i, v);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) pp[c] = r[c] + beta * (pp[c] - omega * v[c]);
-            store_spinor(pg, n2, i, pp);
-            lds_store(op, HV, l, pp);
+                for (int c = 0; c < 12; ++c) pp[c] = r[c] + beta * (pp[c] - omega * v[c]);
+                store_spinor(pg, n2, i, pp);
+                // (only this thread reads its own operand slot after the last barrier)
+                lds_store(op, HV, l, pp);
+            }
         }
+        if (stop) break;
         __syncthreads();
     }
     // x_e += ||r_e|| e in FP64

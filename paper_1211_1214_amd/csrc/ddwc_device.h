@@ -669,6 +669,25 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Workgroup sum with one barrier: `lds` (NV x 16 doubles) must not be the slot of the previous
+// block_sum1 of the workgroup (alternate two slots), which all threads have finished reading
+// before any of them reaches this barrier.
+template <int NV>
+__device__ __forceinline__ void block_sum1(double v[NV], double* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < NV; ++k) lds[k * 16 + wave] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = 0;
+        for (int w = 0; w < nw; ++w) t += lds[k * 16 + w];
+        v[k] = t;
+    }
+}
+
 template <int NV>
 __device__ __forceinline__ void block_sum(double v[NV], double* lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;

@@ -882,11 +882,12 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
     // the correction vector (slot 5) is kept in FP32 when the others are FP16
     const int sprec = lds ? DDWC_MIXED32 : prec;
     const size_t slabS = blk_slab_bytes(sprec, n2), slabX = blk_slab_bytes(h16 ? DDWC_MIXED32 : sprec, n2);
-    double2 *bpe, *re, *xe, *to;
+    double2 *bpe, *re, *xe, *to, *th;
     CK(ws_t(C, "be_bpe", hw64, &bpe));
     CK(ws_t(C, "be_re", hw64, &re));
     CK(ws_t(C, "be_xe", hw64, &xe));
-    CK(ws_t(C, "be_to", hw64, &to));
+    CK(ws_t(C, "be_to", hw64, &to));  // A_oo^-1 b_o (prep)
+    CK(ws_t(C, "be_th", hw64, &th));  // A_oo^-1 H x_e of the last residual pass
     void* w[7];
     const char* names[7] = {"be_r", "be_rh", "be_p", "be_v", "be_t", "be_e", "be_tmp"};
     for (int k = 0; k < 7; ++k)
@@ -941,9 +942,11 @@ static int block_internal_eo(ddwc_ctx* C, Exec& ex, int colour, double mass, con
             const EoFields<float> F = eo_fields<float>(C);
             launch_blk_inner<float>(ex, g, F, A32, re, xe, w, bb, rr, mass4, tol, maxit - imax, iters, colour, nrhs);
         }
-        launch_blk_resid(ex, g, F64, A64, bpe, xe, re, to, rr, mass4, colour, nrhs);
+        launch_blk_resid(ex, g, F64, A64, bpe, xe, re, th, rr, mass4, colour, nrhs);
     }
-    launch_blk_recon(ex, g, F64, A64, b64, xe, x64, colour, nrhs);
+    // x_o = A_oo^-1 b_o + 1/2 A_oo^-1 H x_e from the prep and the last residual pass (x_e = 0 when
+    // no inner solve ran)
+    launch_blk_recon(ex, g, to, nout > 0 ? th : nullptr, xe, x64, colour, nrhs);
     HC(hipGetLastError());
     double worst = 0;
     for (size_t k = 0; k < nb; ++k)
@@ -1300,9 +1303,10 @@ static int schur_hat(ddwc_ctx* C, Exec& ex, double mass, const double2* e, doubl
     double2 *a, *w;
     CK(ws_t(C, "s_a", nw, &a));
     CK(ws_t(C, "s_w", nw, &w));
-    launch_hop<double>(ex, C->g, C->U64, e, a, nrhs, 1);
+    // (each hop output feeds only the block solves of its colour)
+    launch_hop<double>(ex, C->g, C->U64, e, a, nrhs, 1, nullptr, -1, false);
     CK(block_internal(C, ex, 1, mass, a, w, nrhs, tol, 5000, prec, bi));
-    launch_hop<double>(ex, C->g, C->U64, w, a, nrhs, 0);
+    launch_hop<double>(ex, C->g, C->U64, w, a, nrhs, 0, nullptr, -1, false);
     CK(block_internal(C, ex, 0, mass, a, w, nrhs, tol, 5000, prec, bi));
     launch_axpby(ex, C->g, 1.0, e, -1.0, w, out, nrhs, MASK_P);
     return DDWC_OK;
@@ -1372,8 +1376,9 @@ static int schur_diff_source(ddwc_ctx* C, Exec& ex, double mp, double mn, const 
     CK(ws_t(C, "e_W1", nw, &W1));
     CK(ws_t(C, "e_W12", nw, &W12));
     CK(ws_t(C, "e_A1", nw, &A1));
+    // each hop output feeds only the block solves of its colour (and the black-masked sum)
     auto hop = [&](const double2* in, double2* out, int dir) {
-        launch_hop<double>(ex, g, C->U64, in, out, nrhs, dir, rg ? &rg->Bo : nullptr, rg ? rg->colour : -1);
+        launch_hop<double>(ex, g, C->U64, in, out, nrhs, dir, rg ? &rg->Bo : nullptr, rg ? rg->colour : -1, false);
     };
     hop(E, A, 1);
     CK(block_internal(C, ex, 1, mp, A, W1, nrhs, tol, 5000, prec, bi));

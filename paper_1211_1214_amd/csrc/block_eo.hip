@@ -194,26 +194,27 @@ __global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_resid(Geom g, EoFields<d
     if (threadIdx.x == 0) rr[k.key] = red[0];
 }
 
-__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, EoFields<double> F, const double2* __restrict__ Ainv,
-                                                             const double2* __restrict__ b, const double2* __restrict__ xe,
-                                                             double2* __restrict__ x, int colour, int nrhs) {
+// x = (x_e, x_o) on the blocks of the colour with x_o = A_oo^-1 (b_o + 1/2 H^k x_e), assembled
+// from the two parts the FP64 passes already hold: to = A_oo^-1 b_o (k_blk_prep) and, when a
+// residual pass ran on the final x_e, th = A_oo^-1 H^k x_e (k_blk_resid; th null when x_e = 0).
+__global__ __launch_bounds__(BE_MAX_THREADS) void k_blk_recon(Geom g, const double2* __restrict__ to,
+                                                             const double2* __restrict__ th,
+                                                             const double2* __restrict__ xe, double2* __restrict__ x,
+                                                             int colour, int nrhs) {
     const BlkIdx k = blk_idx(g, colour, nrhs);
-    const unsigned n2 = F.n2;
+    const unsigned n2 = g.V / 2;
     const size_t of = (size_t)k.rhs * 12 * g.V, oh = (size_t)k.rhs * 12 * n2;
 #pragma unroll 1
     for (int l = threadIdx.x; l < g.hvb; l += blockDim.x) {
         const unsigned j = k.h0 + l;
-        cx<double> bo[12], w[12], e[12];
-        // x_o = A_oo^-1 (b_o + 1/2 H^k x_e)
-        load_spinor(b + of, g.V, full_index(g, j, 1), bo);
-        cx<double> acc[12];
-        hop_sum<double, HOPS_INSIDE, 2>(n2, j, xe + oh, F.U[1], F.U[0], F.nbr[1], acc, 8);
+        cx<double> w[12], e[12];
+        load_spinor(to + oh, n2, j, w);
+        if (th) {
+            cx<double> h[12];
+            load_spinor(th + oh, n2, j, h);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            acc[c] = bo[c] + 0.5 * acc[c];
-            w[c] = mk(0.0, 0.0);
+            for (int c = 0; c < 12; ++c) w[c] = w[c] + 0.5 * h[c];
         }
-        apply_diag<double>(Ainv, n2, j, 0.0, acc, w, 0.0);
         store_spinor(x + of, g.V, full_index(g, j, 1), w);
         load_spinor(xe + oh, n2, j, e);
         store_spinor(x + of, g.V, full_index(g, j, 0), e);
@@ -692,10 +693,10 @@ void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const d
     k_blk_resid<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, bpe, xe, re, to, rr, mass4, colour,
                                                                     nrhs);
 }
-void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
-                      const double2* xe, double2* x, int colour, int nrhs) {
+void launch_blk_recon(Exec& e, const Geom& g, const double2* to, const double2* th, const double2* xe, double2* x,
+                      int colour, int nrhs) {
     Timed t(e, 4, 0);  // FP64 defect-correction passes: "other"
-    k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, F, Ainv, b, xe, x, colour, nrhs);
+    k_blk_recon<<<g.NBc * nrhs, block_eo_threads(g, e.blk_threads), 0, e.stream>>>(g, to, th, xe, x, colour, nrhs);
 }
 template <class S>
 void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,

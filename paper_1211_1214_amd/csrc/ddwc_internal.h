@@ -120,12 +120,14 @@ struct Ext4 {
 };
 
 // out = hops crossing block faces into sites of colour `to_colour` (D_wb for white, D_bw for
-// black); out is zero on the other colour.  With cut, out is also zero outside the outer blocks
-// (extents *cut) of colour cut_colour: the hops of the Dirichlet operator of those blocks.
+// black); out is zero on the other colour (left untouched there with clear_other false, for
+// consumers that read only colour to_colour: the block solves of that colour).  With cut, out is
+// also zero outside the outer blocks (extents *cut) of colour cut_colour: the hops of the
+// Dirichlet operator of those blocks.
 template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
                 typename Traits<R>::word* out, int nrhs, int to_colour, const Ext4* cut = nullptr,
-                int cut_colour = -1);
+                int cut_colour = -1, bool clear_other = true);
 
 // BiCGStab vector kernels on fields of n sites, nrhs RHS, per-RHS scalars in st, storage S
 // (double, float or H16; H16 fields must be RHS-innermost).  ri selects the RHS-innermost
@@ -251,8 +253,8 @@ void launch_blk_prep(Exec& e, const Geom& g, const EoFields<double>& F, const do
                      double2* bpe, double2* re, double2* xe, double2* to, double* bb, double* rr, int colour, int nrhs);
 void launch_blk_resid(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* bpe,
                       const double2* xe, double2* re, double2* to, double* rr, double mass4, int colour, int nrhs);
-void launch_blk_recon(Exec& e, const Geom& g, const EoFields<double>& F, const double2* Ainv, const double2* b,
-                      const double2* xe, double2* x, int colour, int nrhs);
+void launch_blk_recon(Exec& e, const Geom& g, const double2* to, const double2* th, const double2* xe, double2* x,
+                      int colour, int nrhs);
 template <class S>
 void launch_blk_inner(Exec& e, const Geom& g, const EoFields<S>& F, const typename Traits<S>::kword* Ainv,
                       const double2* re, double2* xe, void* const w[7], const double* bb, const double* rr,

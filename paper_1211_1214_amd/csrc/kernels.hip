@@ -237,10 +237,11 @@ template <class R>
 __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __restrict__ U,
                                             const typename Traits<R>::word* __restrict__ in,
                                             typename Traits<R>::word* __restrict__ out, int nrhs, int to_colour,
-                                            const int* __restrict__ nbr, int ndir, Ext4 cut, int cut_colour) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+                                            const int* __restrict__ nbr, int ndir, Ext4 cut, int cut_colour, int s0,
+                                            int s1) {
+    int s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
-    if (s >= g.V) return;
+    if (s >= s1) return;
     const size_t off = (size_t)rhs * Traits<R>::NCW * g.V;
     cx<R> y[12];
     bool keep = (s / (g.V / 2)) == to_colour;
@@ -263,11 +264,14 @@ __global__ __launch_bounds__(WG) DDWC_OCC void k_hop(Geom g, const cx<R>* __rest
 
 template <class R>
 void launch_hop(Exec& e, const Geom& g, const cx<R>* U, const typename Traits<R>::word* in,
-                typename Traits<R>::word* out, int nrhs, int to_colour, const Ext4* cut, int cut_colour) {
+                typename Traits<R>::word* out, int nrhs, int to_colour, const Ext4* cut, int cut_colour,
+                bool clear_other) {
     Timed t(e, 4, 0);
     const Ext4 c = cut ? *cut : Ext4{{1, 1, 1, 1}};
-    k_hop<R><<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour, e.nbr, 8, c,
-                                                             cut ? cut_colour : -1);
+    // the sites of colour c are [c V/2, (c + 1) V/2) of the colour-major full index
+    const int s0 = clear_other ? 0 : to_colour * (g.V / 2), s1 = clear_other ? g.V : s0 + g.V / 2;
+    k_hop<R><<<dim3(tiles_of(s1 - s0), nrhs), WG, 0, e.stream>>>(g, U, in, out, nrhs, to_colour, e.nbr, 8, c,
+                                                                 cut ? cut_colour : -1, s0, s1);
 }
 
 // ------------------------------------------------------------------ BiCGStab vector kernels
@@ -833,7 +837,7 @@ void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float
                                      const Traits<R>::word*, const Traits<R>::word*, Traits<R>::word*, double*,   \
                                      int, int, double);                                                           \
     template void launch_hop<R>(Exec&, const Geom&, const cx<R>*, const Traits<R>::word*, Traits<R>::word*, int,  \
-                                int, const Ext4*, int);                                                           \
+                                int, const Ext4*, int, bool);                                                     \
     template void launch_bicg_init<R>(Exec&, unsigned, bool, const double2*, const double*, Traits<R>::word*,      \
                                       Traits<R>::word*, Traits<R>::word*, Traits<R>::word*, double*, int);        \
     template void launch_bicg_s<R>(Exec&, unsigned, bool, const BiState*, const Traits<R>::word*,                 \

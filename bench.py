@@ -210,7 +210,7 @@ def main():
     dslash_gbs = ds_b / (ds_ms * 1e-3) / 1e9 if ds_ms > 0 else None
     block = block_summary(prof["block"])
     if roofline["bound"] == "hbm":
-        roofline["traffic"] = measured_traffic(args.workload, dom)
+        roofline["traffic"] = measured_traffic(args.workload, dom, ctx.get_option(dd.binding.OPT_OP_THREADS))
         roofline["peak_measured"] = None if stream_gbs is None else round(stream_gbs, 1)
         roofline["frac_of_measured"] = None if not stream_gbs else round(roofline["achieved"] / stream_gbs, 4)
     roofline["timing"] = f"HIP events around each launch on its stream, profiled pass of {psteps} steps"
@@ -299,7 +299,8 @@ def kernel_sources_digest():
 
 
 # kernel whose counters stand for each profiler class
-CLASS_KERNEL = {"eohop": "void ddwc::k_eo_hopinv<float, true>", "block": "ddwc::k_blk_lds"}
+# kernel of a profiling class in the counter records; {nt}: the operator workgroup size in use
+CLASS_KERNEL = {"eohop": "void ddwc::k_eo_hopinv<float, true, true, {nt}>", "block": "ddwc::k_blk_lds"}
 
 
 def nested_bench(args, dd, inputs, np, torch):
@@ -539,11 +540,12 @@ def one_flavour_bench(args, dd, inputs, np, torch):
     ctx.close()
 
 
-def measured_traffic(workload, kclass):
+def measured_traffic(workload, kclass, op_threads=256):
     """HBM bytes per dispatch (FETCH_SIZE and WRITE_SIZE, calibrated) of the kernel of `kclass`,
     from profiles/traffic_<workload>.json if it was measured on the current sources, else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     name = CLASS_KERNEL.get(kclass)
+    name = name.format(nt=op_threads) if name else None
     if not name or not os.path.exists(path):
         return None
     rec = json.load(open(path))

@@ -716,8 +716,9 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     }
     // b'_e = b_e + 1/2 H_eo A_oo^-1 b_o ; x_e = 0 ; r_e = b'_e
     launch_eo_split(ex, g, b64, be, bo, nrhs);
-    launch_eo_hopinv<double>(ex, F64, 1, false, nullptr, bo, 0.0, A64, to, nrhs, DDWC_K_OTHER, 0);
-    launch_eo_diaghop<double>(ex, F64, 0, false, 0, false, be, to, 0.5, 0.0, nullptr, bpe, nullptr, nrhs, DDWC_K_OTHER, 0);
+    // t0 = A_oo^-1 b_o is kept: with the last residual's A_oo^-1 H x_e it gives x_o at the end
+    launch_eo_hopinv<double>(ex, F64, 1, false, nullptr, bo, 0.0, A64, xo, nrhs, DDWC_K_OTHER, 0);
+    launch_eo_diaghop<double>(ex, F64, 0, false, 0, false, be, xo, 0.5, 0.0, nullptr, bpe, nullptr, nrhs, DDWC_K_OTHER, 0);
     HC(hipMemsetAsync(xe, 0, sizeof(double2) * hw64, sm));
     HC(hipMemcpyAsync(re, bpe, sizeof(double2) * hw64, hipMemcpyDeviceToDevice, sm));
     launch_dots(ex, gh, re, re, part, nrhs);
@@ -810,9 +811,9 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
             if (!isfinite(rr[k])) return fail(DDWC_ENONFINITE, "non-finite residual in the global solve");
         }
     }
-    // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e), x = (x_e, x_o)
-    launch_eo_hopinv<double>(ex, F64, 1, false, xe, bo, 0.5, A64, xo, nrhs, DDWC_K_OTHER, 0);
-    launch_eo_merge(ex, g, xe, xo, x64, nrhs);
+    // x_o = A_oo^-1 (b_o + 1/2 H_oe x_e) = t0 + 1/2 (A_oo^-1 H_oe x_e), the second term from the
+    // last residual pass (x_e = 0 when no outer step ran), x = (x_e, x_o)
+    launch_eo_merge(ex, g, xe, xo, x64, nrhs, nout > 0 ? to : nullptr, 0.5);
     HC(hipGetLastError());
     double worst = 0;
     for (int k = 0; k < nrhs; ++k)

@@ -233,7 +233,8 @@ void launch_eo_setup(Exec& e, const Geom& g, const cx<double>* U64, const double
 void launch_eo_links_own(Exec& e, unsigned n2, const cx<float>* Uh32, const int* nbr_eo, cx<float>* Lown);
 void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, double2* A64, float4* A32);
 void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs);
-void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs);
+void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs,
+                     const double2* ho2 = nullptr, double w2 = 0.0);
 // y_p = Ainv (c + alpha H_{p,1-p} x); c may be null, alpha = 0 skips the hops.  ri: the fields
 // are RHS-innermost (as for the vector kernels).
 template <class S>

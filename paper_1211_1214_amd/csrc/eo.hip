@@ -82,9 +82,10 @@ void launch_eo_inverse(Exec& e, unsigned V2, const double2* Kp, double mass4, do
     k_eo_inverse<<<(V2 + 127) / 128, 128, 0, e.stream>>>(V2, Kp, mass4, A64, A32);
 }
 
-// full FP64 field <-> (even, odd) FP64 half fields
+// full FP64 field <-> (even, odd) FP64 half fields; merging, the odd part is ho + w2 ho2 when
+// ho2 is given
 __global__ void k_eo_split(Geom g, const double2* __restrict__ full, double2* __restrict__ he, double2* __restrict__ ho,
-                           int merge) {
+                           int merge, const double2* __restrict__ ho2, double w2) {
     const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     if (s >= (unsigned)g.V) return;
@@ -92,21 +93,30 @@ __global__ void k_eo_split(Geom g, const double2* __restrict__ full, double2* __
     int p;
     const unsigned i = half_index(g, s, p);
     double2* h = p ? ho : he;
+    const bool add = merge && p && ho2;
     for (int c = 0; c < 12; ++c) {
-        if (merge)
-            ((double2*)full)[((size_t)rhs * 12 + c) * V + s] = h[((size_t)rhs * 12 + c) * V2 + i];
-        else
-            h[((size_t)rhs * 12 + c) * V2 + i] = full[((size_t)rhs * 12 + c) * V + s];
+        const size_t hi = ((size_t)rhs * 12 + c) * V2 + i;
+        if (merge) {
+            double2 v = h[hi];
+            if (add) {
+                const double2 a = ho2[hi];
+                v = make_double2(v.x + w2 * a.x, v.y + w2 * a.y);
+            }
+            ((double2*)full)[((size_t)rhs * 12 + c) * V + s] = v;
+        } else {
+            h[hi] = full[((size_t)rhs * 12 + c) * V + s];
+        }
     }
 }
 
 void launch_eo_split(Exec& e, const Geom& g, const double2* full, double2* he, double2* ho, int nrhs) {
     Timed t(e, 4, 0);
-    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, he, ho, 0);
+    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, he, ho, 0, nullptr, 0.0);
 }
-void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs) {
+void launch_eo_merge(Exec& e, const Geom& g, const double2* he, const double2* ho, double2* full, int nrhs,
+                     const double2* ho2, double w2) {
     Timed t(e, 4, 0);
-    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, (double2*)he, (double2*)ho, 1);
+    k_eo_split<<<dim3(tiles_of(g.V), nrhs), WG, 0, e.stream>>>(g, full, (double2*)he, (double2*)ho, 1, ho2, w2);
 }
 
 // ------------------------------------------------------------------ operator kernels

@@ -283,6 +283,9 @@ int ddwc_log_w_nested_total(ddwc_ctx *outer, ddwc_ctx *inner, double kappa1, dou
  *   DDWC_OPT_OP_THREADS    workgroup size of the even-odd global solver's RHS-innermost operator
  *                          kernels (more than one RHS): 128, 256 (default) or 512; a value below
  *                          the RHS count runs 256.
+ *   DDWC_OPT_TILE_ORDER    dispatch order of those kernels' workgroups: 0 half-site index order;
+ *                          1 (default) interleaved by Schwarz-block rank, so that face-adjacent blocks
+ *                          of the two colours run on the same XCD at about the same time.
  * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */
@@ -294,7 +297,8 @@ typedef enum {
     DDWC_OPT_BLOCK_LDS = 4,
     DDWC_OPT_BLOCK_KERNEL = 5,
     DDWC_OPT_INNER_FLOOR = 6,
-    DDWC_OPT_OP_THREADS = 7
+    DDWC_OPT_OP_THREADS = 7,
+    DDWC_OPT_TILE_ORDER = 8
 } ddwc_option;
 int ddwc_set_option(ddwc_ctx *ctx, int option, int value);
 int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
@@ -305,8 +309,9 @@ int ddwc_get_option(ddwc_ctx *ctx, int option, int *value);
  * turn: the block inner solver on a block sweep of one colour (DDWC_OPT_BLOCK_KERNEL 0 where it
  * applies; kernel 1 at each DDWC_OPT_BLOCK_THREADS in {0, 128, 256, 512} without and with the
  * LDS reservations that leave room for 2 or 4 block-solver workgroups per CU); then, on a global
- * solve, DDWC_OPT_OP_THREADS in {128, 256, 512}; then each poll interval in {2, 4, 8} with and
- * without graphs.  *seconds_host (may be null) receives the tuning time.  Synchronises.
+ * solve, DDWC_OPT_OP_THREADS in {128, 256, 512} with each DDWC_OPT_TILE_ORDER; then each poll
+ * interval in {2, 4, 8} with and without graphs.  *seconds_host (may be null) receives the
+ * tuning time.  Synchronises.
  */
 int ddwc_autotune(ddwc_ctx *ctx, double kappa, int nrhs, int prec, double *seconds_host, void *stream);
 

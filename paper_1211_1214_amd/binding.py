@@ -20,7 +20,7 @@ BLACK, WHITE = 0, 1
 OP_FULL, OP_SCHUR = 0, 1
 K_DSLASH64, K_DSLASH32, K_BLOCK, K_BLAS, K_OTHER, K_EOHOP = range(6)
 (OPT_GRAPHS, OPT_POLL, OPT_BLOCK_THREADS, OPT_SOLVER, OPT_BLOCK_LDS, OPT_BLOCK_KERNEL, OPT_INNER_FLOOR,
- OPT_OP_THREADS) = range(8)
+ OPT_OP_THREADS, OPT_TILE_ORDER) = range(9)
 _STATUS = {EINVAL: "EINVAL", ENOCONV: "ENOCONV", EHIP: "EHIP", ENONFINITE: "ENONFINITE", EUNDEF: "EUNDEF"}
 
 # Every function the header declares, with its ctypes signature.
@@ -342,7 +342,7 @@ class Context:
         return {"graphs": self.get_option(OPT_GRAPHS), "poll": self.get_option(OPT_POLL),
                 "block_threads": self.get_option(OPT_BLOCK_THREADS), "block_lds": self.get_option(OPT_BLOCK_LDS),
                 "block_kernel": self.get_option(OPT_BLOCK_KERNEL), "op_threads": self.get_option(OPT_OP_THREADS),
-                "seconds": t.value}
+                "tile_order": self.get_option(OPT_TILE_ORDER), "seconds": t.value}
 
     def profile_enable(self, on=True):
         _check(lib().ddwc_profile_enable(self._h, int(bool(on))), "ddwc_profile_enable")

@@ -165,6 +165,8 @@ struct ddwc_ctx {
     int opt_blk_lds = 0;      // KiB of LDS reserved per persistent block-solver workgroup
     int opt_blk_kernel = 0;   // block inner solver: 0 LDS-resident where it fits (FP32/FP16), 1 global-memory
     int opt_op_threads = WG;  // workgroup size of the global solver's RHS-innermost operator kernels
+    int opt_tile_order = 1;   // their dispatch order: 0 half-site index order, 1 interleaved by block rank
+    std::map<std::string, std::pair<int*, std::vector<int>>> orders;  // cached tile orders (device, host)
     int lds_max = 0;          // LDS bytes per workgroup of the device
     void* scratch = nullptr;  // this device's copy of the static scratch (ddwc_dslash_apply_noalloc)
     hipStream_t cap = nullptr;  // private stream the graphs are captured on
@@ -369,6 +371,7 @@ extern "C" int ddwc_destroy(ddwc_ctx* C) {
     }
     for (auto& kv : C->ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto& kv : C->orders) (void)hipFree(kv.second.first);
     if (C->host) (void)hipHostFree(C->host);
     delete C;
     return DDWC_OK;
@@ -547,6 +550,37 @@ EoFields<H16> eo_fields<H16>(const ddwc_ctx* C, bool site_major) {
     return F;
 }
 
+// Dispatch order of the tiles of the RHS-innermost operator kernels on half fields of n2 sites
+// (nrhs RHS, nt pairs per tile): sorted by the block rank of their first site, then by colour.
+// Blocks of the two colours with the same rank are neighbours along x3 (block_base), and after
+// the XCD remap each XCD takes a contiguous run of ranks (a time layer at 48x24^3), so a block's
+// face neighbours of the other colour are processed on the same XCD at nearly the same time,
+// while in index order they are on another XCD.
+static int tile_order(ddwc_ctx* C, unsigned n2, int nrhs, int nt, const int** out) {
+    const Geom& g = C->g;
+    const std::string key = std::to_string(n2) + "/" + std::to_string(nrhs) + "/" + std::to_string(nt);
+    auto it = C->orders.find(key);
+    if (it == C->orders.end()) {
+        const long long pairs = (long long)n2 * nrhs;
+        const int ntiles = (int)((pairs + nt - 1) / nt);
+        std::vector<std::pair<long long, int>> keys(ntiles);
+        for (int t = 0; t < ntiles; ++t) {
+            const long long b = ((long long)t * nt / nrhs) / g.hvb;  // colour-major block of the first pair
+            const long long c = b / g.NBc, rank = b % g.NBc;
+            keys[t] = {(rank * 2 + c) * (long long)ntiles + t, t};
+        }
+        std::sort(keys.begin(), keys.end());
+        std::vector<int> ord(ntiles);
+        for (int t = 0; t < ntiles; ++t) ord[t] = keys[t].second;
+        int* d = nullptr;
+        HC(hipMalloc(&d, sizeof(int) * ntiles));
+        HC(hipMemcpy(d, ord.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice));
+        it = C->orders.emplace(key, std::make_pair(d, std::move(ord))).first;
+    }
+    *out = it->second.first;
+    return DDWC_OK;
+}
+
 // Odd-site inverses of 4 + m + C for mass4 = 4 + m (kept for the last few masses).
 static int get_ainv(ddwc_ctx* C, Exec& ex, double mass4, const double2** a64, const float4** a32) {
     const size_t n2 = C->g.V / 2;
@@ -648,7 +682,8 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
     // (FP16 fields, whose scale plane follows the word planes, always are)
     CK(check_h16_global(C, nrhs, h16 ? DDWC_MIXED16 : DDWC_MIXED32));
     const bool ri = h16 || (nrhs > 1 && nrhs <= WG && ri_fits(n2, nrhs));
-    const EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read own-site link records
+    EoFields<S> FR = eo_fields<S>(C, ri && !fp64);  // RI kernels read own-site link records
+    if (ri && g.eo && C->opt_tile_order == 1) CK(tile_order(C, n2, nrhs, eo_op_threads(FR, nrhs, ri), &FR.order));
     const int ntR = vector_tiles(n2, nrhs, ri);
     const int ntM = eo_op_tiles(FR, nrhs, ri);  // tiles of the operator kernels' partial sums
     const double mass4 = 4.0 + mass;
@@ -761,7 +796,8 @@ static int eo_solve(ddwc_ctx* C, Exec& ex, double mass, const double2* b64, doub
                                       (uintptr_t)n2, (uintptr_t)poll, (uintptr_t)mb, (uintptr_t)r, (uintptr_t)rh,
                                       (uintptr_t)p, (uintptr_t)v, (uintptr_t)s, (uintptr_t)t, (uintptr_t)tmp,
                                       (uintptr_t)xR, (uintptr_t)part, (uintptr_t)st, (uintptr_t)AR,
-                                      (uintptr_t)FR.U[0], (uintptr_t)FR.K[0], (uintptr_t)FR.op_threads};
+                                      (uintptr_t)FR.U[0], (uintptr_t)FR.K[0], (uintptr_t)FR.op_threads,
+                                      (uintptr_t)FR.order};
         gx = graph_for(C, key, [&](Exec& ee) { chunk(ee, poll); });
     }
     while (true) {
@@ -1937,6 +1973,10 @@ extern "C" int ddwc_set_option(ddwc_ctx* C, int option, int value) {
                 return fail(DDWC_EINVAL, "operator threads must be 128, 256 or 512");
             C->opt_op_threads = value;
             break;
+        case DDWC_OPT_TILE_ORDER:
+            if (value != 0 && value != 1) return fail(DDWC_EINVAL, "tile order must be 0 or 1");
+            C->opt_tile_order = value;
+            break;
         default:
             return fail(DDWC_EINVAL, "unknown option");
     }
@@ -1955,6 +1995,7 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
         case DDWC_OPT_BLOCK_KERNEL: *value = C->opt_blk_kernel; break;
         case DDWC_OPT_INNER_FLOOR: *value = C->opt_inner_floor; break;
         case DDWC_OPT_OP_THREADS: *value = C->opt_op_threads; break;
+        case DDWC_OPT_TILE_ORDER: *value = C->opt_tile_order; break;
         default: return fail(DDWC_EINVAL, "unknown option");
     }
     return DDWC_OK;
@@ -1963,8 +2004,8 @@ extern "C" int ddwc_get_option(ddwc_ctx* C, int option, int* value) {
 // Times the schedule choices on this context's lattice with nrhs reproducible right-hand
 // sides and keeps the fastest, one group after the other: the block inner solver (the
 // LDS-resident kernel where it applies; the global-memory kernel at each workgroup size and
-// residency) on one colour's block sweep, then the operator workgroup size of the global solve,
-// then its poll interval and graph replay.  Each candidate runs once to warm up and once timed.
+// residency) on one colour's block sweep, then the operator workgroup size and dispatch order of
+// the global solve, then its poll interval and graph replay.  Each candidate runs once to warm up and once timed.
 extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, double* seconds_host, void* stream) {
     CK(check_common(C, kappa, nrhs, prec));
     auto t0 = std::chrono::steady_clock::now();
@@ -2032,19 +2073,24 @@ extern "C" int ddwc_autotune(ddwc_ctx* C, double kappa, int nrhs, int prec, doub
             return solve_internal(C, ex, mass, b, x, nrhs, 1e-8, 5000, prec, &si);
         });
     };
-    const int saved_op = C->opt_op_threads, saved_poll = C->opt_poll, saved_graphs = C->opt_graphs;
+    const int saved_op = C->opt_op_threads, saved_order = C->opt_tile_order, saved_poll = C->opt_poll,
+              saved_graphs = C->opt_graphs;
     best = 1e300;
-    int po = saved_op;
-    for (int nt : {128, 256, 512}) {
-        C->opt_op_threads = nt;
-        const double t = solve_time();
-        if (t < 0) {
-            C->opt_op_threads = saved_op;
-            return fail(DDWC_ENOCONV, "autotune: global solve failed");
+    int po = saved_op, pr = saved_order;
+    for (int nt : {128, 256, 512})
+        for (int order : {0, 1}) {
+            C->opt_op_threads = nt;
+            C->opt_tile_order = order;
+            const double t = solve_time();
+            if (t < 0) {
+                C->opt_op_threads = saved_op;
+                C->opt_tile_order = saved_order;
+                return fail(DDWC_ENOCONV, "autotune: global solve failed");
+            }
+            if (t < best) best = t, po = nt, pr = order;
         }
-        if (t < best) best = t, po = nt;
-    }
     C->opt_op_threads = po;
+    C->opt_tile_order = pr;
     best = 1e300;
     int pp = saved_poll, pg = saved_graphs;
     for (int poll : {2, 4, 8})

@@ -207,6 +207,7 @@ struct EoFields {
     const typename Traits<R>::kword* K[2];              // clover of the sites of parity p
     const int* nbr[2];                                  // [8][n2] neighbour half indices (other parity)
     int op_threads = WG;                                // workgroup size of the RHS-innermost operator kernels
+    const int* order = nullptr;                         // their tile dispatch order (null: index order)
 };
 
 // Workgroup size and tile count of the operator kernels (launch_eo_hopinv / launch_eo_diaghop) on

@@ -151,9 +151,10 @@ __global__ __launch_bounds__(NT) void k_eo_hopinv(unsigned n2, const typename Tr
                                                   const cx<typename Traits<S>::link>* __restrict__ Uq,
                                                   const int* __restrict__ nbrp,
                                                   const typename Traits<S>::kword* __restrict__ Ainv,
-                                                  typename Traits<S>::word* __restrict__ y, int nrhs, int ntiles) {
+                                                  typename Traits<S>::word* __restrict__ y, int nrhs, int ntiles,
+                                                  const int* __restrict__ order) {
     typedef typename Traits<S>::real R;
-    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles);
+    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles, order);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Ak = Ainv;
     const int* nb = nbrp;
@@ -206,9 +207,9 @@ __global__ __launch_bounds__(NT) void k_eo_diaghop(unsigned n2, const typename T
                                                    typename Traits<S>::real mass4,
                                                    const typename Traits<S>::word* __restrict__ aux,
                                                    typename Traits<S>::word* __restrict__ y, double* part, int nrhs,
-                                                   int ntiles) {
+                                                   int ntiles, const int* __restrict__ order) {
     typedef typename Traits<S>::real R;
-    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles);
+    const VItem it = vitem<RI, NT>(n2, nrhs, ntiles, order);
     const cx<typename Traits<S>::link>* Uf = Up;
     const typename Traits<S>::kword* Kk = Kp;
     const int* nb = nbrp;
@@ -283,7 +284,7 @@ void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typen
     const int nt = eo_op_tiles(F, nrhs, ri);
     if (!ri) {
         k_eo_hopinv<S, false, false, WG><<<nt * nrhs, WG, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
-                                                                         F.nbr[p], Ainv, y, nrhs, nt);
+                                                                         F.nbr[p], Ainv, y, nrhs, nt, nullptr);
         return;
     }
     const bool stg = stage_ok<S>(nrhs);
@@ -291,10 +292,10 @@ void launch_eo_hopinv(Exec& e, const EoFields<S>& F, int p, bool ri, const typen
         constexpr int NT = decltype(ntc)::value;
         if (stg)
             k_eo_hopinv<S, true, true, NT><<<nt, NT, stage_bytes<S, NT>(), e.stream>>>(
-                F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y, nrhs, nt);
+                F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p], F.nbr[p], Ainv, y, nrhs, nt, F.order);
         else
             k_eo_hopinv<S, true, false, NT><<<nt, NT, 0, e.stream>>>(F.n2, x, c, (R)alpha, F.U[p], F.U[1 - p],
-                                                                     F.nbr[p], Ainv, y, nrhs, nt);
+                                                                     F.nbr[p], Ainv, y, nrhs, nt, F.order);
     });
 }
 
@@ -313,10 +314,12 @@ void launch_eo_diaghop(Exec& e, const EoFields<S>& F, int p, bool ri, int epi, b
         const int ng = RIV ? nt : nt * nrhs;
         if (RIV && stg)
             k_eo_diaghop<S, EP, UA, RIV, RIV, NT><<<ng, NT, stage_bytes<S, NT>(), e.stream>>>(
-                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);
+                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt,
+                RIV ? F.order : nullptr);
         else
             k_eo_diaghop<S, EP, UA, RIV, false, NT><<<ng, NT, 0, e.stream>>>(
-                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt);
+                F.n2, c, tv, (R)beta, F.U[p], F.U[1 - p], F.nbr[p], F.K[p], (R)mass4, aux, y, part, nrhs, nt,
+                RIV ? F.order : nullptr);
     };
     typedef std::integral_constant<bool, true> T_;
     typedef std::integral_constant<bool, false> F_;

@@ -53,8 +53,9 @@ struct VItem {
 };
 
 // NT: threads per workgroup of an RHS-innermost kernel (the RHS-major path always uses WG).
+// order (RI, may be null): the tile each dispatch slot processes, after the XCD remap.
 template <bool RI, int NT = WG>
-__device__ __forceinline__ VItem vitem(unsigned n, int nrhs, int ntiles) {
+__device__ __forceinline__ VItem vitem(unsigned n, int nrhs, int ntiles, const int* __restrict__ order = nullptr) {
     VItem it;
     if (!RI) {
         const TileRhs tr = tile_rhs(ntiles, nrhs);
@@ -65,6 +66,7 @@ __device__ __forceinline__ VItem vitem(unsigned n, int nrhs, int ntiles) {
         it.g0 = 0;
     } else {
         it.tile = xcd_remap(blockIdx.x, ntiles);
+        if (order) it.tile = order[it.tile];
         it.g0 = (unsigned)it.tile * NT;
         const unsigned gi = it.g0 + threadIdx.x;
         it.ok = gi < n * (unsigned)nrhs;

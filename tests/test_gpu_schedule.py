@@ -110,7 +110,8 @@ def test_option_validation(env):
     for opt, bad in ((binding.OPT_GRAPHS, 2), (binding.OPT_POLL, 0), (binding.OPT_POLL, 65),
                      (binding.OPT_BLOCK_THREADS, 96), (binding.OPT_BLOCK_THREADS, 832), (binding.OPT_SOLVER, 2),
                      (binding.OPT_BLOCK_LDS, -1), (binding.OPT_BLOCK_LDS, 4096),
-                     (binding.OPT_OP_THREADS, 64), (binding.OPT_OP_THREADS, 384), (8, 1)):
+                     (binding.OPT_OP_THREADS, 64), (binding.OPT_OP_THREADS, 384), (binding.OPT_TILE_ORDER, 2),
+                     (9, 1)):
         with pytest.raises(dd.DDWCError) as e:
             ctx.set_option(opt, bad)
         assert e.value.code == -1
@@ -122,11 +123,12 @@ def test_option_validation(env):
 OPT_LAT = (4, 4, 4, 12)  # 384 even sites: 9 RHS leave a ragged last tile at 256 and 512 threads
 
 
-@pytest.mark.parametrize("threads", [128, 512])
+@pytest.mark.parametrize("threads,order", [(128, 0), (512, 0), (256, 1), (512, 1)])
 @pytest.mark.parametrize("prec", [dd.MIXED32, dd.MIXED16])
-def test_op_threads_option(threads, prec):
-    """Global solves with the RHS-innermost operator kernels at another workgroup size, with
-    (9 RHS) and without (3 RHS) the per-site staging, against the oracle."""
+def test_op_threads_option(threads, order, prec):
+    """Global solves with the RHS-innermost operator kernels at another workgroup size or in the
+    block-interleaved dispatch order, with (9 RHS) and without (3 RHS) the per-site staging,
+    against the oracle."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     dev = torch.device("cuda:0")
@@ -135,11 +137,13 @@ def test_op_threads_option(threads, prec):
     ctx = dd.Context(torch.from_numpy(U).to(dev), OPT_LAT, BLK, -1, 1.0)
     try:
         ctx.set_option(binding.OPT_OP_THREADS, threads)
+        ctx.set_option(binding.OPT_TILE_ORDER, order)
         assert ctx.get_option(binding.OPT_OP_THREADS) == threads
+        assert ctx.get_option(binding.OPT_TILE_ORDER) == order
         m = dirac.mass(0.121)
         inv = S.inv_full(m)
         for nrhs in (3, 9):
-            say("op threads", threads, "prec", prec, "nrhs", nrhs)
+            say("op threads", threads, "order", order, "prec", prec, "nrhs", nrhs)
             b = inputs.make_spinor(OPT_LAT, 90 + nrhs, nrhs=nrhs)
             x, st = ctx.solve(0.121, T(b, dev), tol=1e-12, prec=prec)
             want = np.stack([inv(bb.reshape(-1)).reshape(bb.shape) for bb in b])
@@ -153,7 +157,7 @@ def test_autotune(env):
     say("autotune")
     r = ctx.autotune(0.121, 4, dd.MIXED32)
     assert r["graphs"] in (0, 1) and r["poll"] in (2, 4, 8) and r["block_threads"] in (0, 128, 256, 512)
-    assert r["block_kernel"] in (0, 1) and r["op_threads"] in (128, 256, 512)
+    assert r["block_kernel"] in (0, 1) and r["op_threads"] in (128, 256, 512) and r["tile_order"] in (0, 1)
     assert 0 <= r["block_lds"] < 160
     assert r["seconds"] > 0
     b = inputs.make_spinor(LAT, 85, nrhs=4)

@@ -280,12 +280,14 @@ int ddwc_log_w_nested_total(ddwc_ctx *outer, ddwc_ctx *inner, double kappa1, dou
  *   DDWC_OPT_INNER_FLOOR   the FP32 inner BiCGStab of the even-odd global solver (DDWC_MIXED32) stops
  *                          at a relative residual of at least value x 1e-8 before the FP64 defect
  *                          correction restarts it, in [1, 100000]; default 200 (2e-6).
- *   DDWC_OPT_OP_THREADS    workgroup size of the even-odd global solver's RHS-innermost operator
- *                          kernels (more than one RHS): 128, 256 (default) or 512; a value below
- *                          the RHS count runs 256.
- *   DDWC_OPT_TILE_ORDER    dispatch order of those kernels' workgroups: 0 half-site index order;
+ *   DDWC_OPT_OP_THREADS    workgroup size of the RHS-innermost operator kernels (the even-odd
+ *                          global solver's, and ddwc_dslash_apply's with several FP32 RHS): 128,
+ *                          256 (default) or 512; a value below the RHS count runs 256.
+ *   DDWC_OPT_TILE_ORDER    dispatch order of those kernels' workgroups: 0 site index order;
  *                          1 (default) interleaved by Schwarz-block rank, so that face-adjacent blocks
- *                          of the two colours run on the same XCD at about the same time.
+ *                          of the two colours run on the same XCD at about the same time (not in
+ *                          ddwc_dslash_apply_noalloc, which builds no order table).  Neither option
+ *                          changes a result of ddwc_dslash_apply.
  * Results do not depend on the graph and LDS options; the others can change iteration counts and
  * rounding, never the tolerance reached.  EINVAL for unknown options or values.
  */

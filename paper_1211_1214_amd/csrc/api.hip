@@ -550,22 +550,25 @@ EoFields<H16> eo_fields<H16>(const ddwc_ctx* C, bool site_major) {
     return F;
 }
 
-// Dispatch order of the tiles of the RHS-innermost operator kernels on half fields of n2 sites
-// (nrhs RHS, nt pairs per tile): sorted by the block rank of their first site, then by colour.
+// Dispatch order of the tiles of the RHS-innermost operator kernels on fields of n2 sites with
+// per_block sites per block (half or full fields; nrhs RHS, nt pairs per tile): sorted by the
+// block rank of their first site, then by colour.
 // Blocks of the two colours with the same rank are neighbours along x3 (block_base), and after
 // the XCD remap each XCD takes a contiguous run of ranks (a time layer at 48x24^3), so a block's
 // face neighbours of the other colour are processed on the same XCD at nearly the same time,
 // while in index order they are on another XCD.
-static int tile_order(ddwc_ctx* C, unsigned n2, int nrhs, int nt, const int** out) {
+static int tile_order(ddwc_ctx* C, unsigned n2, int nrhs, int nt, const int** out, int per_block = 0) {
     const Geom& g = C->g;
-    const std::string key = std::to_string(n2) + "/" + std::to_string(nrhs) + "/" + std::to_string(nt);
+    if (per_block == 0) per_block = g.hvb;  // half fields; full fields pass Vb
+    const std::string key = std::to_string(n2) + "/" + std::to_string(nrhs) + "/" + std::to_string(nt) + "/" +
+                            std::to_string(per_block);
     auto it = C->orders.find(key);
     if (it == C->orders.end()) {
         const long long pairs = (long long)n2 * nrhs;
         const int ntiles = (int)((pairs + nt - 1) / nt);
         std::vector<std::pair<long long, int>> keys(ntiles);
         for (int t = 0; t < ntiles; ++t) {
-            const long long b = ((long long)t * nt / nrhs) / g.hvb;  // colour-major block of the first pair
+            const long long b = ((long long)t * nt / nrhs) / per_block;  // colour-major block of the first pair
             const long long c = b / g.NBc, rank = b % g.NBc;
             keys[t] = {(rank * 2 + c) * (long long)ntiles + t, t};
         }
@@ -1077,7 +1080,7 @@ static size_t dslash_field_bytes(const ddwc_ctx* C, int nrhs, int prec) {
     return vec_words(C, nrhs, prec == DDWC_FP64) * 16;
 }
 static int dslash_apply_with(ddwc_ctx* C, Exec& ex, double kappa, const void* in, void* out, int nrhs, int prec,
-                             void* a, void* b) {
+                             void* a, void* b, bool may_allocate) {
     const Geom& g = C->g;
     const double mass4 = 4.0 + mass_of(kappa);
     if (prec == DDWC_FP64) {
@@ -1087,9 +1090,15 @@ static int dslash_apply_with(ddwc_ctx* C, Exec& ex, double kappa, const void* in
         launch_export<double>(ex, g, (const double2*)b, out, nrhs, MASK_ALL);
     } else if (nrhs > 1 && nrhs <= WG && ri_fits((unsigned)g.V, nrhs)) {
         // several RHS: RHS-innermost fields, the RHS of a site share its links and clover
+        // (the schedule's operator workgroup size; its dispatch order only where the order table
+        // may be built: the per-site arithmetic, and so the result, is the same in any order)
+        const int* order = nullptr;
+        const int nt = C->opt_op_threads;
+        if (may_allocate && g.eo && C->opt_tile_order == 1)
+            CK(tile_order(C, (unsigned)g.V, nrhs, nrhs <= nt ? nt : WG, &order, g.Vb));
         launch_import_ri32(ex, g, in, (float4*)a, nrhs);
         launch_dslash_ri32(ex, g, C->U32s, C->K32, mass4, (const float4*)a, (float4*)b, nrhs, DDWC_K_DSLASH32,
-                           ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32));
+                           ddwc_dslash_bytes(C, nrhs, DDWC_MIXED32), nt, order);
         launch_export_ri32(ex, g, (const float4*)b, out, nrhs);
     } else {
         launch_import<float>(ex, g, in, (float4*)a, nrhs, MASK_ALL);
@@ -1110,7 +1119,7 @@ extern "C" int ddwc_dslash_apply(ddwc_ctx* C, double kappa, const void* in, void
     void *a, *b;
     CK(ws_get(C, fp64 ? "d_in64" : "d_in32", dslash_field_bytes(C, nrhs, prec), &a));
     CK(ws_get(C, fp64 ? "d_out64" : "d_out32", dslash_field_bytes(C, nrhs, prec), &b));
-    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, a, b);
+    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, a, b, true);
 }
 
 extern "C" int ddwc_dslash_apply_noalloc(ddwc_ctx* C, double kappa, const void* in, void* out, int nrhs, int prec,
@@ -1126,7 +1135,7 @@ extern "C" int ddwc_dslash_apply_noalloc(ddwc_ctx* C, double kappa, const void* 
     Exec ex = make_exec(C, stream);
     ex.prof = nullptr;  // no event pairs: nothing is created during the call
     char* base = (char*)C->scratch;
-    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, base, base + fb);
+    return dslash_apply_with(C, ex, kappa, in, out, nrhs, prec, base, base + fb, false);
 }
 
 extern "C" int ddwc_block_solve(ddwc_ctx* C, int colour, double kappa, const void* rhs, void* sol, int nrhs,

@@ -81,11 +81,14 @@ void launch_links_import(Exec& e, const Geom& g, const void* canon, cx<double>* 
 void launch_links_own(Exec& e, unsigned n, const cx<float>* Uf, const cx<float>* Ub, const int* nbr,
                       cx<float>* Lown);
 // Full-lattice FP32 Dslash on RHS-innermost fields [6][V][nrhs] (canonical FP64 in and out), with
-// the own-site link records Us [V][8][9].
+// the own-site link records Us [V][8][9]; op_threads (128, 256 or 512; 256 below nrhs) threads per
+// workgroup, tiles dispatched in `order` (null: index order; dslash_ri32_tiles() entries).
 void launch_import_ri32(Exec& e, const Geom& g, const void* canon, float4* out, int nrhs);
 void launch_export_ri32(Exec& e, const Geom& g, const float4* in, void* canon, int nrhs);
 void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float4* K, double mass4, const float4* in,
-                        float4* out, int nrhs, int kclass, double bytes);
+                        float4* out, int nrhs, int kclass, double bytes, int op_threads = WG,
+                        const int* order = nullptr);
+int dslash_ri32_tiles(const Geom& g, int nrhs, int op_threads);
 void launch_nbr_build(Exec& e, const Geom& g, int* nbr);
 void launch_clover_build(Exec& e, const Geom& g, const cx<double>* U64, double csw, double2* K64, float4* K32);
 

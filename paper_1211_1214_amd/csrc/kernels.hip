@@ -772,22 +772,24 @@ __global__ __launch_bounds__(WG) void k_export_ri32(Geom g, const float4* __rest
     for (int c = 0; c < 12; ++c) dst[c] = make_double2((double)q[c].re, (double)q[c].im);
 }
 
-template <bool STG>
-__global__ __launch_bounds__(WG) void k_dslash_ri32(Geom g, const cx<float>* __restrict__ Lown,
+// NT threads per workgroup; order (may be null): the tile of each dispatch slot.
+template <bool STG, int NT>
+__global__ __launch_bounds__(NT) void k_dslash_ri32(Geom g, const cx<float>* __restrict__ Lown,
                                                     const float4* __restrict__ K, float mass4,
                                                     const float4* __restrict__ in, float4* __restrict__ out,
-                                                    const int* __restrict__ nbr, int nrhs, int ntiles) {
-    const VItem it = vitem<true>((unsigned)g.V, nrhs, ntiles);
+                                                    const int* __restrict__ nbr, int nrhs, int ntiles,
+                                                    const int* __restrict__ order) {
+    const VItem it = vitem<true, NT>((unsigned)g.V, nrhs, ntiles, order);
     const cx<float>* Uf = Lown;
     const float4* Kk = K;
     const int* nb = nbr;
     unsigned kst = (unsigned)g.V, l0 = 0, nstr = 0;
     if (STG) {
-        const Staged<float> sd = stage_site_data<float>(it, (unsigned)g.V, nrhs, Lown, K, nbr);
+        const Staged<float> sd = stage_site_data<float, NT>(it, (unsigned)g.V, nrhs, Lown, K, nbr);
         Uf = sd.U;
         Kk = sd.K;
         nb = sd.nbr;
-        kst = nstr = stg_sites<WG>();
+        kst = nstr = stg_sites<NT>();
         l0 = sd.l0;
     }
     if (!it.ok) return;
@@ -811,14 +813,27 @@ void launch_export_ri32(Exec& e, const Geom& g, const float4* in, void* canon, i
     k_export_ri32<<<nt, WG, 0, e.stream>>>(g, in, (double2*)canon, nrhs, nt);
 }
 void launch_dslash_ri32(Exec& e, const Geom& g, const cx<float>* Us, const float4* K, double mass4, const float4* in,
-                        float4* out, int nrhs, int kclass, double bytes) {
+                        float4* out, int nrhs, int kclass, double bytes, int op_threads, const int* order) {
     Timed t(e, kclass, bytes);
-    const int nt = tiles_of(g.V * nrhs);
-    if (stage_ok<float>(nrhs))
-        k_dslash_ri32<true><<<nt, WG, stage_bytes<float>(), e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs,
-                                                                        nt);
-    else
-        k_dslash_ri32<false><<<nt, WG, 0, e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs, nt);
+    const int NTr = nrhs <= op_threads ? op_threads : WG;
+    const int nt = (int)(((long long)g.V * nrhs + NTr - 1) / NTr);
+    auto launch = [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        if (stage_ok<float>(nrhs))
+            k_dslash_ri32<true, NT><<<nt, NT, stage_bytes<float, NT>(), e.stream>>>(g, Us, K, (float)mass4, in, out,
+                                                                                  e.nbr, nrhs, nt, order);
+        else
+            k_dslash_ri32<false, NT><<<nt, NT, 0, e.stream>>>(g, Us, K, (float)mass4, in, out, e.nbr, nrhs, nt, order);
+    };
+    switch (NTr) {
+        case 128: launch(std::integral_constant<int, 128>()); break;
+        case 512: launch(std::integral_constant<int, 512>()); break;
+        default: launch(std::integral_constant<int, WG>()); break;
+    }
+}
+int dslash_ri32_tiles(const Geom& g, int nrhs, int op_threads) {
+    const int NTr = nrhs <= op_threads ? op_threads : WG;
+    return (int)(((long long)g.V * nrhs + NTr - 1) / NTr);
 }
 
 // ------------------------------------------------------------------ instantiations
